@@ -1,0 +1,151 @@
+/*
+ * sfft.h -- C ABI of the split-FFT multilevel block-Toeplitz matrix-vector
+ * product for AMD Instinct MI355X (gfx950).
+ *
+ * The operation (Siron & Molesky, "A Split Fast Fourier Transform Algorithm
+ * for Block Toeplitz Matrix-Vector Multiplication", Algorithm 1 and its
+ * statement y = T v): for a d-level block-Toeplitz matrix with b x b blocks on
+ * the grid n_1 x ... x n_d,
+ *
+ *     y[a, i] = sum_{j in grid} sum_{c < b} t(i - j)[a, c] * x[c, j].
+ *
+ * SFFT_SPLIT evaluates it with the lazy-embedding / eager-projection split of
+ * Section II (per level an even branch and a phase-shifted odd branch of the
+ * unpadded vector, 2^d branch products with the parity parts T[bId] of the
+ * embedded symbol, inverse transforms merged back level by level). SFFT_EMBED
+ * evaluates the same product with the standard circulant embedding of every
+ * level (vectors padded to 2n per level), the baseline the paper compares to.
+ *
+ * Layouts (C order, interleaved complex: re, im):
+ *   coefficients  (b, b, 2n_1-1, ..., 2n_d-1) complex128; offset r_l is at
+ *                 index r_l + n_l - 1 along level l (level 1 outermost).
+ *   x, y          (nrhs, b, n_1, ..., n_d) of the plan's dtype.
+ * All pointers passed to sfft_plan_create / sfft_apply / sfft_apply_multi are
+ * DEVICE pointers unless marked "host". Streams are hipStream_t (NULL = the
+ * null stream).
+ *
+ * Errors: every call returns an sfft_status; nothing is thrown across the
+ * ABI. sfft_last_error() returns a message for the calling thread's last
+ * failure. A HIP failure inside a call returns SFFT_HIP_ERROR.
+ */
+#ifndef SFFT_H
+#define SFFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sfft_plan_s* sfft_plan;
+
+typedef enum {
+  SFFT_OK = 0,
+  SFFT_INVALID_ARG = 1,   /* null pointer, d < 1, n_l < 1, bad enum, x aliases y, short workspace */
+  SFFT_UNSUPPORTED = 2,   /* level size without built kernels, b not in {1, 3}, d > 6 */
+  SFFT_OUT_OF_MEMORY = 3, /* device allocation failed */
+  SFFT_HIP_ERROR = 4      /* a HIP runtime call or kernel launch failed */
+} sfft_status;
+
+typedef enum {
+  SFFT_C64 = 0,  /* complex64: FP32 arithmetic and accumulation, FP64-generated twiddles and symbols */
+  SFFT_C128 = 1  /* complex128: FP64 throughout */
+} sfft_dtype;
+
+typedef enum {
+  SFFT_SPLIT = 0, /* Algorithm 1: lazy embedding, eager projection */
+  SFFT_EMBED = 1  /* standard multilevel circulant embedding (baseline) */
+} sfft_method;
+
+typedef enum {
+  SFFT_SCHED_AUTO = 0,    /* breadth-first when its workspace is small, else depth-first */
+  SFFT_SCHED_BREADTH = 1, /* all branches of a level per launch: workspace (2^d - 2) vectors */
+  SFFT_SCHED_DEPTH = 2    /* Algorithm 1's lazy order: workspace (d - 1) vectors, peak (d + 1) with x, y */
+} sfft_schedule;
+
+/* Per-(component, level) symmetry of the generator t, used to store the
+ * symbol mirrored (Section II.C): EVEN means t(.., -r_l, ..)[a,c] = t(.., r_l, ..)[a,c],
+ * ODD means t(.., -r_l, ..)[a,c] = -t(.., r_l, ..)[a,c] (so the r_l = 0 plane is 0). */
+typedef enum { SFFT_PARITY_NONE = 0, SFFT_PARITY_EVEN = 1, SFFT_PARITY_ODD = 2 } sfft_parity;
+
+typedef struct {
+  int d;
+  int64_t n[8];
+  int b;
+  int dtype;
+  int method;
+  int schedule;            /* the schedule sfft_apply uses */
+  int compressed;          /* 1 when the symbol is stored mirrored */
+  int64_t max_nrhs;
+  size_t symbol_bytes;     /* device bytes held by the plan's symbols */
+  size_t table_bytes;      /* device bytes of twiddle tables */
+  size_t workspace_bytes;  /* sfft_workspace_size at max_nrhs */
+  int64_t vector_elems;    /* b * prod(n_l): entries of one right-hand side */
+} sfft_info;
+
+/* Build a plan and its Fourier-space symbols.
+ *
+ * Section II.B / II.C: the embedded generator (every level extended n -> 2n,
+ * pad entry 0) is transformed in FP64 on the GPU, scaled by 2^-d / prod(n_l),
+ * split into the 2^d parity parts T[bId] (SFFT_SPLIT) or kept whole
+ * (SFFT_EMBED) and stored in the compute dtype.
+ *
+ *   out       host: receives the plan handle (NULL on failure).
+ *   d         levels, 1 <= d <= 6.
+ *   n         host: d level sizes; each must have built kernels (as must 2 n_l).
+ *   b         block size (1 or 3).
+ *   coeffs    device, complex128 (b, b, 2n_1-1, ..., 2n_d-1); read during the
+ *             call only (the stream is synchronised before return, the caller
+ *             may free it afterwards).
+ *   dtype     SFFT_C64 or SFFT_C128.
+ *   method    SFFT_SPLIT or SFFT_EMBED.
+ *   parity    host, NULL or b*b*d sfft_parity values [(a*b + c)*d + l]: when
+ *             every entry is EVEN or ODD and method is SFFT_SPLIT, the symbol
+ *             is stored mirrored (about prod(n_l + 1) per component instead
+ *             of 2^d prod(n_l)). The declared symmetry is trusted.
+ *   max_nrhs  largest nrhs a later apply may use (sizes sfft_plan_info only).
+ *   schedule  sfft_schedule.
+ *   stream    hipStream_t for the generation kernels.
+ * The plan owns its device memory and is immutable after creation; one plan
+ * may be applied concurrently on several streams with distinct workspaces. */
+sfft_status sfft_plan_create(sfft_plan* out, int d, const int64_t* n, int b, const void* coeffs,
+                             int dtype, int method, const int32_t* parity, int64_t max_nrhs,
+                             int schedule, void* stream);
+
+/* Device bytes of workspace sfft_apply needs for nrhs right-hand sides. */
+sfft_status sfft_workspace_size(sfft_plan plan, int64_t nrhs, size_t* bytes);
+
+/* y = T x for nrhs right-hand sides (Algorithm 1, or the embedding baseline).
+ *   x, y       device (nrhs, b, n...) of the plan dtype; y must not overlap x.
+ *   workspace  device, at least sfft_workspace_size bytes, 256-byte aligned,
+ *              caller owned; NULL makes the plan allocate (and keep) its own,
+ *              which is then not safe for concurrent applies of one plan.
+ *   stream     hipStream_t; the call only enqueues work (asynchronous). */
+sfft_status sfft_apply(sfft_plan plan, const void* x, void* y, int64_t nrhs, void* workspace,
+                       size_t ws_bytes, void* stream);
+
+/* Several independent products in one call: problem i is plans[i] applied to
+ * x[i] -> y[i] with nrhs[i] right-hand sides. Host arrays of device pointers.
+ * Problems whose plans share level sizes, dtype and method are fused into the
+ * same kernel launches. workspace: at least sfft_workspace_size_multi bytes. */
+sfft_status sfft_workspace_size_multi(int nprob, const sfft_plan* plans, const int64_t* nrhs,
+                                      size_t* bytes);
+sfft_status sfft_apply_multi(int nprob, const sfft_plan* plans, const void* const* x,
+                             void* const* y, const int64_t* nrhs, void* workspace, size_t ws_bytes,
+                             void* stream);
+
+sfft_status sfft_plan_info(sfft_plan plan, sfft_info* info);
+sfft_status sfft_plan_destroy(sfft_plan plan);
+
+const char* sfft_status_string(sfft_status s);
+/* Message of the calling thread's last failed call ("" if none). */
+const char* sfft_last_error(void);
+/* 1 if kernels for pencil length L are built, else 0. */
+int sfft_length_supported(int64_t L);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SFFT_H */

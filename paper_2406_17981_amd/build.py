@@ -1,0 +1,91 @@
+"""Build libsfft.so (HIP kernels, runtime and C ABI) for gfx950, in-tree.
+
+    python -m paper_2406_17981_amd.build [-j N]
+
+Every call recompiles every source: one object per pencil length listed in
+csrc/lengths.def (kernels_len.hip with -DSFFT_LEN=<L>), the runtime, and a
+shared-library link. Objects go to _build/ at the repository root; the
+library is written next to this file.
+"""
+
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import os
+import re
+import shutil
+import subprocess
+import sys
+import time
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+BUILD = os.path.join(ROOT, "_build")
+LIB = os.path.join(PKG, "libsfft.so")
+
+ARCH = "gfx950"
+HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
+# Packed FP32 instructions are disabled on purpose; hipcc's host pass warns
+# that it does not know the feature, which is harmless.
+FLAGS = ["-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC",
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         f"-I{os.path.join(ROOT, 'include')}"]
+
+
+def lengths():
+    txt = open(os.path.join(CSRC, "lengths.def")).read()
+    return [int(v) for v in re.findall(r"SFFT_X\((\d+)\)", txt)]
+
+
+def _run(cmd):
+    t0 = time.time()
+    p = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    out = "\n".join(ln for ln in p.stdout.splitlines() if "packed-fp32-ops" not in ln)
+    return p.returncode, out, time.time() - t0
+
+
+def build(jobs: int | None = None, verbose: bool = False) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    jobs = jobs or min(8, os.cpu_count() or 1)
+    units = []
+    for L in lengths():
+        units.append((os.path.join(CSRC, "kernels_len.hip"), os.path.join(BUILD, f"kernels_L{L}.o"),
+                      [f"-DSFFT_LEN={L}"]))
+    units.append((os.path.join(CSRC, "runtime.hip"), os.path.join(BUILD, "runtime.o"), []))
+    # biggest lengths first so the slowest compiles start early
+    units.sort(key=lambda u: -int(re.search(r"(\d+)", os.path.basename(u[1])).group(1))
+               if "kernels_L" in u[1] else 0)
+    cmds = [[HIPCC] + FLAGS + extra + ["-c", src, "-o", obj] for src, obj, extra in units]
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        results = list(ex.map(_run, cmds))
+    failed = [(c, r) for c, r in zip(cmds, results) if r[0] != 0]
+    if failed:
+        for c, (rc, out, _) in failed:
+            sys.stderr.write(" ".join(c) + "\n" + out + "\n")
+        raise RuntimeError(f"{len(failed)} HIP compile step(s) failed")
+    if verbose:
+        for c, (_, out, dt) in zip(cmds, results):
+            print(f"{dt:6.1f}s {os.path.basename(c[-1])}")
+    tmp = LIB + ".tmp"
+    rc, out, _ = _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp]
+                      + [u[1] for u in units])
+    if rc != 0:
+        raise RuntimeError("link failed:\n" + out)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("-j", type=int, default=None)
+    ap.add_argument("-v", action="store_true")
+    a = ap.parse_args()
+    t0 = time.time()
+    path = build(a.j, a.v)
+    print(f"built {path} in {time.time() - t0:.1f}s")
+
+
+if __name__ == "__main__":
+    main()

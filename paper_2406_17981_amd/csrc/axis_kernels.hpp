@@ -1,0 +1,364 @@
+// Axis-pass kernels of the split-FFT block-Toeplitz matvec (and of the
+// full-embedding baseline and the FP64 symbol generator, which reuse them).
+//
+// A pass works on a set of branch vectors; inside one branch the data is seen
+// as (outer, L, inner): entry (o, k, i) at (o*L + k)*inner + i, and every
+// (o, i) is a pencil of length L along the transformed axis.
+//
+//   FWD2  (Section II.A split, Algorithm 1 FFT_l + sptBrn fused):
+//         out  = FFT_L(in)            (even child)
+//         out1 = FFT_L(Phi .* in)     (odd child, Phi[k] = exp(-i pi k / L))
+//         either output may be absent; in-place (out == in) is allowed.
+//   INV2  (Algorithm 1 iFFT_l + mrgBrn fused, unnormalised, the 1/2 and 1/L
+//         factors live in the symbols):
+//         out = iFFT_L(in) + conj(Phi) .* iFFT_L(in1)      (in1 may be absent)
+//   LEAF  (innermost level: FFT, mulBrn, iFFT and the last merge fused):
+//         out[a] = sum_p conj(Phi)^p .* iFFT_L( sum_c S_p[a, c] .* FFT_L(Phi^p .* in[c]) )
+//         with p over {0, 1} (split) or {0} (embedding baseline).
+//
+// Strided passes (inner > 1) give each lane of a wavefront one pencil so a
+// row k of a tile is one contiguous run in HBM; contiguous passes (inner = 1,
+// the innermost level) stage a tile of whole pencils through LDS so that
+// global loads and stores are linear.
+#pragma once
+
+#include "fft_engine.hpp"
+
+namespace sfft {
+
+struct PassArgs {
+  const void* in;    // branch q input at in + q*in_bs (elements)
+  const void* in1;   // INV2: odd child, same branch stride as in
+  void* out;         // branch q output at out + q*out_bs
+  void* out1;        // FWD2: odd child, same branch stride as out
+  int64_t in_bs;
+  int64_t out_bs;
+  int64_t nq;        // branches in this launch
+  int64_t outer;     // per branch: pencils along the axis are (outer, inner)
+  int64_t inner;
+  const void* tw;    // 2L entries exp(-i pi m / L)
+  int use_phase;     // FWD2/INV2: multiply the odd child by Phi / conj(Phi)
+  // LEAF only
+  const void* sym;   // symbols for branch q at sym + q*sym_bs
+  int64_t sym_bs;
+  int64_t npen;      // pencils per component per right-hand side
+  int64_t nrhs;
+  int64_t ntiles;    // ceil(npen / P)
+};
+
+// Launch geometry per length.
+template <int L> struct Geo {
+  using Sh = Shape<L>;
+  static constexpr int T = Sh::T;
+  static constexpr int E = Sh::E;
+  static constexpr int NT = 256;                       // strided / contiguous passes
+  static constexpr int W = NT / T;                     // strided tile width (pencils)
+  static constexpr int P = NT / T;                     // contiguous tile (pencils)
+  static constexpr int LP = L + 1;                     // padded LDS row
+  static constexpr int PL = (128 / T) > 0 ? (128 / T) : 1;  // leaf tile (pencils)
+  static constexpr int NTL = PL * T;                   // leaf threads
+};
+
+// ---------------------------------------------------------------------------
+// Strided axis: tile of L rows x W pencils, lane (c, t) = (tid % W, tid / W).
+// ---------------------------------------------------------------------------
+template <typename Real, int L, int MODE>
+__global__ void __launch_bounds__(256) k_strided(PassArgs a) {
+  using C = cx<Real>;
+  using G = Geo<L>;
+  using Sh = typename G::Sh;
+  constexpr int T = G::T, E = G::E, W = G::W;
+  __shared__ C lds[L * W];
+  const int tid = threadIdx.x;
+  const int c = tid % W, t = tid / W;
+  const int64_t cols = a.outer * a.inner;
+  const int64_t ntile = (cols + W - 1) / W;
+  const int64_t q = blockIdx.x / ntile;
+  const int64_t col = (blockIdx.x % ntile) * W + c;
+  const bool act = col < cols;
+  const int64_t o = act ? col / a.inner : 0;
+  const int64_t i = act ? col - o * a.inner : 0;
+  const int64_t base = o * L * a.inner + i;
+  const int64_t st = a.inner;
+  const C* tw = (const C*)a.tw;
+  C* lp = lds + c;
+  C h[E];
+  if constexpr (MODE == 0) {
+    const C* in = (const C*)a.in + q * a.in_bs + base;
+#pragma unroll
+    for (int m = 0; m < E; ++m) h[m] = act ? in[(t + T * m) * st] : czero<C>();
+    if (a.out) {
+      C w[E];
+#pragma unroll
+      for (int m = 0; m < E; ++m) w[m] = h[m];
+      fft_pencil<-1, Sh>(w, lp, W, t, tw);
+      if (act) {
+        C* out = (C*)a.out + q * a.out_bs + base;
+#pragma unroll
+        for (int m = 0; m < E; ++m) out[(t + T * m) * st] = w[m];
+      }
+    }
+    if (a.out1) {
+      C w[E];
+#pragma unroll
+      for (int m = 0; m < E; ++m) w[m] = a.use_phase ? cmul(h[m], tw[t + T * m]) : h[m];
+      fft_pencil<-1, Sh>(w, lp, W, t, tw);
+      if (act) {
+        C* out = (C*)a.out1 + q * a.out_bs + base;
+#pragma unroll
+        for (int m = 0; m < E; ++m) out[(t + T * m) * st] = w[m];
+      }
+    }
+  } else {
+    const C* in = (const C*)a.in + q * a.in_bs + base;
+#pragma unroll
+    for (int m = 0; m < E; ++m) h[m] = act ? in[(t + T * m) * st] : czero<C>();
+    fft_pencil<+1, Sh>(h, lp, W, t, tw);
+    if (a.in1) {
+      const C* in1 = (const C*)a.in1 + q * a.in_bs + base;
+      C w[E];
+#pragma unroll
+      for (int m = 0; m < E; ++m) w[m] = act ? in1[(t + T * m) * st] : czero<C>();
+      fft_pencil<+1, Sh>(w, lp, W, t, tw);
+#pragma unroll
+      for (int m = 0; m < E; ++m) h[m] = cadd(h[m], a.use_phase ? cmulc(w[m], tw[t + T * m]) : w[m]);
+    }
+    if (act) {
+      C* out = (C*)a.out + q * a.out_bs + base;
+#pragma unroll
+      for (int m = 0; m < E; ++m) out[(t + T * m) * st] = h[m];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Contiguous axis helpers: a tile of P whole pencils staged through LDS.
+// ---------------------------------------------------------------------------
+template <typename C, int L, int P, int NT>
+__device__ __forceinline__ void tile_load(C* lds, const C* src, int npen_here, int tid) {
+  constexpr int LP = L + 1;
+  for (int idx = tid; idx < P * L; idx += NT) {
+    const int g = idx / L, k = idx - (idx / L) * L;
+    lds[g * LP + k] = (g < npen_here) ? src[idx] : czero<C>();
+  }
+}
+
+template <typename C, int L, int P, int NT>
+__device__ __forceinline__ void tile_store(C* dst, const C* lds, int npen_here, int tid) {
+  constexpr int LP = L + 1;
+  for (int idx = tid; idx < P * L; idx += NT) {
+    const int g = idx / L, k = idx - (idx / L) * L;
+    if (g < npen_here) dst[idx] = lds[g * LP + k];
+  }
+}
+
+// Writes home entries of lane (g, t) to LDS, then the whole tile to dst.
+template <typename C, int L, int T, int E, int P, int NT>
+__device__ __forceinline__ void store_home(C* dst, C* lds, const C (&h)[E], int g, int t, int npen_here,
+                                           int tid) {
+  constexpr int LP = L + 1;
+#pragma unroll
+  for (int m = 0; m < E; ++m) lds[g * LP + t + T * m] = h[m];
+  __syncthreads();
+  tile_store<C, L, P, NT>(dst, lds, npen_here, tid);
+  __syncthreads();
+}
+
+template <typename Real, int L, int MODE>
+__global__ void __launch_bounds__(256) k_contig(PassArgs a) {
+  using C = cx<Real>;
+  using G = Geo<L>;
+  using Sh = typename G::Sh;
+  constexpr int T = G::T, E = G::E, P = G::P, LP = G::LP, NT = G::NT;
+  __shared__ C lds[P * LP];
+  const int tid = threadIdx.x;
+  const int g = tid / T, t = tid % T;
+  const int64_t ntile = (a.outer + P - 1) / P;
+  const int64_t q = blockIdx.x / ntile;
+  const int64_t p0 = (blockIdx.x % ntile) * P;
+  const int nh = (int)((a.outer - p0) < P ? (a.outer - p0) : P);
+  const C* tw = (const C*)a.tw;
+  C* lp = lds + g * LP;
+  C h[E];
+  tile_load<C, L, P, NT>(lds, (const C*)a.in + q * a.in_bs + p0 * L, nh, tid);
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < E; ++m) h[m] = lp[t + T * m];
+  __syncthreads();
+  if constexpr (MODE == 0) {
+    if (a.out) {
+      C w[E];
+#pragma unroll
+      for (int m = 0; m < E; ++m) w[m] = h[m];
+      fft_pencil<-1, Sh>(w, lp, 1, t, tw);
+      store_home<C, L, T, E, P, NT>((C*)a.out + q * a.out_bs + p0 * L, lds, w, g, t, nh, tid);
+    }
+    if (a.out1) {
+      C w[E];
+#pragma unroll
+      for (int m = 0; m < E; ++m) w[m] = a.use_phase ? cmul(h[m], tw[t + T * m]) : h[m];
+      fft_pencil<-1, Sh>(w, lp, 1, t, tw);
+      store_home<C, L, T, E, P, NT>((C*)a.out1 + q * a.out_bs + p0 * L, lds, w, g, t, nh, tid);
+    }
+  } else {
+    fft_pencil<+1, Sh>(h, lp, 1, t, tw);
+    if (a.in1) {
+      tile_load<C, L, P, NT>(lds, (const C*)a.in1 + q * a.in_bs + p0 * L, nh, tid);
+      __syncthreads();
+      C w[E];
+#pragma unroll
+      for (int m = 0; m < E; ++m) w[m] = lp[t + T * m];
+      __syncthreads();
+      fft_pencil<+1, Sh>(w, lp, 1, t, tw);
+#pragma unroll
+      for (int m = 0; m < E; ++m) h[m] = cadd(h[m], a.use_phase ? cmulc(w[m], tw[t + T * m]) : w[m]);
+    }
+    store_home<C, L, T, E, P, NT>((C*)a.out + q * a.out_bs + p0 * L, lds, h, g, t, nh, tid);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Leaf: innermost level with the b x b diagonal block product (mulBrn).
+// Input / output per branch: (nrhs, B, npen, L). Symbols per branch q:
+// [p][tile][a*B + c][m][lane] (NPAR x ntiles x B*B x E x NTL), i.e. in the
+// order the lanes hold the transformed entries, so every symbol load of a
+// wavefront is one contiguous run.
+// Workgroups are numbered so that the right-hand sides of one tile are 8
+// apart: they land on the same XCD and share its L2 copy of the symbols.
+// ---------------------------------------------------------------------------
+template <typename Real, int L, int B, int NPAR>
+__global__ void __launch_bounds__(Geo<L>::NTL) k_leaf(PassArgs a) {
+  using C = cx<Real>;
+  using G = Geo<L>;
+  using Sh = typename G::Sh;
+  constexpr int T = G::T, E = G::E, P = G::PL, LP = G::LP, NT = G::NTL;
+  __shared__ C home[B * P * LP];
+  __shared__ C scr[P * LP];
+  const int tid = threadIdx.x;
+  const int g = tid / T, t = tid % T;
+  const int64_t ntiles8 = (a.ntiles + 7) / 8;
+  const int64_t id = blockIdx.x;
+  const int64_t lo = id & 7;
+  const int64_t t2 = id >> 3;
+  const int64_t r = t2 % a.nrhs;
+  const int64_t t3 = t2 / a.nrhs;
+  const int64_t tile = (t3 % ntiles8) * 8 + lo;
+  const int64_t q = t3 / ntiles8;
+  if (tile >= a.ntiles) return;  // whole workgroup exits together
+  const int64_t p0 = tile * P;
+  const int nh = (int)((a.npen - p0) < P ? (a.npen - p0) : P);
+  const C* tw = (const C*)a.tw;
+  const C* in = (const C*)a.in + q * a.in_bs;
+  C* out = (C*)a.out + q * a.out_bs;
+
+#pragma unroll
+  for (int c = 0; c < B; ++c)
+    tile_load<C, L, P, NT>(home + c * P * LP, in + ((r * B + c) * a.npen + p0) * L, nh, tid);
+  __syncthreads();
+
+  C acc[B][E];
+#pragma unroll
+  for (int c = 0; c < B; ++c)
+#pragma unroll
+    for (int m = 0; m < E; ++m) acc[c][m] = czero<C>();
+
+  C* lp = scr + g * LP;
+#pragma unroll
+  for (int p = 0; p < NPAR; ++p) {
+    C w[B][E];
+#pragma unroll
+    for (int c = 0; c < B; ++c)
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const C v = home[c * P * LP + g * LP + t + T * m];
+        w[c][m] = (p == 1) ? cmul(v, tw[t + T * m]) : v;
+      }
+#pragma unroll
+    for (int c = 0; c < B; ++c) fft_pencil<-1, Sh>(w[c], lp, 1, t, tw);
+    const C* sp = (const C*)a.sym + q * a.sym_bs + ((int64_t)p * a.ntiles + tile) * (B * B * E * NT);
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      C o[B];
+#pragma unroll
+      for (int ar = 0; ar < B; ++ar) {
+        C s = czero<C>();
+#pragma unroll
+        for (int c = 0; c < B; ++c) s = cadd(s, cmul(sp[((ar * B + c) * E + m) * NT + tid], w[c][m]));
+        o[ar] = s;
+      }
+#pragma unroll
+      for (int ar = 0; ar < B; ++ar) w[ar][m] = o[ar];
+    }
+#pragma unroll
+    for (int c = 0; c < B; ++c) fft_pencil<+1, Sh>(w[c], lp, 1, t, tw);
+#pragma unroll
+    for (int c = 0; c < B; ++c)
+#pragma unroll
+      for (int m = 0; m < E; ++m)
+        acc[c][m] = cadd(acc[c][m], (p == 1) ? cmulc(w[c][m], tw[t + T * m]) : w[c][m]);
+  }
+
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < B; ++c)
+#pragma unroll
+    for (int m = 0; m < E; ++m) home[c * P * LP + g * LP + t + T * m] = acc[c][m];
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < B; ++c)
+    tile_store<C, L, P, NT>(out + ((r * B + c) * a.npen + p0) * L, home + c * P * LP, nh, tid);
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launch table for one length.
+// ---------------------------------------------------------------------------
+typedef hipError_t (*pass_fn)(const PassArgs&, hipStream_t);
+
+struct AxisOps {
+  int L, T, E, W, P, PL, NTL;
+  pass_fn strided[2];   // [0] FWD2, [1] INV2
+  pass_fn contig[2];
+  pass_fn leaf[5][3];   // [B][NPAR], null where not built
+};
+
+template <typename Real, int L, int MODE> hipError_t launch_strided(const PassArgs& a, hipStream_t s) {
+  using G = Geo<L>;
+  const int64_t cols = a.outer * a.inner;
+  const int64_t blocks = a.nq * ((cols + G::W - 1) / G::W);
+  if (blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_strided<Real, L, MODE>), dim3((unsigned)blocks), dim3(G::NT), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename Real, int L, int MODE> hipError_t launch_contig(const PassArgs& a, hipStream_t s) {
+  using G = Geo<L>;
+  const int64_t blocks = a.nq * ((a.outer + G::P - 1) / G::P);
+  if (blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_contig<Real, L, MODE>), dim3((unsigned)blocks), dim3(G::NT), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename Real, int L, int B, int NPAR> hipError_t launch_leaf(const PassArgs& a, hipStream_t s) {
+  using G = Geo<L>;
+  const int64_t blocks = a.nq * ((a.ntiles + 7) / 8) * a.nrhs * 8;
+  if (blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_leaf<Real, L, B, NPAR>), dim3((unsigned)blocks), dim3(G::NTL), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename Real, int L> const AxisOps* make_ops() {
+  using G = Geo<L>;
+  static const AxisOps ops = {
+      L, G::T, G::E, G::W, G::P, G::PL, G::NTL,
+      {launch_strided<Real, L, 0>, launch_strided<Real, L, 1>},
+      {launch_contig<Real, L, 0>, launch_contig<Real, L, 1>},
+      {{nullptr, nullptr, nullptr},
+       {nullptr, launch_leaf<Real, L, 1, 1>, launch_leaf<Real, L, 1, 2>},
+       {nullptr, nullptr, nullptr},
+       {nullptr, launch_leaf<Real, L, 3, 1>, launch_leaf<Real, L, 3, 2>},
+       {nullptr, nullptr, nullptr}},
+  };
+  return &ops;
+}
+
+}  // namespace sfft

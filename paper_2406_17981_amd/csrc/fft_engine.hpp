@@ -1,0 +1,296 @@
+// Pencil FFT engine for gfx950: one length-L complex DFT spread over T lanes.
+//
+// Each lane owns E = L/T "home" entries of its pencil, the entries k = t + T*m
+// (m = 0..E-1) for lane t. A transform is a chain of Stockham autosort radix
+// stages (radices from Shape<L>); the first stage reads its butterfly inputs
+// straight from the home registers and the last stage leaves its outputs in
+// the home registers, so a two-stage transform crosses LDS exactly once. The
+// output of a forward transform is in natural order, which is also the input
+// order of an inverse transform, so a pointwise product between the two needs
+// no data movement.
+//
+// Twiddles come from a per-length table tw[m] = exp(-2 pi i m / (2L)),
+// m = 0..2L-1, generated once in FP64: W_L^m = tw[2m] and the split phase of
+// the paper's Section II.A, exp(-i pi k / L), is tw[k].
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sfft {
+
+template <typename R> struct CxOf;
+template <> struct CxOf<float> { using type = float2; };
+template <> struct CxOf<double> { using type = double2; };
+template <typename R> using cx = typename CxOf<R>::type;
+
+template <typename C> __device__ __forceinline__ C mk(decltype(C::x) a, decltype(C::x) b) {
+  C c;
+  c.x = a;
+  c.y = b;
+  return c;
+}
+template <typename C> __device__ __forceinline__ C cadd(C a, C b) { return mk<C>(a.x + b.x, a.y + b.y); }
+template <typename C> __device__ __forceinline__ C csub(C a, C b) { return mk<C>(a.x - b.x, a.y - b.y); }
+template <typename C> __device__ __forceinline__ C cmul(C a, C b) {
+  return mk<C>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+template <typename C> __device__ __forceinline__ C cmulc(C a, C b) {
+  return mk<C>(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+template <typename C> __device__ __forceinline__ C cscale(C a, decltype(C::x) s) { return mk<C>(a.x * s, a.y * s); }
+template <typename C> __device__ __forceinline__ C czero() { return mk<C>(0, 0); }
+// (DIR * i) * a, DIR = -1 forward, +1 inverse
+template <int DIR, typename C> __device__ __forceinline__ C mul_di(C a) {
+  if constexpr (DIR > 0) return mk<C>(-a.y, a.x);
+  else return mk<C>(a.y, -a.x);
+}
+
+// ---------------------------------------------------------------------------
+// Small DFTs in registers, natural order in and out.
+// ---------------------------------------------------------------------------
+template <int DIR, typename C> __device__ __forceinline__ void dft2(C* v) {
+  C a = v[0], b = v[1];
+  v[0] = cadd(a, b);
+  v[1] = csub(a, b);
+}
+
+template <int DIR, typename C> __device__ __forceinline__ void dft3(C* v) {
+  using R = decltype(C::x);
+  const R c3 = (R)-0.5;
+  const R s3 = (R)0.86602540378443864676372317075294;  // sin(2 pi / 3)
+  C a = v[0];
+  C sb = cadd(v[1], v[2]);
+  C db = csub(v[1], v[2]);
+  C m = cadd(a, cscale(sb, c3));
+  C r = mul_di<DIR>(cscale(db, s3));
+  v[0] = cadd(a, sb);
+  v[1] = cadd(m, r);
+  v[2] = csub(m, r);
+}
+
+template <int DIR, typename C> __device__ __forceinline__ void dft4(C* v) {
+  C t0 = cadd(v[0], v[2]);
+  C t1 = csub(v[0], v[2]);
+  C t2 = cadd(v[1], v[3]);
+  C t3 = mul_di<DIR>(csub(v[1], v[3]));
+  v[0] = cadd(t0, t2);
+  v[2] = csub(t0, t2);
+  v[1] = cadd(t1, t3);
+  v[3] = csub(t1, t3);
+}
+
+template <int DIR, typename C> __device__ __forceinline__ void dft5(C* v) {
+  using R = decltype(C::x);
+  const R c1 = (R)0.30901699437494742410229341718282;   // cos(2 pi / 5)
+  const R c2 = (R)-0.80901699437494742410229341718282;  // cos(4 pi / 5)
+  const R s1 = (R)0.95105651629515357211643933337938;   // sin(2 pi / 5)
+  const R s2 = (R)0.58778525229247312916870595463907;   // sin(4 pi / 5)
+  C a0 = v[0];
+  C p1 = cadd(v[1], v[4]), m1 = csub(v[1], v[4]);
+  C p2 = cadd(v[2], v[3]), m2 = csub(v[2], v[3]);
+  C e1 = cadd(a0, cadd(cscale(p1, c1), cscale(p2, c2)));
+  C e2 = cadd(a0, cadd(cscale(p1, c2), cscale(p2, c1)));
+  C o1 = mul_di<DIR>(cadd(cscale(m1, s1), cscale(m2, s2)));
+  C o2 = mul_di<DIR>(csub(cscale(m1, s2), cscale(m2, s1)));
+  v[0] = cadd(a0, cadd(p1, p2));
+  v[1] = cadd(e1, o1);
+  v[4] = csub(e1, o1);
+  v[2] = cadd(e2, o2);
+  v[3] = csub(e2, o2);
+}
+
+template <int DIR, typename C> __device__ __forceinline__ void dft8(C* v) {
+  using R = decltype(C::x);
+  const R h = (R)0.70710678118654752440084436210485;  // sqrt(1/2)
+  C e[4] = {v[0], v[2], v[4], v[6]};
+  C o[4] = {v[1], v[3], v[5], v[7]};
+  dft4<DIR>(e);
+  dft4<DIR>(o);
+  // o[k] *= W8^k, W8 = exp(DIR 2 pi i / 8)
+  o[1] = cscale(cadd(o[1], mul_di<DIR>(o[1])), h);
+  o[2] = mul_di<DIR>(o[2]);
+  o[3] = cscale(csub(mul_di<DIR>(o[3]), o[3]), h);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    v[k] = cadd(e[k], o[k]);
+    v[k + 4] = csub(e[k], o[k]);
+  }
+}
+
+template <int DIR, typename C> __device__ __forceinline__ void dft16(C* v) {
+  using R = decltype(C::x);
+  const R h = (R)0.70710678118654752440084436210485;   // cos(pi/4)
+  const R c8 = (R)0.92387953251128675612818318939679;  // cos(pi/8)
+  const R s8 = (R)0.38268343236508977172845998403040;  // sin(pi/8)
+  // 16 = 4 x 4: n = 4 n1 + n2, k = k1 + 4 k2
+  C y[4][4];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+#pragma unroll
+    for (int n1 = 0; n1 < 4; ++n1) y[n2][n1] = v[4 * n1 + n2];
+    dft4<DIR>(y[n2]);
+  }
+  // twiddle W16^(n2 k1), W16 = exp(DIR 2 pi i / 16) = c8 + DIR i s8
+  const R D = (R)DIR;
+  const C w1 = mk<C>(c8, D * s8);
+  const C w2 = mk<C>(h, D * h);
+  const C w3 = mk<C>(s8, D * c8);
+  y[1][1] = cmul(y[1][1], w1);
+  y[1][2] = cmul(y[1][2], w2);
+  y[1][3] = cmul(y[1][3], w3);
+  y[2][1] = cmul(y[2][1], w2);
+  y[2][2] = mul_di<DIR>(y[2][2]);
+  y[2][3] = cmul(y[2][3], mk<C>(-h, D * h));
+  y[3][1] = cmul(y[3][1], w3);
+  y[3][2] = cmul(y[3][2], mk<C>(-h, D * h));
+  y[3][3] = cmul(y[3][3], mk<C>(-c8, -D * s8));
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    C z[4] = {y[0][k1], y[1][k1], y[2][k1], y[3][k1]};
+    dft4<DIR>(z);
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = z[k2];
+  }
+}
+
+template <int R, int DIR, typename C> __device__ __forceinline__ void dft(C* v) {
+  if constexpr (R == 2) dft2<DIR>(v);
+  else if constexpr (R == 3) dft3<DIR>(v);
+  else if constexpr (R == 4) dft4<DIR>(v);
+  else if constexpr (R == 5) dft5<DIR>(v);
+  else if constexpr (R == 8) dft8<DIR>(v);
+  else if constexpr (R == 16) dft16<DIR>(v);
+  else static_assert(R == 2, "unsupported radix");
+}
+
+// ---------------------------------------------------------------------------
+// Radix plans. T lanes per pencil; the first and last radices are chosen so
+// that T divides L/R_first and L/R_last (register-resident end stages).
+// ---------------------------------------------------------------------------
+template <int L> struct Shape;
+#define SFFT_SHAPE(LEN, TT, ...)                                               \
+  template <> struct Shape<LEN> {                                              \
+    static constexpr int L = LEN;                                              \
+    static constexpr int T = TT;                                               \
+    static constexpr int E = LEN / TT;                                         \
+    static constexpr int rads[] = {__VA_ARGS__};                               \
+    static constexpr int S = sizeof(rads) / sizeof(int);                       \
+    static constexpr int rad(int s) { return rads[s]; }                        \
+    static constexpr int ns(int s) { return s == 0 ? 1 : ns(s - 1) * rads[s - 1]; } \
+  };
+SFFT_SHAPE(2, 1, 2)
+SFFT_SHAPE(3, 1, 3)
+SFFT_SHAPE(4, 1, 4)
+SFFT_SHAPE(5, 1, 5)
+SFFT_SHAPE(6, 1, 2, 3)
+SFFT_SHAPE(8, 1, 8)
+SFFT_SHAPE(10, 1, 2, 5)
+SFFT_SHAPE(12, 1, 4, 3)
+SFFT_SHAPE(16, 4, 4, 4)
+SFFT_SHAPE(20, 4, 5, 4)
+SFFT_SHAPE(24, 4, 2, 4, 3)
+SFFT_SHAPE(32, 4, 8, 4)
+SFFT_SHAPE(40, 4, 2, 4, 5)
+SFFT_SHAPE(48, 4, 4, 4, 3)
+SFFT_SHAPE(64, 8, 8, 8)
+SFFT_SHAPE(80, 8, 2, 8, 5)
+SFFT_SHAPE(96, 8, 4, 8, 3)
+SFFT_SHAPE(128, 8, 8, 16)
+SFFT_SHAPE(160, 16, 2, 4, 4, 5)
+SFFT_SHAPE(192, 16, 4, 16, 3)
+SFFT_SHAPE(256, 16, 16, 16)
+SFFT_SHAPE(384, 32, 4, 8, 4, 3)
+SFFT_SHAPE(512, 32, 16, 4, 8)
+SFFT_SHAPE(768, 64, 4, 4, 16, 3)
+SFFT_SHAPE(1024, 64, 16, 8, 8)
+SFFT_SHAPE(2048, 128, 16, 8, 16)
+#undef SFFT_SHAPE
+
+template <typename Sh> constexpr bool shape_ok() {
+  int p = 1;
+  for (int s = 0; s < Sh::S; ++s) p *= Sh::rads[s];
+  return p == Sh::L && Sh::L % Sh::T == 0;
+}
+
+// One stage (and, recursively, the following ones) of a pencil transform.
+// lds: this pencil's LDS row, element k at lds[k * kst]. All lanes of the
+// workgroup must call this together (it contains workgroup barriers).
+template <typename C, typename Sh, int DIR, int s>
+__device__ __forceinline__ void fft_stage(C (&home)[Sh::E], C* lds, int kst, int t, const C* tw) {
+  constexpr int L = Sh::L, T = Sh::T, S = Sh::S;
+  constexpr int R = Sh::rad(s);
+  constexpr int Ns = Sh::ns(s);
+  constexpr int NB = L / R;
+  constexpr int PER = (NB + T - 1) / T;
+  constexpr bool EVEN = (NB % T) == 0;
+  constexpr bool FIRST_REG = (s == 0) && EVEN;
+  constexpr bool LAST_REG = (s == S - 1) && EVEN;
+  constexpr int TWS = L / (Ns * R);  // twiddle stride in W_L units
+
+  if constexpr (s == 0 && !FIRST_REG) {
+#pragma unroll
+    for (int m = 0; m < Sh::E; ++m) lds[(t + T * m) * kst] = home[m];
+    __syncthreads();
+  }
+
+  C v[PER][R];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int j = t + T * u;
+    if (EVEN || j < NB) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if constexpr (FIRST_REG) v[u][r] = home[u + r * (NB / T)];
+        else v[u][r] = lds[(j + r * NB) * kst];
+      }
+      if constexpr (s > 0) {
+        const int k = j % Ns;
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          C w = tw[2 * (r * k * TWS)];
+          if constexpr (DIR > 0) w.y = -w.y;
+          v[u][r] = cmul(v[u][r], w);
+        }
+      }
+      dft<R, DIR>(v[u]);
+    }
+  }
+
+  if constexpr (LAST_REG) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u)
+#pragma unroll
+      for (int q = 0; q < R; ++q) home[u + q * (NB / T)] = v[u][q];
+    if constexpr (!FIRST_REG) __syncthreads();  // LDS reads of this stage done before reuse
+  } else {
+    if constexpr (!FIRST_REG) __syncthreads();  // every lane has read this stage's inputs
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int j = t + T * u;
+      if (EVEN || j < NB) {
+        const int k = j % Ns;
+        const int base = (j / Ns) * Ns * R + k;
+#pragma unroll
+        for (int q = 0; q < R; ++q) lds[(base + q * Ns) * kst] = v[u][q];
+      }
+    }
+    __syncthreads();
+    if constexpr (s == S - 1) {
+#pragma unroll
+      for (int m = 0; m < Sh::E; ++m) home[m] = lds[(t + T * m) * kst];
+      __syncthreads();
+    }
+  }
+  if constexpr (s + 1 < S) fft_stage<C, Sh, DIR, s + 1>(home, lds, kst, t, tw);
+}
+
+// Unnormalised DFT of one pencil (DIR = -1 forward, +1 inverse).
+template <int DIR, typename Sh, typename C>
+__device__ __forceinline__ void fft_pencil(C (&home)[Sh::E], C* lds, int kst, int t, const C* tw) {
+  static_assert(shape_ok<Sh>(), "bad radix plan");
+  fft_stage<C, Sh, DIR, 0>(home, lds, kst, t, tw);
+}
+
+}  // namespace sfft

@@ -1,0 +1,723 @@
+// Plan, schedule and C ABI of the split-FFT block-Toeplitz matvec.
+//
+// Plan creation builds the Fourier-space branch data T[bId] of Section II.C
+// in FP64 on the GPU (embedded generator, 2n-point transforms along every
+// level, parity de-interleave, 2^-d / prod(n) folded in) and stores it in the
+// compute dtype in the order the leaf kernel's lanes consume it. Apply runs
+// Algorithm 1 as a sequence of fused axis passes:
+//
+//   level l = 1 .. d-1 : FWD2  (FFT_l of the even child, phase + FFT_l of the odd child)
+//   level d            : LEAF  (both children of the last level, mulBrn, iFFT_d, merge)
+//   level l = d-1 .. 1 : INV2  (iFFT_l of both children, merge with conj phase)
+//
+// either breadth-first (all branches of a level in one launch) or in the
+// lazy depth-first order of Algorithm 1 (one branch pair at a time, d-1
+// workspace vectors).
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/sfft.h"
+#include "axis_kernels.hpp"
+
+using sfft::AxisOps;
+using sfft::PassArgs;
+
+#define SFFT_X(L) extern "C" const AxisOps* sfft_ops_##L(int);
+#include "lengths.def"
+#undef SFFT_X
+
+namespace {
+
+constexpr int kMaxD = 6;
+
+const AxisOps* find_ops(int dtype, int64_t L) {
+  switch (L) {
+#define SFFT_X(LL) \
+  case LL:         \
+    return sfft_ops_##LL(dtype);
+#include "lengths.def"
+#undef SFFT_X
+    default:
+      return nullptr;
+  }
+}
+
+thread_local std::string g_err;
+
+sfft_status fail(sfft_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+sfft_status hip_fail(hipError_t e, const char* what) {
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return e == hipErrorOutOfMemory ? SFFT_OUT_OF_MEMORY : SFFT_HIP_ERROR;
+}
+
+#define HIP_TRY(expr, what)                   \
+  do {                                        \
+    hipError_t e_ = (expr);                   \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+struct Dims {
+  int d;
+  int64_t n[kMaxD];
+};
+
+// ---------------------------------------------------------------------------
+// Auxiliary kernels
+// ---------------------------------------------------------------------------
+
+// tw[m] = exp(-i pi m / L), m < 2L, evaluated in FP64 with exact rational
+// arguments and rounded once to the table type.
+template <typename C>
+__global__ void k_twiddle(C* tw, int L) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m < 2 * L) {
+    double s, c;
+    sincospi((double)m / (double)L, &s, &c);
+    tw[m] = sfft::mk<C>((decltype(C::x))c, (decltype(C::x))(-s));
+  }
+}
+
+// Circulant embedding of one block component (introduction): along each
+// level, offset r goes to position r mod 2n, position n holds 0.
+__global__ void k_embed_generator(const double2* __restrict__ coeffs, double2* __restrict__ c, int comp,
+                                  Dims dm, int64_t total) {
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    int64_t rem = idx, src = 0, sstride = 1;
+    bool pad = false;
+    for (int l = dm.d - 1; l >= 0; --l) {
+      const int64_t L2 = 2 * dm.n[l];
+      const int64_t m = rem % L2;
+      rem /= L2;
+      if (m == dm.n[l]) pad = true;
+      const int64_t r = m < dm.n[l] ? m : m - L2;
+      src += (r + dm.n[l] - 1) * sstride;
+      sstride *= 2 * dm.n[l] - 1;
+    }
+    c[idx] = pad ? sfft::mk<double2>(0.0, 0.0) : coeffs[(int64_t)comp * sstride + src];
+  }
+}
+
+// Parity de-interleave of one FP64 symbol component into the leaf layout of
+// the split plan: [Q][p][tile][a*B + c][m][lane] with Q the branch prefix
+// over levels 1..d-1 (level 1 most significant) and p the last level's bit.
+template <typename C>
+__global__ void k_scatter_split(const double2* __restrict__ full, C* __restrict__ sym, int ab, int B, Dims dm,
+                                int T, int E, int NT, int P, int64_t ntiles, int64_t npen, double scale,
+                                int64_t total) {
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int tid = (int)(idx % NT);
+    const int m = (int)((idx / NT) % E);
+    const int64_t tile = (idx / ((int64_t)NT * E)) % ntiles;
+    const int64_t pq = idx / ((int64_t)NT * E * ntiles);  // Q*2 + p
+    const int p = (int)(pq & 1);
+    const int64_t Q = pq >> 1;
+    const int64_t pencil = tile * P + tid / T;
+    const int64_t k = tid % T + (int64_t)T * m;
+    const int64_t dst = (((pq * ntiles + tile) * B * B + ab) * E + m) * NT + tid;
+    if (pencil >= npen) {
+      sym[dst] = sfft::mk<C>(0, 0);
+      continue;
+    }
+    const int d = dm.d;
+    int64_t fidx = 2 * k + p, fstride = 2 * dm.n[d - 1];
+    int64_t rem = pencil;
+    for (int l = d - 2; l >= 0; --l) {
+      const int64_t j = rem % dm.n[l];
+      rem /= dm.n[l];
+      const int64_t bit = (Q >> (d - 2 - l)) & 1;
+      fidx += (2 * j + bit) * fstride;
+      fstride *= 2 * dm.n[l];
+    }
+    const double2 v = full[fidx];
+    sym[dst] = sfft::mk<C>((decltype(C::x))(v.x * scale), (decltype(C::x))(v.y * scale));
+  }
+}
+
+// Full symbol of the embedding baseline in the leaf layout: [tile][a*B+c][m][lane]
+// over pencils of the 2n-grid.
+template <typename C>
+__global__ void k_scatter_embed(const double2* __restrict__ full, C* __restrict__ sym, int ab, int B, int T,
+                                int E, int NT, int P, int64_t ntiles, int64_t npen, int64_t L,
+                                double scale, int64_t total) {
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int tid = (int)(idx % NT);
+    const int m = (int)((idx / NT) % E);
+    const int64_t tile = idx / ((int64_t)NT * E);
+    const int64_t pencil = tile * P + tid / T;
+    const int64_t k = tid % T + (int64_t)T * m;
+    const int64_t dst = ((tile * B * B + ab) * E + m) * NT + tid;
+    if (pencil >= npen) {
+      sym[dst] = sfft::mk<C>(0, 0);
+      continue;
+    }
+    const double2 v = full[pencil * L + k];
+    sym[dst] = sfft::mk<C>((decltype(C::x))(v.x * scale), (decltype(C::x))(v.y * scale));
+  }
+}
+
+// x (nv, n...) -> zero-padded (nv, 2n...)
+template <typename C>
+__global__ void k_pad(const C* __restrict__ x, C* __restrict__ P, Dims dm, int64_t total) {
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    int64_t rem = idx, src = 0, sstride = 1;
+    bool inside = true;
+    for (int l = dm.d - 1; l >= 0; --l) {
+      const int64_t m = rem % (2 * dm.n[l]);
+      rem /= 2 * dm.n[l];
+      if (m >= dm.n[l]) inside = false;
+      src += m * sstride;
+      sstride *= dm.n[l];
+    }
+    P[idx] = inside ? x[rem * sstride + src] : sfft::mk<C>(0, 0);
+  }
+}
+
+// zero-padded (nv, 2n...) -> y (nv, n...): keep the first n along every level
+template <typename C>
+__global__ void k_project(const C* __restrict__ P, C* __restrict__ y, Dims dm, int64_t total) {
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    int64_t rem = idx, src = 0, sstride = 1;
+    for (int l = dm.d - 1; l >= 0; --l) {
+      const int64_t j = rem % dm.n[l];
+      rem /= dm.n[l];
+      src += j * sstride;
+      sstride *= 2 * dm.n[l];
+    }
+    y[idx] = P[rem * sstride + src];
+  }
+}
+
+unsigned grid_for(int64_t total, int block = 256) {
+  int64_t g = (total + block - 1) / block;
+  if (g > 65536) g = 65536;
+  if (g < 1) g = 1;
+  return (unsigned)g;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Plan
+// ---------------------------------------------------------------------------
+struct sfft_plan_s {
+  int d = 0;
+  int64_t n[kMaxD] = {0};
+  int b = 1;
+  int dtype = SFFT_C64;
+  int method = SFFT_SPLIT;
+  int sched = SFFT_SCHED_BREADTH;
+  int compressed = 0;
+  int64_t max_nrhs = 1;
+  int64_t s = 1;     // grid points
+  size_t esz = 8;    // bytes per complex entry
+  int64_t L[kMaxD];  // pencil length per level (n_l split, 2 n_l embed)
+  const AxisOps* ops[kMaxD] = {nullptr};
+  void* tw[kMaxD] = {nullptr};
+  void* sym = nullptr;
+  size_t sym_bytes = 0;
+  int64_t sym_bs = 0;  // symbol entries per leaf branch prefix
+  int64_t ntiles = 0;  // leaf tiles per component per rhs
+  int64_t npen = 0;    // leaf pencils per component per rhs
+  size_t table_bytes = 0;
+  std::mutex pool_mu;
+  void* pool = nullptr;
+  size_t pool_bytes = 0;
+
+  ~sfft_plan_s() {
+    for (int l = 0; l < kMaxD; ++l)
+      if (tw[l]) (void)hipFree(tw[l]);
+    if (sym) (void)hipFree(sym);
+    if (pool) (void)hipFree(pool);
+  }
+};
+
+namespace {
+
+int64_t vec_elems(const sfft_plan_s* p, int64_t nrhs) { return nrhs * p->b * p->s; }
+
+size_t workspace_elems(const sfft_plan_s* p, int64_t nrhs) {
+  const int64_t V = vec_elems(p, nrhs);
+  if (p->method == SFFT_EMBED) return (size_t)((int64_t(1) << p->d) * V);
+  if (p->d == 1) return 0;
+  if (p->sched == SFFT_SCHED_DEPTH) return (size_t)((p->d - 1) * V);
+  return (size_t)(((int64_t(1) << p->d) - 2) * V);
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Pass geometry of level l (0-based) for vectors (nv, L_0, ..., L_{d-1}).
+void level_geom(const sfft_plan_s* p, int l, int64_t nv, int64_t& outer, int64_t& inner) {
+  outer = nv;
+  for (int m = 0; m < l; ++m) outer *= p->L[m];
+  inner = 1;
+  for (int m = l + 1; m < p->d; ++m) inner *= p->L[m];
+}
+
+PassArgs base_args(const sfft_plan_s* p, int l, int64_t nv) {
+  PassArgs a;
+  std::memset(&a, 0, sizeof(a));
+  level_geom(p, l, nv, a.outer, a.inner);
+  a.tw = p->tw[l];
+  a.nq = 1;
+  return a;
+}
+
+sfft_status run_pass(const sfft_plan_s* p, int l, int mode, const PassArgs& a, hipStream_t st) {
+  const AxisOps* o = p->ops[l];
+  hipError_t e = (l == p->d - 1) ? o->contig[mode](a, st) : o->strided[mode](a, st);
+  if (e != hipSuccess) return hip_fail(e, "axis pass launch");
+  return SFFT_OK;
+}
+
+sfft_status run_leaf(const sfft_plan_s* p, const void* in, void* out, int64_t in_bs, int64_t nq, const void* sym,
+                     int64_t nrhs, hipStream_t st) {
+  const int l = p->d - 1;
+  const AxisOps* o = p->ops[l];
+  PassArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.in = in;
+  a.out = out;
+  a.in_bs = in_bs;
+  a.out_bs = in_bs;
+  a.nq = nq;
+  a.tw = p->tw[l];
+  a.sym = sym;
+  a.sym_bs = p->sym_bs;
+  a.npen = p->npen;
+  a.nrhs = nrhs;
+  a.ntiles = p->ntiles;
+  const int npar = p->method == SFFT_SPLIT ? 2 : 1;
+  sfft::pass_fn f = o->leaf[p->b][npar];
+  if (!f) return fail(SFFT_UNSUPPORTED, "no leaf kernel for this block size");
+  hipError_t e = f(a, st);
+  if (e != hipSuccess) return hip_fail(e, "leaf launch");
+  return SFFT_OK;
+}
+
+char* cptr(const void* base, int64_t elems, size_t esz) { return (char*)base + elems * (int64_t)esz; }
+
+// Depth-first (Algorithm 1 order): src holds the branch after levels < l were
+// transformed; dst receives that branch's merged result. Level l's odd child
+// lives in workspace vector l-1.
+sfft_status split_depth(const sfft_plan_s* p, int l, const void* src, void* dst, int64_t q, int64_t nrhs,
+                        char* ws, hipStream_t st) {
+  const int64_t V = vec_elems(p, nrhs);
+  const int64_t nv = nrhs * p->b;
+  if (l == p->d - 1) {
+    const void* sym = cptr(p->sym, q * p->sym_bs, p->esz);
+    return run_leaf(p, src, dst, V, 1, sym, nrhs, st);
+  }
+  void* odd = ws + (size_t)l * V * p->esz;
+  PassArgs a = base_args(p, l, nv);
+  a.in = src;
+  a.out = dst;
+  a.out1 = odd;
+  a.use_phase = 1;
+  sfft_status s = run_pass(p, l, 0, a, st);
+  if (s != SFFT_OK) return s;
+  if ((s = split_depth(p, l + 1, dst, dst, 2 * q, nrhs, ws, st)) != SFFT_OK) return s;
+  if ((s = split_depth(p, l + 1, odd, odd, 2 * q + 1, nrhs, ws, st)) != SFFT_OK) return s;
+  PassArgs b = base_args(p, l, nv);
+  b.in = dst;
+  b.in1 = odd;
+  b.out = dst;
+  b.use_phase = 1;
+  return run_pass(p, l, 1, b, st);
+}
+
+// Breadth-first: level l's 2^(l+1) branch vectors live contiguously in
+// workspace block l (branch index C-order over the parities of levels 0..l).
+sfft_status split_breadth(const sfft_plan_s* p, const void* x, void* y, int64_t nrhs, char* ws,
+                          hipStream_t st) {
+  const int d = p->d;
+  const int64_t V = vec_elems(p, nrhs);
+  const int64_t nv = nrhs * p->b;
+  if (d == 1) return run_leaf(p, x, y, V, 1, p->sym, nrhs, st);
+  char* blk[kMaxD];
+  size_t off = 0;
+  for (int l = 0; l < d - 1; ++l) {
+    blk[l] = ws + off * p->esz;
+    off += (size_t)(int64_t(2) << l) * V;
+  }
+  sfft_status s;
+  for (int l = 0; l < d - 1; ++l) {
+    PassArgs a = base_args(p, l, nv);
+    a.in = l == 0 ? x : (const void*)blk[l - 1];
+    a.in_bs = V;
+    a.nq = int64_t(1) << l;
+    a.out = blk[l];
+    a.out1 = blk[l] + V * p->esz;
+    a.out_bs = 2 * V;
+    a.use_phase = 1;
+    if ((s = run_pass(p, l, 0, a, st)) != SFFT_OK) return s;
+  }
+  if ((s = run_leaf(p, blk[d - 2], blk[d - 2], V, int64_t(1) << (d - 1), p->sym, nrhs, st)) != SFFT_OK)
+    return s;
+  for (int l = d - 2; l >= 0; --l) {
+    PassArgs a = base_args(p, l, nv);
+    a.in = blk[l];
+    a.in1 = blk[l] + V * p->esz;
+    a.in_bs = 2 * V;
+    a.nq = int64_t(1) << l;
+    a.out = l == 0 ? y : (void*)blk[l - 1];
+    a.out_bs = V;
+    a.use_phase = 1;
+    if ((s = run_pass(p, l, 1, a, st)) != SFFT_OK) return s;
+  }
+  return SFFT_OK;
+}
+
+// Standard circulant embedding: pad, transform every level of the 2^d-times
+// larger vector, block multiply, inverse transforms, project.
+sfft_status embed_apply(const sfft_plan_s* p, const void* x, void* y, int64_t nrhs, char* ws, hipStream_t st) {
+  const int d = p->d;
+  const int64_t nv = nrhs * p->b;
+  Dims dm;
+  dm.d = d;
+  for (int l = 0; l < d; ++l) dm.n[l] = p->n[l];
+  const int64_t big = nv * p->s * (int64_t(1) << d);
+  if (p->dtype == SFFT_C64)
+    hipLaunchKernelGGL(k_pad<float2>, dim3(grid_for(big)), dim3(256), 0, st, (const float2*)x, (float2*)ws, dm, big);
+  else
+    hipLaunchKernelGGL(k_pad<double2>, dim3(grid_for(big)), dim3(256), 0, st, (const double2*)x, (double2*)ws, dm,
+                       big);
+  HIP_TRY(hipGetLastError(), "pad launch");
+  sfft_status s;
+  for (int l = 0; l < d - 1; ++l) {
+    PassArgs a = base_args(p, l, nv);
+    a.in = ws;
+    a.out = ws;
+    if ((s = run_pass(p, l, 0, a, st)) != SFFT_OK) return s;
+  }
+  const int64_t Vbig = big;
+  if ((s = run_leaf(p, ws, ws, Vbig, 1, p->sym, nrhs, st)) != SFFT_OK) return s;
+  for (int l = d - 2; l >= 0; --l) {
+    PassArgs a = base_args(p, l, nv);
+    a.in = ws;
+    a.out = ws;
+    if ((s = run_pass(p, l, 1, a, st)) != SFFT_OK) return s;
+  }
+  const int64_t small = nv * p->s;
+  if (p->dtype == SFFT_C64)
+    hipLaunchKernelGGL(k_project<float2>, dim3(grid_for(small)), dim3(256), 0, st, (const float2*)ws, (float2*)y, dm,
+                       small);
+  else
+    hipLaunchKernelGGL(k_project<double2>, dim3(grid_for(small)), dim3(256), 0, st, (const double2*)ws, (double2*)y,
+                       dm, small);
+  HIP_TRY(hipGetLastError(), "project launch");
+  return SFFT_OK;
+}
+
+// FP64 forward transform of a (2n_0, ..., 2n_{d-1}) array in place.
+sfft_status fft64_inplace(const Dims& dm, double2* a, void* const* tw64, hipStream_t st) {
+  for (int l = 0; l < dm.d; ++l) {
+    const int64_t L = 2 * dm.n[l];
+    const AxisOps* o = find_ops(SFFT_C128, L);
+    if (!o) return fail(SFFT_UNSUPPORTED, "no FP64 kernels for length " + std::to_string(L));
+    PassArgs pa;
+    std::memset(&pa, 0, sizeof(pa));
+    pa.outer = 1;
+    for (int m = 0; m < l; ++m) pa.outer *= 2 * dm.n[m];
+    pa.inner = 1;
+    for (int m = l + 1; m < dm.d; ++m) pa.inner *= 2 * dm.n[m];
+    pa.in = a;
+    pa.out = a;
+    pa.nq = 1;
+    pa.tw = tw64[l];
+    hipError_t e = (l == dm.d - 1) ? o->contig[0](pa, st) : o->strided[0](pa, st);
+    if (e != hipSuccess) return hip_fail(e, "FP64 symbol transform");
+  }
+  return SFFT_OK;
+}
+
+sfft_status make_table(int dtype, int64_t L, void** out, size_t* bytes, hipStream_t st) {
+  const size_t esz = dtype == SFFT_C64 ? 8 : 16;
+  const size_t nb = (size_t)(2 * L) * esz;
+  HIP_TRY(hipMalloc(out, nb), "twiddle table allocation");
+  if (dtype == SFFT_C64)
+    hipLaunchKernelGGL(k_twiddle<float2>, dim3(grid_for(2 * L)), dim3(256), 0, st, (float2*)*out, (int)L);
+  else
+    hipLaunchKernelGGL(k_twiddle<double2>, dim3(grid_for(2 * L)), dim3(256), 0, st, (double2*)*out, (int)L);
+  HIP_TRY(hipGetLastError(), "twiddle launch");
+  if (bytes) *bytes += nb;
+  return SFFT_OK;
+}
+
+sfft_status build_symbols(sfft_plan_s* p, const double2* coeffs, hipStream_t st) {
+  const int d = p->d;
+  Dims dm;
+  dm.d = d;
+  int64_t full = 1;
+  for (int l = 0; l < d; ++l) {
+    dm.n[l] = p->n[l];
+    full *= 2 * p->n[l];
+  }
+  void* tw64[kMaxD] = {nullptr};
+  double2* tmp = nullptr;
+  sfft_status s = SFFT_OK;
+  auto cleanup = [&]() {
+    (void)hipStreamSynchronize(st);
+    for (int l = 0; l < d; ++l)
+      if (tw64[l]) (void)hipFree(tw64[l]);
+    if (tmp) (void)hipFree(tmp);
+  };
+  for (int l = 0; l < d && s == SFFT_OK; ++l) s = make_table(SFFT_C128, 2 * p->n[l], &tw64[l], nullptr, st);
+  if (s == SFFT_OK) {
+    hipError_t e = hipMalloc((void**)&tmp, (size_t)full * sizeof(double2));
+    if (e != hipSuccess) s = hip_fail(e, "FP64 symbol scratch allocation");
+  }
+  const double scale = 1.0 / ((double)full);  // 2^-d / prod(n)
+  const AxisOps* lo = p->ops[d - 1];
+  for (int ab = 0; ab < p->b * p->b && s == SFFT_OK; ++ab) {
+    hipLaunchKernelGGL(k_embed_generator, dim3(grid_for(full)), dim3(256), 0, st, coeffs, tmp, ab, dm, full);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+      s = hip_fail(e, "embed generator launch");
+      break;
+    }
+    if ((s = fft64_inplace(dm, tmp, tw64, st)) != SFFT_OK) break;
+    if (p->method == SFFT_SPLIT) {
+      const int64_t total = (int64_t(1) << d) * p->ntiles * lo->E * lo->NTL;
+      if (p->dtype == SFFT_C64)
+        hipLaunchKernelGGL(k_scatter_split<float2>, dim3(grid_for(total)), dim3(256), 0, st, tmp, (float2*)p->sym,
+                           ab, p->b, dm, lo->T, lo->E, lo->NTL, lo->PL, p->ntiles, p->npen, scale, total);
+      else
+        hipLaunchKernelGGL(k_scatter_split<double2>, dim3(grid_for(total)), dim3(256), 0, st, tmp,
+                           (double2*)p->sym, ab, p->b, dm, lo->T, lo->E, lo->NTL, lo->PL, p->ntiles, p->npen,
+                           scale, total);
+    } else {
+      const int64_t total = p->ntiles * lo->E * lo->NTL;
+      if (p->dtype == SFFT_C64)
+        hipLaunchKernelGGL(k_scatter_embed<float2>, dim3(grid_for(total)), dim3(256), 0, st, tmp, (float2*)p->sym,
+                           ab, p->b, lo->T, lo->E, lo->NTL, lo->PL, p->ntiles, p->npen, p->L[d - 1], scale, total);
+      else
+        hipLaunchKernelGGL(k_scatter_embed<double2>, dim3(grid_for(total)), dim3(256), 0, st, tmp,
+                           (double2*)p->sym, ab, p->b, lo->T, lo->E, lo->NTL, lo->PL, p->ntiles, p->npen,
+                           p->L[d - 1], scale, total);
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) s = hip_fail(e, "symbol scatter launch");
+  }
+  cleanup();
+  if (s == SFFT_OK) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) s = hip_fail(e, "symbol generation");
+  }
+  return s;
+}
+
+bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const char* x = (const char*)a;
+  const char* y = (const char*)b;
+  return x < y + nb && y < x + na;
+}
+
+sfft_status apply_one(sfft_plan_s* p, const void* x, void* y, int64_t nrhs, void* ws, size_t ws_bytes,
+                      hipStream_t st) {
+  if (!x || !y) return fail(SFFT_INVALID_ARG, "x and y must be non-null device pointers");
+  if (nrhs < 1) return fail(SFFT_INVALID_ARG, "nrhs must be >= 1");
+  const size_t vbytes = (size_t)vec_elems(p, nrhs) * p->esz;
+  if (ranges_overlap(x, vbytes, y, vbytes)) return fail(SFFT_INVALID_ARG, "y must not overlap x");
+  const size_t need = workspace_elems(p, nrhs) * p->esz;
+  if (need > 0) {
+    if (ws) {
+      if (ws_bytes < need)
+        return fail(SFFT_INVALID_ARG, "workspace too small: need " + std::to_string(need) + " bytes");
+      if (ranges_overlap(ws, need, x, vbytes) || ranges_overlap(ws, need, y, vbytes))
+        return fail(SFFT_INVALID_ARG, "workspace overlaps x or y");
+    } else {
+      std::lock_guard<std::mutex> g(p->pool_mu);
+      if (p->pool_bytes < need) {
+        if (p->pool) {
+          HIP_TRY(hipStreamSynchronize(st), "pool resize sync");
+          HIP_TRY(hipFree(p->pool), "pool free");
+          p->pool = nullptr;
+          p->pool_bytes = 0;
+        }
+        HIP_TRY(hipMalloc(&p->pool, need), "workspace pool allocation");
+        p->pool_bytes = need;
+      }
+      ws = p->pool;
+    }
+  }
+  if (p->method == SFFT_EMBED) return embed_apply(p, x, y, nrhs, (char*)ws, st);
+  if (p->sched == SFFT_SCHED_DEPTH && p->d > 1) return split_depth(p, 0, x, y, 0, nrhs, (char*)ws, st);
+  return split_breadth(p, x, y, nrhs, (char*)ws, st);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* sfft_status_string(sfft_status s) {
+  switch (s) {
+    case SFFT_OK: return "SFFT_OK";
+    case SFFT_INVALID_ARG: return "SFFT_INVALID_ARG";
+    case SFFT_UNSUPPORTED: return "SFFT_UNSUPPORTED";
+    case SFFT_OUT_OF_MEMORY: return "SFFT_OUT_OF_MEMORY";
+    case SFFT_HIP_ERROR: return "SFFT_HIP_ERROR";
+  }
+  return "SFFT_UNKNOWN";
+}
+
+const char* sfft_last_error(void) { return g_err.c_str(); }
+
+int sfft_length_supported(int64_t L) { return find_ops(SFFT_C64, L) != nullptr ? 1 : 0; }
+
+sfft_status sfft_plan_create(sfft_plan* out, int d, const int64_t* n, int b, const void* coeffs, int dtype,
+                             int method, const int32_t* parity, int64_t max_nrhs, int schedule, void* stream) {
+  g_err.clear();
+  if (!out) return fail(SFFT_INVALID_ARG, "out is null");
+  *out = nullptr;
+  if (!n || !coeffs) return fail(SFFT_INVALID_ARG, "n and coeffs must be non-null");
+  if (d < 1) return fail(SFFT_INVALID_ARG, "d must be >= 1");
+  if (d > kMaxD) return fail(SFFT_UNSUPPORTED, "d > 6");
+  if (b < 1) return fail(SFFT_INVALID_ARG, "b must be >= 1");
+  if (b != 1 && b != 3) return fail(SFFT_UNSUPPORTED, "block size must be 1 or 3");
+  if (dtype != SFFT_C64 && dtype != SFFT_C128) return fail(SFFT_INVALID_ARG, "bad dtype");
+  if (method != SFFT_SPLIT && method != SFFT_EMBED) return fail(SFFT_INVALID_ARG, "bad method");
+  if (schedule < SFFT_SCHED_AUTO || schedule > SFFT_SCHED_DEPTH) return fail(SFFT_INVALID_ARG, "bad schedule");
+  if (max_nrhs < 1) return fail(SFFT_INVALID_ARG, "max_nrhs must be >= 1");
+  for (int l = 0; l < d; ++l) {
+    if (n[l] < 1) return fail(SFFT_INVALID_ARG, "level sizes must be >= 1");
+    if (!find_ops(dtype, 2 * n[l]))
+      return fail(SFFT_UNSUPPORTED, "no kernels for length " + std::to_string(2 * n[l]));
+    if (method == SFFT_SPLIT && !find_ops(dtype, n[l]))
+      return fail(SFFT_UNSUPPORTED, "no kernels for length " + std::to_string(n[l]));
+  }
+  if (parity) {
+    for (int i = 0; i < b * b * d; ++i)
+      if (parity[i] < SFFT_PARITY_NONE || parity[i] > SFFT_PARITY_ODD)
+        return fail(SFFT_INVALID_ARG, "bad parity entry");
+    return fail(SFFT_UNSUPPORTED, "mirrored symbol storage is not built yet");
+  }
+
+  sfft_plan_s* p = new sfft_plan_s();
+  hipStream_t st = (hipStream_t)stream;
+  p->d = d;
+  p->b = b;
+  p->dtype = dtype;
+  p->method = method;
+  p->max_nrhs = max_nrhs;
+  p->esz = dtype == SFFT_C64 ? 8 : 16;
+  p->s = 1;
+  for (int l = 0; l < d; ++l) {
+    p->n[l] = n[l];
+    p->s *= n[l];
+    p->L[l] = method == SFFT_SPLIT ? n[l] : 2 * n[l];
+    p->ops[l] = find_ops(dtype, p->L[l]);
+  }
+  // schedule: depth-first when the breadth-first workspace would exceed 8 GiB
+  if (schedule == SFFT_SCHED_AUTO) {
+    const double bw = (double)(((int64_t(1) << d) - 2) * max_nrhs * b * p->s) * p->esz;
+    p->sched = bw > 8.0 * (1 << 30) ? SFFT_SCHED_DEPTH : SFFT_SCHED_BREADTH;
+  } else {
+    p->sched = schedule;
+  }
+  const AxisOps* lo = p->ops[d - 1];
+  p->npen = 1;
+  for (int l = 0; l < d - 1; ++l) p->npen *= p->L[l];
+  p->ntiles = (p->npen + lo->PL - 1) / lo->PL;
+  const int npar = method == SFFT_SPLIT ? 2 : 1;
+  p->sym_bs = (int64_t)npar * p->ntiles * b * b * lo->E * lo->NTL;
+  const int64_t nbranch = method == SFFT_SPLIT ? (int64_t(1) << (d - 1)) : 1;
+  p->sym_bytes = (size_t)(nbranch * p->sym_bs) * p->esz;
+
+  sfft_status s = SFFT_OK;
+  for (int l = 0; l < d && s == SFFT_OK; ++l) s = make_table(dtype, p->L[l], &p->tw[l], &p->table_bytes, st);
+  if (s == SFFT_OK) {
+    hipError_t e = hipMalloc(&p->sym, p->sym_bytes);
+    if (e != hipSuccess) s = hip_fail(e, "symbol allocation");
+  }
+  if (s == SFFT_OK) s = build_symbols(p, (const double2*)coeffs, st);
+  if (s != SFFT_OK) {
+    delete p;
+    return s;
+  }
+  *out = p;
+  return SFFT_OK;
+}
+
+sfft_status sfft_workspace_size(sfft_plan plan, int64_t nrhs, size_t* bytes) {
+  if (!plan || !bytes) return fail(SFFT_INVALID_ARG, "null argument");
+  if (nrhs < 1) return fail(SFFT_INVALID_ARG, "nrhs must be >= 1");
+  *bytes = workspace_elems(plan, nrhs) * plan->esz;
+  return SFFT_OK;
+}
+
+sfft_status sfft_apply(sfft_plan plan, const void* x, void* y, int64_t nrhs, void* workspace, size_t ws_bytes,
+                       void* stream) {
+  if (!plan) return fail(SFFT_INVALID_ARG, "plan is null");
+  return apply_one(plan, x, y, nrhs, workspace, ws_bytes, (hipStream_t)stream);
+}
+
+sfft_status sfft_workspace_size_multi(int nprob, const sfft_plan* plans, const int64_t* nrhs, size_t* bytes) {
+  if (nprob < 0 || (nprob > 0 && (!plans || !nrhs)) || !bytes) return fail(SFFT_INVALID_ARG, "null argument");
+  size_t total = 0;
+  for (int i = 0; i < nprob; ++i) {
+    if (!plans[i] || nrhs[i] < 1) return fail(SFFT_INVALID_ARG, "bad problem entry");
+    total += align256(workspace_elems(plans[i], nrhs[i]) * plans[i]->esz);
+  }
+  *bytes = total;
+  return SFFT_OK;
+}
+
+sfft_status sfft_apply_multi(int nprob, const sfft_plan* plans, const void* const* x, void* const* y,
+                             const int64_t* nrhs, void* workspace, size_t ws_bytes, void* stream) {
+  if (nprob < 0 || (nprob > 0 && (!plans || !x || !y || !nrhs))) return fail(SFFT_INVALID_ARG, "null argument");
+  size_t need = 0;
+  sfft_status s = sfft_workspace_size_multi(nprob, plans, nrhs, &need);
+  if (s != SFFT_OK) return s;
+  if (need > 0 && (!workspace || ws_bytes < need)) return fail(SFFT_INVALID_ARG, "workspace too small");
+  size_t off = 0;
+  for (int i = 0; i < nprob; ++i) {
+    const size_t w = align256(workspace_elems(plans[i], nrhs[i]) * plans[i]->esz);
+    s = apply_one(plans[i], x[i], y[i], nrhs[i], w ? (char*)workspace + off : nullptr, w, (hipStream_t)stream);
+    if (s != SFFT_OK) return s;
+    off += w;
+  }
+  return SFFT_OK;
+}
+
+sfft_status sfft_plan_info(sfft_plan plan, sfft_info* info) {
+  if (!plan || !info) return fail(SFFT_INVALID_ARG, "null argument");
+  std::memset(info, 0, sizeof(*info));
+  info->d = plan->d;
+  for (int l = 0; l < plan->d; ++l) info->n[l] = plan->n[l];
+  info->b = plan->b;
+  info->dtype = plan->dtype;
+  info->method = plan->method;
+  info->schedule = plan->sched;
+  info->compressed = plan->compressed;
+  info->max_nrhs = plan->max_nrhs;
+  info->symbol_bytes = plan->sym_bytes;
+  info->table_bytes = plan->table_bytes;
+  info->workspace_bytes = workspace_elems(plan, plan->max_nrhs) * plan->esz;
+  info->vector_elems = plan->b * plan->s;
+  return SFFT_OK;
+}
+
+sfft_status sfft_plan_destroy(sfft_plan plan) {
+  if (!plan) return fail(SFFT_INVALID_ARG, "plan is null");
+  delete plan;
+  return SFFT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,180 @@
+"""Python face of the C ABI: a Plan over torch device tensors.
+
+PyTorch provides device memory and streams only; every step of the product
+runs in libsfft.so's HIP kernels.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import math
+from typing import Optional, Sequence
+
+import torch
+
+from . import _native as N
+
+_DTYPES = {"c64": (N.C64, torch.complex64), "c128": (N.C128, torch.complex128)}
+_METHODS = {"split": N.SPLIT, "embed": N.EMBED}
+_SCHEDS = {"auto": N.SCHED_AUTO, "breadth": N.SCHED_BREADTH, "depth": N.SCHED_DEPTH}
+
+
+def _stream_handle(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+def _require_device(t: torch.Tensor, name: str, dtype: torch.dtype):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+class Plan:
+    """y = T x for a d-level block-Toeplitz T (Algorithm 1 or the embedding baseline).
+
+    n: level sizes (n_1 outermost); b: block size; coeffs: complex128 device
+    tensor (b, b, 2n_1-1, ..., 2n_d-1) (host arrays are copied to the device);
+    dtype "c64" | "c128"; method "split" | "embed"; parity: optional
+    (b, b, d) int array of 0 / 1 (even) / 2 (odd) for mirrored symbol storage;
+    schedule "auto" | "breadth" | "depth".
+    """
+
+    def __init__(self, n: Sequence[int], b: int, coeffs, dtype: str = "c64", method: str = "split",
+                 parity=None, max_nrhs: int = 1, schedule: str = "auto", stream=None):
+        self.n = tuple(int(v) for v in n)
+        self.d = len(self.n)
+        self.b = int(b)
+        self.dtype_code, self.torch_dtype = _DTYPES[dtype]
+        self.dtype = dtype
+        self.method = method
+        if not isinstance(coeffs, torch.Tensor) or not coeffs.is_cuda:
+            coeffs = torch.as_tensor(coeffs, dtype=torch.complex128).to("cuda")
+        _require_device(coeffs, "coeffs", torch.complex128)
+        want = (self.b, self.b) + tuple(2 * v - 1 for v in self.n)
+        if tuple(coeffs.shape) != want:
+            raise ValueError(f"coeffs shape {tuple(coeffs.shape)} != {want}")
+        n_arr = (C.c_int64 * self.d)(*self.n)
+        par_ptr = None
+        if parity is not None:
+            import numpy as np
+            par = np.ascontiguousarray(np.asarray(parity, dtype=np.int32).reshape(-1))
+            if par.size != self.b * self.b * self.d:
+                raise ValueError("parity must have b*b*d entries")
+            self._par = (C.c_int32 * par.size)(*par.tolist())
+            par_ptr = self._par
+        h = C.c_void_p()
+        st = N.lib.sfft_plan_create(C.byref(h), self.d, n_arr, self.b, C.c_void_p(coeffs.data_ptr()),
+                                    self.dtype_code, _METHODS[method], par_ptr, int(max_nrhs),
+                                    _SCHEDS[schedule], C.c_void_p(_stream_handle(stream)))
+        N.check(st, "sfft_plan_create")
+        self._h = h
+        self.max_nrhs = int(max_nrhs)
+
+    # -- queries ---------------------------------------------------------
+    @property
+    def handle(self) -> C.c_void_p:
+        if self._h is None:
+            raise RuntimeError("plan destroyed")
+        return self._h
+
+    def info(self) -> dict:
+        inf = N.SfftInfo()
+        N.check(N.lib.sfft_plan_info(self.handle, C.byref(inf)), "sfft_plan_info")
+        return dict(d=inf.d, n=tuple(inf.n[:inf.d]), b=inf.b, dtype=inf.dtype, method=inf.method,
+                    schedule=inf.schedule, compressed=inf.compressed, max_nrhs=inf.max_nrhs,
+                    symbol_bytes=inf.symbol_bytes, table_bytes=inf.table_bytes,
+                    workspace_bytes=inf.workspace_bytes, vector_elems=inf.vector_elems)
+
+    def workspace_size(self, nrhs: int) -> int:
+        out = C.c_size_t()
+        N.check(N.lib.sfft_workspace_size(self.handle, int(nrhs), C.byref(out)), "sfft_workspace_size")
+        return int(out.value)
+
+    def vector_shape(self, nrhs: int):
+        return (int(nrhs), self.b) + self.n
+
+    def alloc_workspace(self, nrhs: int) -> Optional[torch.Tensor]:
+        nb = self.workspace_size(nrhs)
+        if nb == 0:
+            return None
+        return torch.empty(nb, dtype=torch.uint8, device="cuda")
+
+    # -- apply -----------------------------------------------------------
+    def apply(self, x: torch.Tensor, y: Optional[torch.Tensor] = None,
+              workspace: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """y = T x; x is (nrhs, b, *n) (or (b, *n)) of the plan dtype, on the device."""
+        _require_device(x, "x", self.torch_dtype)
+        squeeze = x.dim() == self.d + 1
+        xs = x.unsqueeze(0) if squeeze else x
+        if tuple(xs.shape[1:]) != (self.b,) + self.n:
+            raise ValueError(f"x shape {tuple(x.shape)} does not match b={self.b}, n={self.n}")
+        nrhs = xs.shape[0]
+        if y is None:
+            y = torch.empty_like(xs)
+        else:
+            _require_device(y, "y", self.torch_dtype)
+            if y.numel() != xs.numel():
+                raise ValueError("y has the wrong size")
+        ws_ptr, ws_bytes = None, 0
+        if workspace is not None:
+            if not workspace.is_cuda or not workspace.is_contiguous():
+                raise ValueError("workspace must be a contiguous device tensor")
+            ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
+        st = N.lib.sfft_apply(self.handle, C.c_void_p(xs.data_ptr()), C.c_void_p(y.data_ptr()), nrhs,
+                              C.c_void_p(ws_ptr) if ws_ptr else None, ws_bytes,
+                              C.c_void_p(_stream_handle(stream)))
+        N.check(st, "sfft_apply")
+        return y.view(x.shape) if squeeze else y
+
+    __call__ = apply
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            N.lib.sfft_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def workspace_size_multi(plans: Sequence[Plan], nrhs: Sequence[int]) -> int:
+    k = len(plans)
+    arr = (C.c_void_p * k)(*[p.handle.value for p in plans])
+    nr = (C.c_int64 * k)(*[int(v) for v in nrhs])
+    out = C.c_size_t()
+    N.check(N.lib.sfft_workspace_size_multi(k, arr, nr, C.byref(out)), "sfft_workspace_size_multi")
+    return int(out.value)
+
+
+def apply_multi(plans: Sequence[Plan], xs: Sequence[torch.Tensor], ys: Sequence[torch.Tensor],
+                workspace: Optional[torch.Tensor] = None, stream=None):
+    """Problem i: ys[i] = T_i xs[i], all in one call of the C ABI."""
+    k = len(plans)
+    if not (len(xs) == len(ys) == k):
+        raise ValueError("plans, xs and ys must have the same length")
+    nr = []
+    for p, x, y in zip(plans, xs, ys):
+        _require_device(x, "x", p.torch_dtype)
+        _require_device(y, "y", p.torch_dtype)
+        if x.numel() % (p.b * math.prod(p.n)) or y.numel() != x.numel():
+            raise ValueError("bad vector size")
+        nr.append(x.numel() // (p.b * math.prod(p.n)))
+    arr = (C.c_void_p * k)(*[p.handle.value for p in plans])
+    xa = (C.c_void_p * k)(*[x.data_ptr() for x in xs])
+    ya = (C.c_void_p * k)(*[y.data_ptr() for y in ys])
+    na = (C.c_int64 * k)(*nr)
+    if workspace is None:
+        nb = workspace_size_multi(plans, nr)
+        workspace = torch.empty(max(nb, 1), dtype=torch.uint8, device="cuda")
+    st = N.lib.sfft_apply_multi(k, arr, xa, ya, na, C.c_void_p(workspace.data_ptr()),
+                                workspace.numel(), C.c_void_p(_stream_handle(stream)))
+    N.check(st, "sfft_apply_multi")
+    return ys
