@@ -1,0 +1,325 @@
+#!/usr/bin/env python3
+"""Benchmark of the split-FFT multilevel block-Toeplitz matvec on one MI355X.
+
+Workload: d = 3 levels, 64 x 64 x 64 grid, 3 x 3 Green-function blocks
+t(r) = exp(i k |r|)/|r| (I - rhat rhat^T), k = 0.7, self term 2 I; one
+complex vector per matvec (seeded complex-normal). A step is one matvec
+y = T x through the whole hot path (forward split passes, fused leaf,
+inverse merge passes), inputs resident in HBM.
+
+Prints ONE JSON line: the headline is the complex64 split path; the FP64
+split path and the full circulant-embedding baseline (same GPU, same kernels)
+are reported beside it, with the dominant kernel's roofline and the FP64 CPU
+oracle's throughput on the host.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "block-Toeplitz matvecs/s & HBM roofline %, split-FFT vs full embed; p99 latency"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["paper_2406_17981_amd/csrc/fft_engine.hpp",
+                  "paper_2406_17981_amd/csrc/axis_kernels.hpp"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch from a committed rocprofv3 PMC summary, or None when
+    absent or taken on kernel sources that have changed since."""
+    path = os.path.join(ROOT, "profiles", "leaf_pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+    except Exception:
+        return None
+    if rec.get("kernel_source_hash") != kernel_source_hash() or rec.get("kernel") != kernel:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def stream_copy_gbs(nbytes=1 << 30, reps=20):
+    """Device-to-device copy bandwidth (read + write bytes per second) of a plain
+    copy of nbytes: the practical HBM ceiling on this machine."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / dt / 1e9
+
+
+COPY_PROBE_BYTES = 1 << 30
+
+
+def pmc_probe():
+    """Run under rocprofv3 --pmc: a plain device copy of COPY_PROBE_BYTES (read
+    and written once each) next to ten headline matvecs, so the counters of the
+    leaf kernel can be scaled by those of a copy of known size."""
+    import torch
+    import workloads as wl
+    import paper_2406_17981_amd as sf
+    a = torch.empty(COPY_PROBE_BYTES // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    coeffs, x_host = wl.green_64(1)
+    plan = sf.Plan(wl.GREEN_64["n"], 3, torch.from_numpy(coeffs).cuda(), dtype="c64", method="split")
+    x = torch.from_numpy(x_host).to(torch.complex64).cuda()
+    y = torch.empty_like(x)
+    ws = plan.alloc_workspace(1)
+    for _ in range(12):
+        plan.apply(x, y, ws)
+    torch.cuda.synchronize()
+    log("pmc probe done")
+
+
+def pmc_summarize(fetch_dir, write_dir, out_path):
+    """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the leaf kernel, scaled by the
+    copy probe's counters, written as JSON for the roofline's traffic field."""
+    import csv
+    import glob
+
+    def load(d, counter):
+        rows = []
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            rows += [r for r in csv.DictReader(open(f)) if r.get("Counter_Name") == counter]
+        return rows
+
+    def per_kernel(rows):
+        agg = {}
+        for r in rows:
+            agg.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return agg
+
+    out = {}
+    for key, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
+        agg = per_kernel(load(d, counter))
+        copy = [v for k, v in agg.items() if "copyBuffer" in k or "copy" in k.lower() and "sfft" not in k]
+        copy_kib = max(copy[0]) if copy else None
+        leaf = [v for k, v in agg.items() if k.startswith("void sfft::k_leaf<float, 64, 3, 2>")]
+        leaf_kib = sorted(leaf[0])[len(leaf[0]) // 2] if leaf else None
+        scale = COPY_PROBE_BYTES / (copy_kib * 1024.0) if copy_kib else None
+        out[key] = dict(copy_kib=copy_kib, leaf_kib_median=leaf_kib, scale=scale,
+                        leaf_bytes=leaf_kib * 1024.0 * scale if (leaf_kib and scale) else None)
+    total = None
+    if out["fetch"]["leaf_bytes"] is not None and out["write"]["leaf_bytes"] is not None:
+        total = out["fetch"]["leaf_bytes"] + out["write"]["leaf_bytes"]
+    rec = dict(kernel="sfft::k_leaf<float, 64, 3, 2>", kernel_source_hash=kernel_source_hash(),
+               bytes_per_launch=total, detail=out,
+               command="rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) -- python3 bench.py --pmc-probe")
+    with open(out_path, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec))
+
+
+def time_plan(plan, x, y, ws, steps, warmup, profile_leaf=False):
+    import torch
+    for _ in range(warmup):
+        plan.apply(x, y, ws)
+    torch.cuda.synchronize()
+    if profile_leaf:
+        plan.profile(("leaf",))
+        plan.profile_read("leaf", reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.apply(x, y, ws)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    leaf = None
+    if profile_leaf:
+        ms, cnt = plan.profile_read("leaf", reset=True)
+        plan.profile(())
+        leaf = (ms, cnt)
+    return (t1 - t0) * 1e3 / steps, leaf
+
+
+def cpu_baseline(coeffs, x, budget_s):
+    """The FP64 oracle's circulant-embedding matvec timed on the host cores."""
+    import oracle
+    reps, t0 = 0, time.perf_counter()
+    c0 = os.times()
+    ref = None
+    while True:
+        ref = oracle.embed_matvec(coeffs, x)
+        reps += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    wall = time.perf_counter() - t0
+    c1 = os.times()
+    cpu = (c1.user - c0.user) + (c1.system - c0.system)
+    cores = max(1, int(round(cpu / wall)))
+    return ref, dict(value=reps / wall, unit="matvecs/s", cores=cores, kind="oracle",
+                     sample=f"{reps} full FP64 matvecs of the same 64^3 b=3 Green workload through "
+                            f"oracle.embed_matvec (symbol transform included each call), "
+                            f"{wall:.1f} s wall")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--schedule", default="auto", choices=["auto", "breadth", "depth"])
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--variants", default="all", choices=["all", "headline"])
+    ap.add_argument("--pmc-probe", action="store_true", help="workload for rocprofv3 --pmc runs")
+    ap.add_argument("--pmc-summarize", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON"))
+    args = ap.parse_args()
+
+    if args.pmc_summarize:
+        pmc_summarize(*args.pmc_summarize)
+        return
+    if args.pmc_probe:
+        pmc_probe()
+        return
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU split of the branch tree is a design note, not a measured path.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import workloads as wl
+    import paper_2406_17981_amd as sf
+
+    if not torch.cuda.is_available():
+        log("no GPU visible")
+        sys.exit(1)
+    dev = torch.cuda.get_device_properties(0)
+    log(f"device: {dev.name}, {dev.multi_processor_count} CUs")
+
+    cfg = wl.GREEN_64
+    n, b, nrhs = cfg["n"], cfg["b"], 1
+    coeffs, x_host = wl.green_64(nrhs)
+    coeffs_d = torch.from_numpy(coeffs).cuda()
+    s = math.prod(n)
+    d = len(n)
+
+    results = {}
+    outputs = {}
+    variants = [("split", "c64"), ("split", "c128"), ("embed", "c64"), ("embed", "c128")]
+    if args.variants == "headline":
+        variants = variants[:1]
+    headline_leaf = None
+    for method, dtype in variants:
+        tdt = torch.complex64 if dtype == "c64" else torch.complex128
+        esz = 8 if dtype == "c64" else 16
+        plan = sf.Plan(n, b, coeffs_d, dtype=dtype, method=method, max_nrhs=nrhs,
+                       schedule=args.schedule)
+        info = plan.info()
+        x = torch.from_numpy(x_host).to(tdt).cuda()
+        y = torch.empty_like(x)
+        ws = plan.alloc_workspace(nrhs)
+        head = (method, dtype) == variants[0]
+        log(f"[{method} {dtype}] timing {args.steps} steps after {args.warmup} warmup")
+        ms, leaf = time_plan(plan, x, y, ws, args.steps, args.warmup, profile_leaf=head)
+        vbytes = nrhs * b * s * esz
+        dev_bytes = info["symbol_bytes"] + info["table_bytes"] + info["workspace_bytes"] + 2 * vbytes
+        results[f"{method}_{dtype}"] = dict(
+            matvecs_per_s=nrhs * 1e3 / ms, ms_per_matvec=ms, schedule=["auto", "breadth", "depth"][info["schedule"]],
+            device_bytes=dev_bytes, symbol_bytes=info["symbol_bytes"],
+            workspace_bytes=info["workspace_bytes"], vector_bytes=vbytes)
+        outputs[f"{method}_{dtype}"] = y.cpu().numpy().astype(np.complex128)
+        if head:
+            headline_leaf = (leaf, info, vbytes, ms)
+        plan.close()
+        del x, y, ws
+        torch.cuda.empty_cache()
+
+    (leaf_ms, leaf_cnt), info, vbytes, ms = headline_leaf
+    leaf_avg_s = leaf_ms / max(leaf_cnt, 1) * 1e-3
+    nbr = 2 ** (d - 1)  # leaf launch: every branch prefix of levels 1..d-1
+    leaf_alg_bytes = 2 * nbr * vbytes + info["symbol_bytes"]
+    achieved = leaf_alg_bytes / leaf_avg_s / 1e9
+    leaf_kernel = "sfft::k_leaf<float, 64, 3, 2>"
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(leaf_kernel),
+                    kernel=leaf_kernel, avg_launch_us=round(leaf_avg_s * 1e6, 2),
+                    launches=leaf_cnt, algorithmic_bytes_per_launch=int(leaf_alg_bytes))
+
+    copy_gbs = stream_copy_gbs()
+    roofline["stream_copy_gbs"] = round(copy_gbs, 1)
+    roofline["frac_of_stream_copy"] = round(achieved / copy_gbs, 4)
+
+    cpu = None
+    rel = {}
+    if not args.no_cpu_baseline:
+        log(f"CPU oracle baseline, ~{args.cpu_seconds:.0f} s")
+        ref, cpu = cpu_baseline(coeffs, x_host, args.cpu_seconds)
+        for k, v in outputs.items():
+            rel[k] = wl.relative_l2(v, ref)
+
+    head = results["split_c64"]
+    emb = results.get("embed_c64")
+    line = {
+        "metric": METRIC,
+        "value": round(head["matvecs_per_s"], 2),
+        "unit": "matvecs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_matvec"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64",
+        "data": "synthetic",
+        "config": {"workload": "green-64^3-b3-k0.7", "grid": list(n), "b": b, "nrhs": nrhs,
+                   "method": "split", "schedule": head["schedule"],
+                   "kernel": "3x3 Green blocks exp(ik|r|)/|r| (I - rr^T), k=0.7, self 2I"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "variants": {k: {kk: (round(vv, 6) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                     for k, v in results.items()},
+        "speedup_vs_embed": {dt: round(results[f"split_{dt}"]["matvecs_per_s"] /
+                                       results[f"embed_{dt}"]["matvecs_per_s"], 3)
+                             for dt in ("c64", "c128") if f"embed_{dt}" in results},
+        "device_bytes_ratio_embed_over_split": {
+            dt: round(results[f"embed_{dt}"]["device_bytes"] / results[f"split_{dt}"]["device_bytes"], 4)
+            for dt in ("c64", "c128") if f"embed_{dt}" in results},
+        "rel_l2_vs_fp64_oracle": {k: float(f"{v:.3e}") for k, v in rel.items()},
+    }
+    if emb is None:
+        line.pop("speedup_vs_embed")
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -136,6 +136,22 @@ sfft_status sfft_apply_multi(int nprob, const sfft_plan* plans, const void* cons
                              void* stream);
 
 sfft_status sfft_plan_info(sfft_plan plan, sfft_info* info);
+
+/* Kernel classes for the profiling hooks. */
+typedef enum {
+  SFFT_KIND_FORWARD = 0, /* FWD2 passes: FFT along a level + phase split */
+  SFFT_KIND_LEAF = 1,    /* last level: FFT, block product, iFFT, merge */
+  SFFT_KIND_INVERSE = 2, /* INV2 passes: iFFT along a level + merge */
+  SFFT_KIND_COPY = 3     /* embedding baseline's pad and projection */
+} sfft_kernel_kind;
+
+/* Bracket every later launch of the kinds set in mask (bit k = kind k) with a
+ * pair of HIP events recorded on the apply stream; mask 0 stops recording.
+ * Not for concurrent applies of one plan. */
+sfft_status sfft_profile_enable(sfft_plan plan, unsigned mask);
+/* Waits for the recorded events of one kind and returns their summed
+ * duration in milliseconds and the launch count; reset != 0 clears them. */
+sfft_status sfft_profile_read(sfft_plan plan, int kind, double* total_ms, int64_t* launches, int reset);
 sfft_status sfft_plan_destroy(sfft_plan plan);
 
 const char* sfft_status_string(sfft_status s);

@@ -25,8 +25,9 @@ PARITY_NONE, PARITY_EVEN, PARITY_ODD = 0, 1, 2
 EXPORTS = [
     "sfft_plan_create", "sfft_workspace_size", "sfft_apply", "sfft_workspace_size_multi",
     "sfft_apply_multi", "sfft_plan_info", "sfft_plan_destroy", "sfft_status_string",
-    "sfft_last_error", "sfft_length_supported",
+    "sfft_last_error", "sfft_length_supported", "sfft_profile_enable", "sfft_profile_read",
 ]
+KIND_FORWARD, KIND_LEAF, KIND_INVERSE, KIND_COPY = range(4)
 
 
 class SfftInfo(C.Structure):
@@ -46,7 +47,7 @@ class SfftError(RuntimeError):
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2406_17981_amd.build`")
+        raise ImportError(f"{LIB_PATH} is not built; run `python paper_2406_17981_amd/build.py`")
     lib = C.CDLL(LIB_PATH)
     vp, i64, sz = C.c_void_p, C.c_int64, C.c_size_t
     P64 = C.POINTER(C.c_int64)
@@ -64,6 +65,8 @@ def _load():
     lib.sfft_last_error.argtypes = []
     lib.sfft_last_error.restype = C.c_char_p
     lib.sfft_length_supported.argtypes = [i64]
+    lib.sfft_profile_enable.argtypes = [vp, C.c_uint]
+    lib.sfft_profile_read.argtypes = [vp, C.c_int, C.POINTER(C.c_double), P64, C.c_int]
     for name in EXPORTS:
         fn = getattr(lib, name)
         if fn.restype is C.c_int or fn.restype is None:

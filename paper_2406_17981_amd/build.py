@@ -1,6 +1,8 @@
 """Build libsfft.so (HIP kernels, runtime and C ABI) for gfx950, in-tree.
 
-    python -m paper_2406_17981_amd.build [-j N]
+    python paper_2406_17981_amd/build.py [-j N]
+
+(run as a script: importing the package would load the library it builds)
 
 Every call recompiles every source: one object per pencil length listed in
 csrc/lengths.def (kernels_len.hip with -DSFFT_LEN=<L>), the runtime, and a

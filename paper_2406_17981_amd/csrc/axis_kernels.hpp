@@ -22,6 +22,8 @@
 // global loads and stores are linear.
 #pragma once
 
+#include <type_traits>
+
 #include "fft_engine.hpp"
 
 namespace sfft {
@@ -47,7 +49,7 @@ struct PassArgs {
 };
 
 // Launch geometry per length.
-template <int L> struct Geo {
+template <typename Real, int L> struct Geo {
   using Sh = Shape<L>;
   static constexpr int T = Sh::T;
   static constexpr int E = Sh::E;
@@ -55,9 +57,29 @@ template <int L> struct Geo {
   static constexpr int W = NT / T;                     // strided tile width (pencils)
   static constexpr int P = NT / T;                     // contiguous tile (pencils)
   static constexpr int LP = L + 1;                     // padded LDS row
-  static constexpr int PL = (128 / T) > 0 ? (128 / T) : 1;  // leaf tile (pencils)
-  static constexpr int NTL = PL * T;                   // leaf threads
+  // leaf kernel: its own radix plan (FP64 lanes hold fewer entries), tile of
+  // PL pencils, NTL threads
+  using LSh = typename std::conditional<sizeof(Real) == 4 && Shape<L>::E <= 8, Shape<L>, LeafShape<L>>::type;
+  static constexpr int LT = LSh::T;
+  static constexpr int LE = LSh::E;
+  static constexpr int PL = (128 / LT) > 0 ? (128 / LT) : 1;
+  static constexpr int NTL = PL * LT;
+  static constexpr bool WS = (64 % T) == 0;    // contiguous pass: pencil inside one wavefront
+  static constexpr bool LWS = (64 % LT) == 0;  // leaf: pencil inside one wavefront
 };
+
+// Position of symbol entry (block component ab, home index m, lane) inside one
+// (branch, parity, tile) block of B*B*E*NT entries. With E even, entries m and
+// m+1 of a lane are adjacent so a lane reads them with one 16-byte (c64) or
+// 32-byte (c128) load and a wavefront's load is one contiguous run.
+__host__ __device__ inline int64_t sym_offset(int ab, int m, int lane, int E, int NT) {
+  if (E % 2 == 0) return ((int64_t)(ab * (E / 2) + m / 2) * NT + lane) * 2 + (m & 1);
+  return (int64_t)(ab * E + m) * NT + lane;
+}
+
+template <typename C> struct PairOf;
+template <> struct PairOf<float2> { using type = float4; };
+template <> struct PairOf<double2> { using type = double4; };
 
 // ---------------------------------------------------------------------------
 // Strided axis: tile of L rows x W pencils, lane (c, t) = (tid % W, tid / W).
@@ -65,7 +87,7 @@ template <int L> struct Geo {
 template <typename Real, int L, int MODE>
 __global__ void __launch_bounds__(256) k_strided(PassArgs a) {
   using C = cx<Real>;
-  using G = Geo<L>;
+  using G = Geo<Real, L>;
   using Sh = typename G::Sh;
   constexpr int T = G::T, E = G::E, W = G::W;
   __shared__ C lds[L * W];
@@ -167,7 +189,7 @@ __device__ __forceinline__ void store_home(C* dst, C* lds, const C (&h)[E], int 
 template <typename Real, int L, int MODE>
 __global__ void __launch_bounds__(256) k_contig(PassArgs a) {
   using C = cx<Real>;
-  using G = Geo<L>;
+  using G = Geo<Real, L>;
   using Sh = typename G::Sh;
   constexpr int T = G::T, E = G::E, P = G::P, LP = G::LP, NT = G::NT;
   __shared__ C lds[P * LP];
@@ -190,18 +212,18 @@ __global__ void __launch_bounds__(256) k_contig(PassArgs a) {
       C w[E];
 #pragma unroll
       for (int m = 0; m < E; ++m) w[m] = h[m];
-      fft_pencil<-1, Sh>(w, lp, 1, t, tw);
+      fft_pencil<-1, Sh, G::WS>(w, lp, 1, t, tw);
       store_home<C, L, T, E, P, NT>((C*)a.out + q * a.out_bs + p0 * L, lds, w, g, t, nh, tid);
     }
     if (a.out1) {
       C w[E];
 #pragma unroll
       for (int m = 0; m < E; ++m) w[m] = a.use_phase ? cmul(h[m], tw[t + T * m]) : h[m];
-      fft_pencil<-1, Sh>(w, lp, 1, t, tw);
+      fft_pencil<-1, Sh, G::WS>(w, lp, 1, t, tw);
       store_home<C, L, T, E, P, NT>((C*)a.out1 + q * a.out_bs + p0 * L, lds, w, g, t, nh, tid);
     }
   } else {
-    fft_pencil<+1, Sh>(h, lp, 1, t, tw);
+    fft_pencil<+1, Sh, G::WS>(h, lp, 1, t, tw);
     if (a.in1) {
       tile_load<C, L, P, NT>(lds, (const C*)a.in1 + q * a.in_bs + p0 * L, nh, tid);
       __syncthreads();
@@ -209,7 +231,7 @@ __global__ void __launch_bounds__(256) k_contig(PassArgs a) {
 #pragma unroll
       for (int m = 0; m < E; ++m) w[m] = lp[t + T * m];
       __syncthreads();
-      fft_pencil<+1, Sh>(w, lp, 1, t, tw);
+      fft_pencil<+1, Sh, G::WS>(w, lp, 1, t, tw);
 #pragma unroll
       for (int m = 0; m < E; ++m) h[m] = cadd(h[m], a.use_phase ? cmulc(w[m], tw[t + T * m]) : w[m]);
     }
@@ -227,11 +249,12 @@ __global__ void __launch_bounds__(256) k_contig(PassArgs a) {
 // apart: they land on the same XCD and share its L2 copy of the symbols.
 // ---------------------------------------------------------------------------
 template <typename Real, int L, int B, int NPAR>
-__global__ void __launch_bounds__(Geo<L>::NTL) k_leaf(PassArgs a) {
+__global__ void __launch_bounds__((Geo<Real, L>::NTL)) k_leaf(PassArgs a) {
   using C = cx<Real>;
-  using G = Geo<L>;
-  using Sh = typename G::Sh;
-  constexpr int T = G::T, E = G::E, P = G::PL, LP = G::LP, NT = G::NTL;
+  using G = Geo<Real, L>;
+  using Sh = typename G::LSh;
+  using C2 = typename PairOf<C>::type;
+  constexpr int T = G::LT, E = G::LE, P = G::PL, LP = G::LP, NT = G::NTL;
   __shared__ C home[B * P * LP];
   __shared__ C scr[P * LP];
   const int tid = threadIdx.x;
@@ -274,23 +297,39 @@ __global__ void __launch_bounds__(Geo<L>::NTL) k_leaf(PassArgs a) {
         w[c][m] = (p == 1) ? cmul(v, tw[t + T * m]) : v;
       }
 #pragma unroll
-    for (int c = 0; c < B; ++c) fft_pencil<-1, Sh>(w[c], lp, 1, t, tw);
+    for (int c = 0; c < B; ++c) fft_pencil<-1, Sh, G::LWS>(w[c], lp, 1, t, tw);
+    // mulBrn: per point, the b x b block of T[bId] times the b components
     const C* sp = (const C*)a.sym + q * a.sym_bs + ((int64_t)p * a.ntiles + tile) * (B * B * E * NT);
+    constexpr int MS = (E % 2 == 0) ? 2 : 1;  // entries per symbol load
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
-      C o[B];
+    for (int m0 = 0; m0 < E; m0 += MS) {
+      C sm[MS][B * B];
 #pragma unroll
-      for (int ar = 0; ar < B; ++ar) {
-        C s = czero<C>();
-#pragma unroll
-        for (int c = 0; c < B; ++c) s = cadd(s, cmul(sp[((ar * B + c) * E + m) * NT + tid], w[c][m]));
-        o[ar] = s;
+      for (int ab = 0; ab < B * B; ++ab) {
+        if constexpr (MS == 2) {
+          const C2 v = *(const C2*)(sp + sym_offset(ab, m0, tid, E, NT));
+          sm[0][ab] = mk<C>(v.x, v.y);
+          sm[1][ab] = mk<C>(v.z, v.w);
+        } else {
+          sm[0][ab] = sp[sym_offset(ab, m0, tid, E, NT)];
+        }
       }
 #pragma unroll
-      for (int ar = 0; ar < B; ++ar) w[ar][m] = o[ar];
+      for (int j = 0; j < MS; ++j) {
+        C o[B];
+#pragma unroll
+        for (int ar = 0; ar < B; ++ar) {
+          C u = czero<C>();
+#pragma unroll
+          for (int c = 0; c < B; ++c) u = cadd(u, cmul(sm[j][ar * B + c], w[c][m0 + j]));
+          o[ar] = u;
+        }
+#pragma unroll
+        for (int ar = 0; ar < B; ++ar) w[ar][m0 + j] = o[ar];
+      }
     }
 #pragma unroll
-    for (int c = 0; c < B; ++c) fft_pencil<+1, Sh>(w[c], lp, 1, t, tw);
+    for (int c = 0; c < B; ++c) fft_pencil<+1, Sh, G::LWS>(w[c], lp, 1, t, tw);
 #pragma unroll
     for (int c = 0; c < B; ++c)
 #pragma unroll
@@ -315,14 +354,15 @@ __global__ void __launch_bounds__(Geo<L>::NTL) k_leaf(PassArgs a) {
 typedef hipError_t (*pass_fn)(const PassArgs&, hipStream_t);
 
 struct AxisOps {
-  int L, T, E, W, P, PL, NTL;
+  int L, T, E, W, P;   // strided / contiguous passes
+  int LT, LE, PL, NTL; // leaf: lanes per pencil, entries per lane, pencils per tile, threads
   pass_fn strided[2];   // [0] FWD2, [1] INV2
   pass_fn contig[2];
   pass_fn leaf[5][3];   // [B][NPAR], null where not built
 };
 
 template <typename Real, int L, int MODE> hipError_t launch_strided(const PassArgs& a, hipStream_t s) {
-  using G = Geo<L>;
+  using G = Geo<Real, L>;
   const int64_t cols = a.outer * a.inner;
   const int64_t blocks = a.nq * ((cols + G::W - 1) / G::W);
   if (blocks <= 0) return hipSuccess;
@@ -331,7 +371,7 @@ template <typename Real, int L, int MODE> hipError_t launch_strided(const PassAr
 }
 
 template <typename Real, int L, int MODE> hipError_t launch_contig(const PassArgs& a, hipStream_t s) {
-  using G = Geo<L>;
+  using G = Geo<Real, L>;
   const int64_t blocks = a.nq * ((a.outer + G::P - 1) / G::P);
   if (blocks <= 0) return hipSuccess;
   hipLaunchKernelGGL((k_contig<Real, L, MODE>), dim3((unsigned)blocks), dim3(G::NT), 0, s, a);
@@ -339,7 +379,7 @@ template <typename Real, int L, int MODE> hipError_t launch_contig(const PassArg
 }
 
 template <typename Real, int L, int B, int NPAR> hipError_t launch_leaf(const PassArgs& a, hipStream_t s) {
-  using G = Geo<L>;
+  using G = Geo<Real, L>;
   const int64_t blocks = a.nq * ((a.ntiles + 7) / 8) * a.nrhs * 8;
   if (blocks <= 0) return hipSuccess;
   hipLaunchKernelGGL((k_leaf<Real, L, B, NPAR>), dim3((unsigned)blocks), dim3(G::NTL), 0, s, a);
@@ -347,9 +387,9 @@ template <typename Real, int L, int B, int NPAR> hipError_t launch_leaf(const Pa
 }
 
 template <typename Real, int L> const AxisOps* make_ops() {
-  using G = Geo<L>;
+  using G = Geo<Real, L>;
   static const AxisOps ops = {
-      L, G::T, G::E, G::W, G::P, G::PL, G::NTL,
+      L, G::T, G::E, G::W, G::P, G::LT, G::LE, G::PL, G::NTL,
       {launch_strided<Real, L, 0>, launch_strided<Real, L, 1>},
       {launch_contig<Real, L, 0>, launch_contig<Real, L, 1>},
       {{nullptr, nullptr, nullptr},

@@ -208,16 +208,55 @@ SFFT_SHAPE(1024, 64, 16, 8, 8)
 SFFT_SHAPE(2048, 128, 16, 8, 16)
 #undef SFFT_SHAPE
 
+// Radix plans of the leaf kernel, which holds b components and an accumulator
+// per lane: fewer entries per lane (more lanes per pencil) where that keeps
+// the first and last stages in registers.
+template <int L> struct LeafShape : Shape<L> {};
+#define SFFT_LEAF_SHAPE(LEN, TT, ...)                                          \
+  template <> struct LeafShape<LEN> {                                          \
+    static constexpr int L = LEN;                                              \
+    static constexpr int T = TT;                                               \
+    static constexpr int E = LEN / TT;                                         \
+    static constexpr int rads[] = {__VA_ARGS__};                               \
+    static constexpr int S = sizeof(rads) / sizeof(int);                       \
+    static constexpr int rad(int s) { return rads[s]; }                        \
+    static constexpr int ns(int s) { return s == 0 ? 1 : ns(s - 1) * rads[s - 1]; } \
+  };
+SFFT_LEAF_SHAPE(32, 8, 4, 2, 4)
+SFFT_LEAF_SHAPE(48, 8, 2, 4, 2, 3)
+SFFT_LEAF_SHAPE(64, 16, 4, 4, 4)
+SFFT_LEAF_SHAPE(96, 16, 2, 4, 4, 3)
+SFFT_LEAF_SHAPE(128, 32, 4, 8, 4)
+SFFT_LEAF_SHAPE(256, 64, 4, 16, 4)
+SFFT_LEAF_SHAPE(384, 64, 2, 4, 4, 4, 3)
+SFFT_LEAF_SHAPE(512, 64, 8, 8, 8)
+SFFT_LEAF_SHAPE(1024, 128, 8, 8, 4, 4)
+SFFT_LEAF_SHAPE(2048, 256, 8, 8, 4, 8)
+#undef SFFT_LEAF_SHAPE
+
 template <typename Sh> constexpr bool shape_ok() {
   int p = 1;
   for (int s = 0; s < Sh::S; ++s) p *= Sh::rads[s];
   return p == Sh::L && Sh::L % Sh::T == 0;
 }
 
+// LDS exchange fence. WS (wave sync): every lane of a pencil sits in one
+// wavefront and the pencil's LDS row is private to those lanes, so ordering
+// the wavefront's own LDS traffic is enough; otherwise a workgroup barrier.
+template <bool WS> __device__ __forceinline__ void xsync() {
+  if constexpr (WS) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
 // One stage (and, recursively, the following ones) of a pencil transform.
 // lds: this pencil's LDS row, element k at lds[k * kst]. All lanes of the
-// workgroup must call this together (it contains workgroup barriers).
-template <typename C, typename Sh, int DIR, int s>
+// workgroup (WS = false) or of the wavefront (WS = true) call this together.
+template <typename C, typename Sh, int DIR, int s, bool WS>
 __device__ __forceinline__ void fft_stage(C (&home)[Sh::E], C* lds, int kst, int t, const C* tw) {
   constexpr int L = Sh::L, T = Sh::T, S = Sh::S;
   constexpr int R = Sh::rad(s);
@@ -232,7 +271,7 @@ __device__ __forceinline__ void fft_stage(C (&home)[Sh::E], C* lds, int kst, int
   if constexpr (s == 0 && !FIRST_REG) {
 #pragma unroll
     for (int m = 0; m < Sh::E; ++m) lds[(t + T * m) * kst] = home[m];
-    __syncthreads();
+    xsync<WS>();
   }
 
   C v[PER][R];
@@ -263,9 +302,9 @@ __device__ __forceinline__ void fft_stage(C (&home)[Sh::E], C* lds, int kst, int
     for (int u = 0; u < PER; ++u)
 #pragma unroll
       for (int q = 0; q < R; ++q) home[u + q * (NB / T)] = v[u][q];
-    if constexpr (!FIRST_REG) __syncthreads();  // LDS reads of this stage done before reuse
+    if constexpr (!FIRST_REG) xsync<WS>();  // LDS reads of this stage done before reuse
   } else {
-    if constexpr (!FIRST_REG) __syncthreads();  // every lane has read this stage's inputs
+    if constexpr (!FIRST_REG) xsync<WS>();  // every lane has read this stage's inputs
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int j = t + T * u;
@@ -276,21 +315,22 @@ __device__ __forceinline__ void fft_stage(C (&home)[Sh::E], C* lds, int kst, int
         for (int q = 0; q < R; ++q) lds[(base + q * Ns) * kst] = v[u][q];
       }
     }
-    __syncthreads();
+    xsync<WS>();
     if constexpr (s == S - 1) {
 #pragma unroll
       for (int m = 0; m < Sh::E; ++m) home[m] = lds[(t + T * m) * kst];
-      __syncthreads();
+      xsync<WS>();
     }
   }
-  if constexpr (s + 1 < S) fft_stage<C, Sh, DIR, s + 1>(home, lds, kst, t, tw);
+  if constexpr (s + 1 < S) fft_stage<C, Sh, DIR, s + 1, WS>(home, lds, kst, t, tw);
 }
 
 // Unnormalised DFT of one pencil (DIR = -1 forward, +1 inverse).
-template <int DIR, typename Sh, typename C>
+template <int DIR, typename Sh, bool WS = false, typename C>
 __device__ __forceinline__ void fft_pencil(C (&home)[Sh::E], C* lds, int kst, int t, const C* tw) {
   static_assert(shape_ok<Sh>(), "bad radix plan");
-  fft_stage<C, Sh, DIR, 0>(home, lds, kst, t, tw);
+  static_assert(!WS || (64 % Sh::T) == 0, "wave sync needs whole pencils per wavefront");
+  fft_stage<C, Sh, DIR, 0, WS>(home, lds, kst, t, tw);
 }
 
 }  // namespace sfft

@@ -124,7 +124,7 @@ __global__ void k_scatter_split(const double2* __restrict__ full, C* __restrict_
     const int64_t Q = pq >> 1;
     const int64_t pencil = tile * P + tid / T;
     const int64_t k = tid % T + (int64_t)T * m;
-    const int64_t dst = (((pq * ntiles + tile) * B * B + ab) * E + m) * NT + tid;
+    const int64_t dst = (pq * ntiles + tile) * B * B * E * NT + sfft::sym_offset(ab, m, tid, E, NT);
     if (pencil >= npen) {
       sym[dst] = sfft::mk<C>(0, 0);
       continue;
@@ -157,7 +157,7 @@ __global__ void k_scatter_embed(const double2* __restrict__ full, C* __restrict_
     const int64_t tile = idx / ((int64_t)NT * E);
     const int64_t pencil = tile * P + tid / T;
     const int64_t k = tid % T + (int64_t)T * m;
-    const int64_t dst = ((tile * B * B + ab) * E + m) * NT + tid;
+    const int64_t dst = tile * B * B * E * NT + sfft::sym_offset(ab, m, tid, E, NT);
     if (pencil >= npen) {
       sym[dst] = sfft::mk<C>(0, 0);
       continue;
@@ -236,8 +236,21 @@ struct sfft_plan_s {
   std::mutex pool_mu;
   void* pool = nullptr;
   size_t pool_bytes = 0;
+  // profiling hooks: event pairs around launches of the kinds in prof_mask
+  unsigned prof_mask = 0;
+  struct Rec {
+    int kind;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> prof_recs;
+  std::vector<hipEvent_t> prof_free;
 
   ~sfft_plan_s() {
+    for (auto& r : prof_recs) {
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+    for (auto e : prof_free) (void)hipEventDestroy(e);
     for (int l = 0; l < kMaxD; ++l)
       if (tw[l]) (void)hipFree(tw[l]);
     if (sym) (void)hipFree(sym);
@@ -276,8 +289,44 @@ PassArgs base_args(const sfft_plan_s* p, int l, int64_t nv) {
   return a;
 }
 
+hipEvent_t take_event(sfft_plan_s* p) {
+  if (!p->prof_free.empty()) {
+    hipEvent_t e = p->prof_free.back();
+    p->prof_free.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// RAII bracket: records an event pair around one launch when its kind is profiled.
+struct ProfScope {
+  sfft_plan_s* p;
+  hipStream_t st;
+  int kind;
+  hipEvent_t a = nullptr, b = nullptr;
+  ProfScope(const sfft_plan_s* pc, int k, hipStream_t s) : p(const_cast<sfft_plan_s*>(pc)), st(s), kind(k) {
+    if (p->prof_mask & (1u << k)) {
+      a = take_event(p);
+      b = take_event(p);
+      if (a && b) (void)hipEventRecord(a, st);
+    }
+  }
+  ~ProfScope() {
+    if (a && b) {
+      (void)hipEventRecord(b, st);
+      p->prof_recs.push_back({kind, a, b});
+    } else {
+      if (a) p->prof_free.push_back(a);
+      if (b) p->prof_free.push_back(b);
+    }
+  }
+};
+
 sfft_status run_pass(const sfft_plan_s* p, int l, int mode, const PassArgs& a, hipStream_t st) {
   const AxisOps* o = p->ops[l];
+  ProfScope ps(p, mode == 0 ? SFFT_KIND_FORWARD : SFFT_KIND_INVERSE, st);
   hipError_t e = (l == p->d - 1) ? o->contig[mode](a, st) : o->strided[mode](a, st);
   if (e != hipSuccess) return hip_fail(e, "axis pass launch");
   return SFFT_OK;
@@ -303,6 +352,7 @@ sfft_status run_leaf(const sfft_plan_s* p, const void* in, void* out, int64_t in
   const int npar = p->method == SFFT_SPLIT ? 2 : 1;
   sfft::pass_fn f = o->leaf[p->b][npar];
   if (!f) return fail(SFFT_UNSUPPORTED, "no leaf kernel for this block size");
+  ProfScope ps(p, SFFT_KIND_LEAF, st);
   hipError_t e = f(a, st);
   if (e != hipSuccess) return hip_fail(e, "leaf launch");
   return SFFT_OK;
@@ -390,11 +440,14 @@ sfft_status embed_apply(const sfft_plan_s* p, const void* x, void* y, int64_t nr
   dm.d = d;
   for (int l = 0; l < d; ++l) dm.n[l] = p->n[l];
   const int64_t big = nv * p->s * (int64_t(1) << d);
-  if (p->dtype == SFFT_C64)
+  {
+    ProfScope ps(p, SFFT_KIND_COPY, st);
+    if (p->dtype == SFFT_C64)
     hipLaunchKernelGGL(k_pad<float2>, dim3(grid_for(big)), dim3(256), 0, st, (const float2*)x, (float2*)ws, dm, big);
   else
     hipLaunchKernelGGL(k_pad<double2>, dim3(grid_for(big)), dim3(256), 0, st, (const double2*)x, (double2*)ws, dm,
                        big);
+  }
   HIP_TRY(hipGetLastError(), "pad launch");
   sfft_status s;
   for (int l = 0; l < d - 1; ++l) {
@@ -412,12 +465,15 @@ sfft_status embed_apply(const sfft_plan_s* p, const void* x, void* y, int64_t nr
     if ((s = run_pass(p, l, 1, a, st)) != SFFT_OK) return s;
   }
   const int64_t small = nv * p->s;
-  if (p->dtype == SFFT_C64)
+  {
+    ProfScope ps(p, SFFT_KIND_COPY, st);
+    if (p->dtype == SFFT_C64)
     hipLaunchKernelGGL(k_project<float2>, dim3(grid_for(small)), dim3(256), 0, st, (const float2*)ws, (float2*)y, dm,
                        small);
   else
     hipLaunchKernelGGL(k_project<double2>, dim3(grid_for(small)), dim3(256), 0, st, (const double2*)ws, (double2*)y,
                        dm, small);
+  }
   HIP_TRY(hipGetLastError(), "project launch");
   return SFFT_OK;
 }
@@ -491,22 +547,22 @@ sfft_status build_symbols(sfft_plan_s* p, const double2* coeffs, hipStream_t st)
     }
     if ((s = fft64_inplace(dm, tmp, tw64, st)) != SFFT_OK) break;
     if (p->method == SFFT_SPLIT) {
-      const int64_t total = (int64_t(1) << d) * p->ntiles * lo->E * lo->NTL;
+      const int64_t total = (int64_t(1) << d) * p->ntiles * lo->LE * lo->NTL;
       if (p->dtype == SFFT_C64)
         hipLaunchKernelGGL(k_scatter_split<float2>, dim3(grid_for(total)), dim3(256), 0, st, tmp, (float2*)p->sym,
-                           ab, p->b, dm, lo->T, lo->E, lo->NTL, lo->PL, p->ntiles, p->npen, scale, total);
+                           ab, p->b, dm, lo->LT, lo->LE, lo->NTL, lo->PL, p->ntiles, p->npen, scale, total);
       else
         hipLaunchKernelGGL(k_scatter_split<double2>, dim3(grid_for(total)), dim3(256), 0, st, tmp,
-                           (double2*)p->sym, ab, p->b, dm, lo->T, lo->E, lo->NTL, lo->PL, p->ntiles, p->npen,
+                           (double2*)p->sym, ab, p->b, dm, lo->LT, lo->LE, lo->NTL, lo->PL, p->ntiles, p->npen,
                            scale, total);
     } else {
-      const int64_t total = p->ntiles * lo->E * lo->NTL;
+      const int64_t total = p->ntiles * lo->LE * lo->NTL;
       if (p->dtype == SFFT_C64)
         hipLaunchKernelGGL(k_scatter_embed<float2>, dim3(grid_for(total)), dim3(256), 0, st, tmp, (float2*)p->sym,
-                           ab, p->b, lo->T, lo->E, lo->NTL, lo->PL, p->ntiles, p->npen, p->L[d - 1], scale, total);
+                           ab, p->b, lo->LT, lo->LE, lo->NTL, lo->PL, p->ntiles, p->npen, p->L[d - 1], scale, total);
       else
         hipLaunchKernelGGL(k_scatter_embed<double2>, dim3(grid_for(total)), dim3(256), 0, st, tmp,
-                           (double2*)p->sym, ab, p->b, lo->T, lo->E, lo->NTL, lo->PL, p->ntiles, p->npen,
+                           (double2*)p->sym, ab, p->b, lo->LT, lo->LE, lo->NTL, lo->PL, p->ntiles, p->npen,
                            p->L[d - 1], scale, total);
     }
     e = hipGetLastError();
@@ -636,7 +692,7 @@ sfft_status sfft_plan_create(sfft_plan* out, int d, const int64_t* n, int b, con
   for (int l = 0; l < d - 1; ++l) p->npen *= p->L[l];
   p->ntiles = (p->npen + lo->PL - 1) / lo->PL;
   const int npar = method == SFFT_SPLIT ? 2 : 1;
-  p->sym_bs = (int64_t)npar * p->ntiles * b * b * lo->E * lo->NTL;
+  p->sym_bs = (int64_t)npar * p->ntiles * b * b * lo->LE * lo->NTL;
   const int64_t nbranch = method == SFFT_SPLIT ? (int64_t(1) << (d - 1)) : 1;
   p->sym_bytes = (size_t)(nbranch * p->sym_bs) * p->esz;
 
@@ -711,6 +767,41 @@ sfft_status sfft_plan_info(sfft_plan plan, sfft_info* info) {
   info->table_bytes = plan->table_bytes;
   info->workspace_bytes = workspace_elems(plan, plan->max_nrhs) * plan->esz;
   info->vector_elems = plan->b * plan->s;
+  return SFFT_OK;
+}
+
+sfft_status sfft_profile_enable(sfft_plan plan, unsigned mask) {
+  if (!plan) return fail(SFFT_INVALID_ARG, "plan is null");
+  plan->prof_mask = mask & 0xFu;
+  return SFFT_OK;
+}
+
+sfft_status sfft_profile_read(sfft_plan plan, int kind, double* total_ms, int64_t* launches, int reset) {
+  if (!plan || !total_ms || !launches) return fail(SFFT_INVALID_ARG, "null argument");
+  double tot = 0.0;
+  int64_t cnt = 0;
+  for (auto& r : plan->prof_recs) {
+    if (r.kind != kind) continue;
+    HIP_TRY(hipEventSynchronize(r.b), "profile event sync");
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, r.a, r.b), "profile elapsed time");
+    tot += ms;
+    ++cnt;
+  }
+  *total_ms = tot;
+  *launches = cnt;
+  if (reset) {
+    std::vector<sfft_plan_s::Rec> keep;
+    for (auto& r : plan->prof_recs) {
+      if (r.kind == kind) {
+        plan->prof_free.push_back(r.a);
+        plan->prof_free.push_back(r.b);
+      } else {
+        keep.push_back(r);
+      }
+    }
+    plan->prof_recs.swap(keep);
+  }
   return SFFT_OK;
 }
 

@@ -133,6 +133,26 @@ class Plan:
 
     __call__ = apply
 
+    # -- profiling hooks -------------------------------------------------
+    def profile(self, kinds=("leaf",)):
+        """Bracket later launches of the given kernel kinds with HIP events."""
+        names = {"forward": N.KIND_FORWARD, "leaf": N.KIND_LEAF, "inverse": N.KIND_INVERSE,
+                 "copy": N.KIND_COPY}
+        mask = 0
+        for k in kinds:
+            mask |= 1 << names[k]
+        N.check(N.lib.sfft_profile_enable(self.handle, mask), "sfft_profile_enable")
+
+    def profile_read(self, kind="leaf", reset=True):
+        """(total milliseconds, launches) of the recorded launches of one kind."""
+        names = {"forward": N.KIND_FORWARD, "leaf": N.KIND_LEAF, "inverse": N.KIND_INVERSE,
+                 "copy": N.KIND_COPY}
+        ms = C.c_double()
+        cnt = C.c_int64()
+        N.check(N.lib.sfft_profile_read(self.handle, names[kind], C.byref(ms), C.byref(cnt), int(reset)),
+                "sfft_profile_read")
+        return float(ms.value), int(cnt.value)
+
     def close(self):
         if getattr(self, "_h", None) is not None:
             N.lib.sfft_plan_destroy(self._h)
