@@ -234,29 +234,32 @@ def main():
 
     results = {}
     outputs = {}
-    variants = [("split", "c64"), ("split", "c128"), ("embed", "c64"), ("embed", "c128")]
+    variants = [("split", "c64"), ("split", "c128"), ("embed", "c64"), ("embed", "c128"),
+                ("split_mirrored", "c64"), ("split_mirrored", "c128")]
     if args.variants == "headline":
         variants = variants[:1]
     headline_leaf = None
-    for method, dtype in variants:
+    for vmethod, dtype in variants:
+        method = "split" if vmethod.startswith("split") else "embed"
+        parity = wl.green_parity(3) if vmethod == "split_mirrored" else None
         tdt = torch.complex64 if dtype == "c64" else torch.complex128
         esz = 8 if dtype == "c64" else 16
         plan = sf.Plan(n, b, coeffs_d, dtype=dtype, method=method, max_nrhs=nrhs,
-                       schedule=args.schedule)
+                       schedule=args.schedule, parity=parity)
         info = plan.info()
         x = torch.from_numpy(x_host).to(tdt).cuda()
         y = torch.empty_like(x)
         ws = plan.alloc_workspace(nrhs)
-        head = (method, dtype) == variants[0]
-        log(f"[{method} {dtype}] timing {args.steps} steps after {args.warmup} warmup")
+        head = (vmethod, dtype) == variants[0]
+        log(f"[{vmethod} {dtype}] timing {args.steps} steps after {args.warmup} warmup")
         ms, leaf = time_plan(plan, x, y, ws, args.steps, args.warmup, profile_leaf=head)
         vbytes = nrhs * b * s * esz
         dev_bytes = info["symbol_bytes"] + info["table_bytes"] + info["workspace_bytes"] + 2 * vbytes
-        results[f"{method}_{dtype}"] = dict(
+        results[f"{vmethod}_{dtype}"] = dict(
             matvecs_per_s=nrhs * 1e3 / ms, ms_per_matvec=ms, schedule=["auto", "breadth", "depth"][info["schedule"]],
             device_bytes=dev_bytes, symbol_bytes=info["symbol_bytes"],
             workspace_bytes=info["workspace_bytes"], vector_bytes=vbytes)
-        outputs[f"{method}_{dtype}"] = y.cpu().numpy().astype(np.complex128)
+        outputs[f"{vmethod}_{dtype}"] = y.cpu().numpy().astype(np.complex128)
         if head:
             headline_leaf = (leaf, info, vbytes, ms)
         plan.close()

@@ -46,6 +46,17 @@ struct PassArgs {
   int64_t npen;      // pencils per component per right-hand side
   int64_t nrhs;
   int64_t ntiles;    // ceil(npen / P)
+  // LEAF with mirrored symbol storage (Section II.C): per component a
+  // (n_1+1) x ... x (n_d+1) array; along level l the first n_l/2+1 entries
+  // are the even bins 2j of the 2n_l lattice, the rest the odd bins 2j+1,
+  // j <= n_l/2; a bin m > n_l is read as bin 2n_l - m, negated once per
+  // level along which the component is odd.
+  int64_t q0;        // branch index of job 0 (its bits are the parities of levels 1..d-1)
+  int d;
+  int64_t mn[6];     // level sizes
+  int64_t mst[6];    // strides of the stored array
+  int64_t mcomp;     // stored entries per component
+  uint64_t odd_bits; // bit (ab*6 + l): component ab is odd along level l (b*b <= 9, d <= 6)
 };
 
 // Launch geometry per length.
@@ -248,7 +259,7 @@ __global__ void __launch_bounds__(256) k_contig(PassArgs a) {
 // Workgroups are numbered so that the right-hand sides of one tile are 8
 // apart: they land on the same XCD and share its L2 copy of the symbols.
 // ---------------------------------------------------------------------------
-template <typename Real, int L, int B, int NPAR>
+template <typename Real, int L, int B, int NPAR, bool MIR>
 __global__ void __launch_bounds__((Geo<Real, L>::NTL)) k_leaf(PassArgs a) {
   using C = cx<Real>;
   using G = Geo<Real, L>;
@@ -286,6 +297,28 @@ __global__ void __launch_bounds__((Geo<Real, L>::NTL)) k_leaf(PassArgs a) {
     for (int m = 0; m < E; ++m) acc[c][m] = czero<C>();
 
   C* lp = scr + g * LP;
+
+  // mirrored storage: this lane's pencil fixes the outer levels' stored index
+  // and which of them are read mirrored
+  int64_t mbase = 0;
+  uint32_t mbits = 0;
+  if constexpr (MIR) {
+    const int64_t Q = a.q0 + q;
+    int64_t rem = p0 + (g < nh ? g : 0);
+    for (int l = a.d - 2; l >= 0; --l) {
+      const int64_t n = a.mn[l];
+      const int64_t j = rem % n;
+      rem /= n;
+      const int pl = (int)((Q >> (a.d - 2 - l)) & 1);
+      int64_t jj = j;
+      if (2 * j + pl > n) {
+        jj = pl ? n - 1 - j : n - j;
+        mbits |= 1u << l;
+      }
+      mbase += (pl * (n / 2 + 1) + jj) * a.mst[l];
+    }
+  }
+
 #pragma unroll
   for (int p = 0; p < NPAR; ++p) {
     C w[B][E];
@@ -306,7 +339,20 @@ __global__ void __launch_bounds__((Geo<Real, L>::NTL)) k_leaf(PassArgs a) {
       C sm[MS][B * B];
 #pragma unroll
       for (int ab = 0; ab < B * B; ++ab) {
-        if constexpr (MS == 2) {
+        if constexpr (MIR) {
+          const int64_t n = L;
+          const int ld = a.d - 1;
+#pragma unroll
+          for (int j = 0; j < MS; ++j) {
+            const int64_t k = t + T * (m0 + j);
+            const bool mir = 2 * k + p > n;
+            const int64_t jj = mir ? (p ? n - 1 - k : n - k) : k;
+            const uint32_t bits = mbits | ((uint32_t)mir << ld);
+            const uint32_t odd = (uint32_t)(a.odd_bits >> (ab * 6)) & 0x3fu;
+            const C v = ((const C*)a.sym)[ab * a.mcomp + mbase + p * (n / 2 + 1) + jj];
+            sm[j][ab] = (__builtin_popcount(bits & odd) & 1) ? mk<C>(-v.x, -v.y) : v;
+          }
+        } else if constexpr (MS == 2) {
           const C2 v = *(const C2*)(sp + sym_offset(ab, m0, tid, E, NT));
           sm[0][ab] = mk<C>(v.x, v.y);
           sm[1][ab] = mk<C>(v.z, v.w);
@@ -359,6 +405,7 @@ struct AxisOps {
   pass_fn strided[2];   // [0] FWD2, [1] INV2
   pass_fn contig[2];
   pass_fn leaf[5][3];   // [B][NPAR], null where not built
+  pass_fn leaf_mirror[5];  // [B], NPAR = 2, mirrored symbol storage
 };
 
 template <typename Real, int L, int MODE> hipError_t launch_strided(const PassArgs& a, hipStream_t s) {
@@ -378,11 +425,12 @@ template <typename Real, int L, int MODE> hipError_t launch_contig(const PassArg
   return hipGetLastError();
 }
 
-template <typename Real, int L, int B, int NPAR> hipError_t launch_leaf(const PassArgs& a, hipStream_t s) {
+template <typename Real, int L, int B, int NPAR, bool MIR = false>
+hipError_t launch_leaf(const PassArgs& a, hipStream_t s) {
   using G = Geo<Real, L>;
   const int64_t blocks = a.nq * ((a.ntiles + 7) / 8) * a.nrhs * 8;
   if (blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_leaf<Real, L, B, NPAR>), dim3((unsigned)blocks), dim3(G::NTL), 0, s, a);
+  hipLaunchKernelGGL((k_leaf<Real, L, B, NPAR, MIR>), dim3((unsigned)blocks), dim3(G::NTL), 0, s, a);
   return hipGetLastError();
 }
 
@@ -397,6 +445,7 @@ template <typename Real, int L> const AxisOps* make_ops() {
        {nullptr, nullptr, nullptr},
        {nullptr, launch_leaf<Real, L, 3, 1>, launch_leaf<Real, L, 3, 2>},
        {nullptr, nullptr, nullptr}},
+      {nullptr, launch_leaf<Real, L, 1, 2, true>, nullptr, launch_leaf<Real, L, 3, 2, true>, nullptr},
   };
   return &ops;
 }

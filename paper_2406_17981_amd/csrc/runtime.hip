@@ -167,6 +167,29 @@ __global__ void k_scatter_embed(const double2* __restrict__ full, C* __restrict_
   }
 }
 
+// Mirrored storage of one FP64 symbol component (Section II.C): stored index
+// s_l in [0, n_l] along every level, s_l < n_l/2+1 holding the even bin
+// 2 s_l of the 2n_l lattice and the rest the odd bins 2 (s_l - n_l/2 - 1) + 1.
+template <typename C>
+__global__ void k_scatter_mirror(const double2* __restrict__ full, C* __restrict__ sym, int ab, Dims dm,
+                                 double scale, int64_t total) {
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    int64_t rem = idx, fidx = 0, fstride = 1;
+    for (int l = dm.d - 1; l >= 0; --l) {
+      const int64_t n = dm.n[l];
+      const int64_t sl = rem % (n + 1);
+      rem /= n + 1;
+      const int64_t m0 = n / 2 + 1;
+      const int64_t M = sl < m0 ? 2 * sl : 2 * (sl - m0) + 1;
+      fidx += M * fstride;
+      fstride *= 2 * n;
+    }
+    const double2 v = full[fidx];
+    sym[(int64_t)ab * total + idx] = sfft::mk<C>((decltype(C::x))(v.x * scale), (decltype(C::x))(v.y * scale));
+  }
+}
+
 // x (nv, n...) -> zero-padded (nv, 2n...)
 template <typename C>
 __global__ void k_pad(const C* __restrict__ x, C* __restrict__ P, Dims dm, int64_t total) {
@@ -232,6 +255,10 @@ struct sfft_plan_s {
   int64_t sym_bs = 0;  // symbol entries per leaf branch prefix
   int64_t ntiles = 0;  // leaf tiles per component per rhs
   int64_t npen = 0;    // leaf pencils per component per rhs
+  // mirrored symbol storage (compressed = 1)
+  int64_t mst[kMaxD] = {0};
+  int64_t mcomp = 0;
+  uint64_t odd_bits = 0;
   size_t table_bytes = 0;
   std::mutex pool_mu;
   void* pool = nullptr;
@@ -332,7 +359,9 @@ sfft_status run_pass(const sfft_plan_s* p, int l, int mode, const PassArgs& a, h
   return SFFT_OK;
 }
 
-sfft_status run_leaf(const sfft_plan_s* p, const void* in, void* out, int64_t in_bs, int64_t nq, const void* sym,
+// Leaf pass over branches q0 .. q0+nq-1 of levels 1..d-1 (q0 only matters
+// for the symbols: its bits are the branch's parities).
+sfft_status run_leaf(const sfft_plan_s* p, const void* in, void* out, int64_t in_bs, int64_t nq, int64_t q0,
                      int64_t nrhs, hipStream_t st) {
   const int l = p->d - 1;
   const AxisOps* o = p->ops[l];
@@ -344,21 +373,33 @@ sfft_status run_leaf(const sfft_plan_s* p, const void* in, void* out, int64_t in
   a.out_bs = in_bs;
   a.nq = nq;
   a.tw = p->tw[l];
-  a.sym = sym;
-  a.sym_bs = p->sym_bs;
   a.npen = p->npen;
   a.nrhs = nrhs;
   a.ntiles = p->ntiles;
-  const int npar = p->method == SFFT_SPLIT ? 2 : 1;
-  sfft::pass_fn f = o->leaf[p->b][npar];
+  sfft::pass_fn f;
+  if (p->compressed) {
+    a.sym = p->sym;
+    a.sym_bs = 0;
+    a.q0 = q0;
+    a.d = p->d;
+    for (int m = 0; m < p->d; ++m) {
+      a.mn[m] = p->n[m];
+      a.mst[m] = p->mst[m];
+    }
+    a.mcomp = p->mcomp;
+    a.odd_bits = p->odd_bits;
+    f = o->leaf_mirror[p->b];
+  } else {
+    a.sym = (const char*)p->sym + (size_t)(q0 * p->sym_bs) * p->esz;
+    a.sym_bs = p->sym_bs;
+    f = o->leaf[p->b][p->method == SFFT_SPLIT ? 2 : 1];
+  }
   if (!f) return fail(SFFT_UNSUPPORTED, "no leaf kernel for this block size");
   ProfScope ps(p, SFFT_KIND_LEAF, st);
   hipError_t e = f(a, st);
   if (e != hipSuccess) return hip_fail(e, "leaf launch");
   return SFFT_OK;
 }
-
-char* cptr(const void* base, int64_t elems, size_t esz) { return (char*)base + elems * (int64_t)esz; }
 
 // Depth-first (Algorithm 1 order): src holds the branch after levels < l were
 // transformed; dst receives that branch's merged result. Level l's odd child
@@ -367,10 +408,7 @@ sfft_status split_depth(const sfft_plan_s* p, int l, const void* src, void* dst,
                         char* ws, hipStream_t st) {
   const int64_t V = vec_elems(p, nrhs);
   const int64_t nv = nrhs * p->b;
-  if (l == p->d - 1) {
-    const void* sym = cptr(p->sym, q * p->sym_bs, p->esz);
-    return run_leaf(p, src, dst, V, 1, sym, nrhs, st);
-  }
+  if (l == p->d - 1) return run_leaf(p, src, dst, V, 1, q, nrhs, st);
   void* odd = ws + (size_t)l * V * p->esz;
   PassArgs a = base_args(p, l, nv);
   a.in = src;
@@ -396,7 +434,7 @@ sfft_status split_breadth(const sfft_plan_s* p, const void* x, void* y, int64_t 
   const int d = p->d;
   const int64_t V = vec_elems(p, nrhs);
   const int64_t nv = nrhs * p->b;
-  if (d == 1) return run_leaf(p, x, y, V, 1, p->sym, nrhs, st);
+  if (d == 1) return run_leaf(p, x, y, V, 1, 0, nrhs, st);
   char* blk[kMaxD];
   size_t off = 0;
   for (int l = 0; l < d - 1; ++l) {
@@ -415,7 +453,7 @@ sfft_status split_breadth(const sfft_plan_s* p, const void* x, void* y, int64_t 
     a.use_phase = 1;
     if ((s = run_pass(p, l, 0, a, st)) != SFFT_OK) return s;
   }
-  if ((s = run_leaf(p, blk[d - 2], blk[d - 2], V, int64_t(1) << (d - 1), p->sym, nrhs, st)) != SFFT_OK)
+  if ((s = run_leaf(p, blk[d - 2], blk[d - 2], V, int64_t(1) << (d - 1), 0, nrhs, st)) != SFFT_OK)
     return s;
   for (int l = d - 2; l >= 0; --l) {
     PassArgs a = base_args(p, l, nv);
@@ -457,7 +495,7 @@ sfft_status embed_apply(const sfft_plan_s* p, const void* x, void* y, int64_t nr
     if ((s = run_pass(p, l, 0, a, st)) != SFFT_OK) return s;
   }
   const int64_t Vbig = big;
-  if ((s = run_leaf(p, ws, ws, Vbig, 1, p->sym, nrhs, st)) != SFFT_OK) return s;
+  if ((s = run_leaf(p, ws, ws, Vbig, 1, 0, nrhs, st)) != SFFT_OK) return s;
   for (int l = d - 2; l >= 0; --l) {
     PassArgs a = base_args(p, l, nv);
     a.in = ws;
@@ -546,7 +584,15 @@ sfft_status build_symbols(sfft_plan_s* p, const double2* coeffs, hipStream_t st)
       break;
     }
     if ((s = fft64_inplace(dm, tmp, tw64, st)) != SFFT_OK) break;
-    if (p->method == SFFT_SPLIT) {
+    if (p->compressed) {
+      const int64_t total = p->mcomp;
+      if (p->dtype == SFFT_C64)
+        hipLaunchKernelGGL(k_scatter_mirror<float2>, dim3(grid_for(total)), dim3(256), 0, st, tmp, (float2*)p->sym,
+                           ab, dm, scale, total);
+      else
+        hipLaunchKernelGGL(k_scatter_mirror<double2>, dim3(grid_for(total)), dim3(256), 0, st, tmp,
+                           (double2*)p->sym, ab, dm, scale, total);
+    } else if (p->method == SFFT_SPLIT) {
       const int64_t total = (int64_t(1) << d) * p->ntiles * lo->LE * lo->NTL;
       if (p->dtype == SFFT_C64)
         hipLaunchKernelGGL(k_scatter_split<float2>, dim3(grid_for(total)), dim3(256), 0, st, tmp, (float2*)p->sym,
@@ -658,11 +704,17 @@ sfft_status sfft_plan_create(sfft_plan* out, int d, const int64_t* n, int b, con
     if (method == SFFT_SPLIT && !find_ops(dtype, n[l]))
       return fail(SFFT_UNSUPPORTED, "no kernels for length " + std::to_string(n[l]));
   }
+  bool mirror = false;
   if (parity) {
     for (int i = 0; i < b * b * d; ++i)
       if (parity[i] < SFFT_PARITY_NONE || parity[i] > SFFT_PARITY_ODD)
         return fail(SFFT_INVALID_ARG, "bad parity entry");
-    return fail(SFFT_UNSUPPORTED, "mirrored symbol storage is not built yet");
+    if (method == SFFT_SPLIT) {
+      for (int i = 0; i < b * b * d; ++i)
+        if (parity[i] == SFFT_PARITY_NONE)
+          return fail(SFFT_UNSUPPORTED, "mirrored storage needs every (component, level) even or odd");
+      mirror = true;
+    }
   }
 
   sfft_plan_s* p = new sfft_plan_s();
@@ -692,9 +744,23 @@ sfft_status sfft_plan_create(sfft_plan* out, int d, const int64_t* n, int b, con
   for (int l = 0; l < d - 1; ++l) p->npen *= p->L[l];
   p->ntiles = (p->npen + lo->PL - 1) / lo->PL;
   const int npar = method == SFFT_SPLIT ? 2 : 1;
-  p->sym_bs = (int64_t)npar * p->ntiles * b * b * lo->LE * lo->NTL;
-  const int64_t nbranch = method == SFFT_SPLIT ? (int64_t(1) << (d - 1)) : 1;
-  p->sym_bytes = (size_t)(nbranch * p->sym_bs) * p->esz;
+  if (mirror) {
+    p->compressed = 1;
+    p->mcomp = 1;
+    for (int l = d - 1; l >= 0; --l) {
+      p->mst[l] = p->mcomp;
+      p->mcomp *= n[l] + 1;
+    }
+    for (int ab = 0; ab < b * b; ++ab)
+      for (int l = 0; l < d; ++l)
+        if (parity[ab * d + l] == SFFT_PARITY_ODD) p->odd_bits |= uint64_t(1) << (ab * 6 + l);
+    p->sym_bs = 0;
+    p->sym_bytes = (size_t)(b * b * p->mcomp) * p->esz;
+  } else {
+    p->sym_bs = (int64_t)npar * p->ntiles * b * b * lo->LE * lo->NTL;
+    const int64_t nbranch = method == SFFT_SPLIT ? (int64_t(1) << (d - 1)) : 1;
+    p->sym_bytes = (size_t)(nbranch * p->sym_bs) * p->esz;
+  }
 
   sfft_status s = SFFT_OK;
   for (int l = 0; l < d && s == SFFT_OK; ++l) s = make_table(dtype, p->L[l], &p->tw[l], &p->table_bytes, st);

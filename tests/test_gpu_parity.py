@@ -34,12 +34,15 @@ def _say(*a):
     sys.stdout.flush()
 
 
-def _run(sf, coeffs, x, dtype, method="split", schedule="auto"):
+def _run(sf, coeffs, x, dtype, method="split", schedule="auto", parity=None, info=None):
     n = oracle.grid_of(coeffs)
     b = coeffs.shape[0]
-    _say(f"n={n} b={b} dtype={dtype} method={method} sched={schedule} nrhs={x.shape[0]}")
+    _say(f"n={n} b={b} dtype={dtype} method={method} sched={schedule} nrhs={x.shape[0]} "
+         f"mirrored={parity is not None}")
     plan = sf.Plan(n, b, torch.from_numpy(coeffs).cuda(), dtype=dtype, method=method,
-                   max_nrhs=x.shape[0], schedule=schedule)
+                   max_nrhs=x.shape[0], schedule=schedule, parity=parity)
+    if info is not None:
+        info.update(plan.info())
     xd = torch.from_numpy(x.astype(NP[dtype])).cuda()
     ws = plan.alloc_workspace(x.shape[0])
     y = plan.apply(xd, workspace=ws)
@@ -148,3 +151,68 @@ def test_apply_rejects_bad_arguments(sf):
     with pytest.raises(ValueError):
         plan.apply(x.to(torch.complex128))
     plan.close()
+
+
+def _odd_scalar_coeffs(n, seed):
+    """Scalar generator odd along every level: prod_l sgn(r_l) * g(|r|)."""
+    rng = np.random.default_rng(seed)
+    r = wl.offsets(n)
+    dist = np.sqrt(sum(np.asarray(v, dtype=float) ** 2 for v in r))
+    g = np.cos(1.1 * dist) + 1j * np.sin(0.4 * dist + rng.standard_normal())
+    sgn = np.ones(dist.shape)
+    for v in r:
+        sgn = sgn * np.sign(v)
+    return (sgn * g)[None, None].astype(np.complex128)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("grid", [(6, 10, 12), (5, 12, 40), (16, 16, 16), (10, 12)])
+def test_mirrored_symbols_green(sf, grid, dtype):
+    """Green blocks with symbols stored mirrored (Section II.C): same product."""
+    coeffs = wl.green_coeffs(grid, 0.7)
+    x = wl.vectors(21, grid, 3, 2)
+    want = oracle.embed_matvec(coeffs, x)
+    par = wl.green_parity(len(grid))
+    for sched in ("breadth", "depth"):
+        info = {}
+        got = _run(sf, coeffs, x, dtype, "split", sched, parity=par, info=info)
+        assert info["compressed"] == 1
+        esz = 8 if dtype == "c64" else 16
+        assert info["symbol_bytes"] == 9 * math.prod(v + 1 for v in grid) * esz
+        assert wl.relative_l2(got, want) <= TOL[dtype], sched
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("grid", [(6, 10, 12), (8, 5, 16)])
+def test_mirrored_symbols_skew(sf, grid, dtype):
+    coeffs = wl.skew_coeffs(grid, 1.3)
+    x = wl.vectors(22, grid, 3, 1)
+    want = oracle.embed_matvec(coeffs, x)
+    got = _run(sf, coeffs, x, dtype, "split", parity=wl.skew_parity(3))
+    assert wl.relative_l2(got, want) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("grid", [(5, 6), (12, 10, 3), (40,)])
+def test_mirrored_symbols_odd_scalar(sf, grid):
+    coeffs = _odd_scalar_coeffs(grid, 5)
+    x = wl.vectors(23, grid, 1, 2)
+    want = oracle.dense_matvec(coeffs, x)
+    par = np.full((1, 1, len(grid)), wl.ODD, dtype=np.int32)
+    got = _run(sf, coeffs, x, "c128", "split", parity=par)
+    assert wl.relative_l2(got, want) <= 1e-12
+    # declaring the wrong symmetry gives a wrong product (the declaration is trusted)
+    bad = np.full((1, 1, len(grid)), wl.EVEN, dtype=np.int32)
+    got = _run(sf, coeffs, x, "c128", "split", parity=bad)
+    assert wl.relative_l2(got, want) > 1e-3
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_green_64_mirrored_full_size(sf, green64, dtype):
+    """The symmetric-kernel variant of the 64^3 Green workload."""
+    coeffs, x, want, _, _ = green64
+    info = {}
+    got = _run(sf, coeffs, x, dtype, "split", parity=wl.green_parity(3), info=info)
+    err = wl.relative_l2(got, want)
+    _say(f"green64 mirrored {dtype} rel_l2={err:.3e} symbol_bytes={info['symbol_bytes']}")
+    assert info["symbol_bytes"] == 9 * 65 ** 3 * (8 if dtype == "c64" else 16)
+    assert err <= TOL[dtype]

@@ -344,3 +344,19 @@ def test_pins_catch_transposed_blocks():
     bad = np.swapaxes(t, 0, 1).copy()
     assert wl.relative_l2(oracle.embed_matvec(bad, x), want) > 1e-2
     assert wl.relative_l2(oracle.split_alg1(bad, x), want) > 1e-2
+
+
+@pytest.mark.parametrize("kind,n", [("green", (4, 5, 3)), ("green", (5, 4)), ("skew", (4, 3, 5))])
+def test_declared_parity_masks_hold(kind, n):
+    """workloads' parity masks: flipping offset axis l maps t to +t (even) or -t (odd)."""
+    d = len(n)
+    if kind == "green":
+        t, par = wl.green_coeffs(n, 0.7), wl.green_parity(d)
+    else:
+        t, par = wl.skew_coeffs(n, 1.3), wl.skew_parity(d)
+    for a in range(3):
+        for c in range(3):
+            for l in range(d):
+                flipped = np.flip(t[a, c], axis=l)
+                sign = 1.0 if par[a, c, l] == wl.EVEN else -1.0
+                np.testing.assert_allclose(flipped, sign * t[a, c], atol=1e-15)
