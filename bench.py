@@ -145,6 +145,65 @@ def pmc_summarize(fetch_dir, write_dir, out_path):
     print(json.dumps(rec))
 
 
+def bench_large(args):
+    """256 x 256 x 128 grid, 3x3 Green blocks (k=1.3) and the skew kernel, 8 RHS,
+    complex64: time per product and device memory of the split path (both
+    schedules, general and mirrored symbols) against the full embedding."""
+    import numpy as np
+    import torch
+    import workloads as wl
+    import paper_2406_17981_amd as sf
+    cfg = wl.LARGE_256
+    n, nrhs = cfg["n"], cfg["nrhs"]
+    x_host = wl.vectors(cfg["seed_x"], n, 3, nrhs).astype(np.complex64)
+    x = torch.from_numpy(x_host).cuda()
+    y = torch.empty_like(x)
+    del x_host
+    out = {}
+    for kname in ("green", "skew"):
+        coeffs = wl.green_coeffs(n, cfg["k"]) if kname == "green" else wl.skew_coeffs(n, cfg["k"])
+        par = wl.green_parity(3) if kname == "green" else wl.skew_parity(3)
+        cd = torch.from_numpy(coeffs).cuda()
+        del coeffs
+        cases = [("split_depth", "split", "depth", None), ("split_breadth", "split", "breadth", None),
+                 ("split_depth_mirrored", "split", "depth", par), ("embed", "embed", "auto", None)]
+        if kname == "skew":
+            cases = [cases[2], cases[3]]
+        for label, method, sched, parity in cases:
+            torch.cuda.synchronize()
+            free0 = torch.cuda.mem_get_info()[0]
+            plan = sf.Plan(n, 3, cd, dtype="c64", method=method, parity=parity, max_nrhs=nrhs,
+                           schedule=sched)
+            ws = plan.alloc_workspace(nrhs)
+            torch.cuda.synchronize()
+            held = free0 - torch.cuda.mem_get_info()[0]
+            ms, _ = time_plan(plan, x, y, ws, args.steps, args.warmup)
+            info = plan.info()
+            vb = 2 * x.numel() * 8
+            out[f"{kname}_{label}"] = dict(ms_per_apply=round(ms, 4), matvecs_per_s=round(nrhs * 1e3 / ms, 1),
+                                           device_bytes=info["symbol_bytes"] + info["table_bytes"]
+                                           + info["workspace_bytes"] + vb,
+                                           symbol_bytes=info["symbol_bytes"],
+                                           workspace_bytes=info["workspace_bytes"],
+                                           measured_plan_and_workspace_bytes=int(held))
+            log(f"[large {kname} {label}] {ms:.3f} ms per apply of {nrhs} RHS")
+            plan.close()
+            del ws
+            torch.cuda.empty_cache()
+        del cd
+        torch.cuda.empty_cache()
+    g = out
+    line = {"workload": "green/skew-256x256x128-b3-8rhs-c64", "grid": list(n), "b": 3, "nrhs": nrhs,
+            "steps": args.steps, "warmup": args.warmup, "results": g,
+            "split_depth_vs_embed": {
+                "speedup": round(g["green_embed"]["ms_per_apply"] / g["green_split_depth"]["ms_per_apply"], 3),
+                "device_bytes_ratio_embed_over_split": round(g["green_embed"]["device_bytes"]
+                                                             / g["green_split_depth"]["device_bytes"], 3),
+                "device_bytes_ratio_embed_over_split_mirrored": round(
+                    g["green_embed"]["device_bytes"] / g["green_split_depth_mirrored"]["device_bytes"], 3)}}
+    print(json.dumps(line), flush=True)
+
+
 def time_plan(plan, x, y, ws, steps, warmup, profile_leaf=False):
     import torch
     for _ in range(warmup):
@@ -198,6 +257,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variants", default="all", choices=["all", "headline"])
     ap.add_argument("--pmc-probe", action="store_true", help="workload for rocprofv3 --pmc runs")
+    ap.add_argument("--workload", default="green64", choices=["green64", "large"],
+                    help="large: the 256x256x128 8-RHS parity configuration, split vs embed")
     ap.add_argument("--pmc-summarize", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON"))
     args = ap.parse_args()
 
@@ -206,6 +267,9 @@ def main():
         return
     if args.pmc_probe:
         pmc_probe()
+        return
+    if args.workload == "large":
+        bench_large(args)
         return
 
     if args.gpus != 1:

@@ -300,11 +300,17 @@ def sampled_rows(coeffs: np.ndarray, x: np.ndarray, points: np.ndarray) -> np.nd
     x = _as_vectors(x, b, n)
     points = np.asarray(points, dtype=np.int64).reshape(-1, len(n))
     out = np.empty((x.shape[0], b, points.shape[0]), dtype=np.complex128)
+    xf = x.reshape(x.shape[0], b, -1)
     for kk, i in enumerate(points):
-        idx = [int(i[l]) + n[l] - 1 - np.arange(n[l]) for l in range(len(n))]
-        slab = coeffs[(slice(None), slice(None)) + np.ix_(*idx)]
-        out[:, :, kk] = np.einsum("acj,rcj->ra", slab.reshape(b, b, -1),
-                                  x.reshape(x.shape[0], b, -1))
+        # t(i - j) for all j: offsets i_l - j_l, i.e. a reversed window of each offset axis
+        sl = tuple(slice(int(i[l]) + n[l] - 1, (int(i[l]) - 1 if i[l] > 0 else None), -1)
+                   for l in range(len(n)))
+        for a in range(b):
+            acc = np.zeros(x.shape[0], dtype=np.complex128)
+            for c in range(b):
+                slab = np.ascontiguousarray(coeffs[(a, c) + sl]).reshape(-1)
+                acc += xf[:, c, :] @ slab
+            out[:, a, kk] = acc
     return out
 
 

@@ -216,3 +216,51 @@ def test_green_64_mirrored_full_size(sf, green64, dtype):
     _say(f"green64 mirrored {dtype} rel_l2={err:.3e} symbol_bytes={info['symbol_bytes']}")
     assert info["symbol_bytes"] == 9 * 65 ** 3 * (8 if dtype == "c64" else 16)
     assert err <= TOL[dtype]
+
+
+@pytest.fixture(scope="module")
+def large_points():
+    rng = np.random.default_rng(5020)
+    n = wl.LARGE_256["n"]
+    pts = np.stack([rng.integers(0, v, 4) for v in n], axis=1)
+    # corners: the projection boundary
+    extra = np.array([[0, 0, 0], [n[0] - 1, n[1] - 1, n[2] - 1], [0, n[1] - 1, n[2] // 2]])
+    return np.concatenate([pts, extra])
+
+
+def _large_case(sf, coeffs, x, pts, dtype, parity, schedule):
+    n = wl.LARGE_256["n"]
+    _say(f"large n={n} dtype={dtype} mirrored={parity is not None} sched={schedule} nrhs={x.shape[0]}")
+    plan = sf.Plan(n, 3, torch.from_numpy(coeffs).cuda(), dtype=dtype, parity=parity,
+                   max_nrhs=x.shape[0], schedule=schedule)
+    info = plan.info()
+    xd = torch.from_numpy(x.astype(NP[dtype])).cuda()
+    y = plan.apply(xd, workspace=plan.alloc_workspace(x.shape[0]))
+    torch.cuda.synchronize()
+    idx = torch.from_numpy(np.ravel_multi_index(pts.T, n)).cuda()
+    got = y.reshape(x.shape[0], 3, -1)[:, :, idx].cpu().numpy().astype(np.complex128)
+    plan.close()
+    del xd, y
+    torch.cuda.empty_cache()
+    return got, info
+
+
+def test_large_green_and_skew_full_size(sf, large_points):
+    """256 x 256 x 128 grid, 3x3 blocks, 8 right-hand sides, complex64 (FP64 symbols):
+    Green k=1.3 (general and mirrored symbols) and the skew-symmetric kernel
+    (mirrored), each against direct sums at sampled output points."""
+    cfg = wl.LARGE_256
+    n, nrhs = cfg["n"], cfg["nrhs"]
+    x = wl.vectors(cfg["seed_x"], n, 3, nrhs)
+    for name, make, par in (("green", lambda: wl.green_coeffs(n, cfg["k"]), wl.green_parity(3)),
+                            ("skew", lambda: wl.skew_coeffs(n, cfg["k"]), wl.skew_parity(3))):
+        coeffs = make()
+        want = oracle.sampled_rows(coeffs, x, large_points)
+        cases = [(par, "depth")] if name == "skew" else [(None, "depth"), (par, "breadth")]
+        for parity, sched in cases:
+            got, info = _large_case(sf, coeffs, x, large_points, "c64", parity, sched)
+            err = wl.relative_l2(got, want)
+            _say(f"large {name} mirrored={parity is not None} rel_l2={err:.3e} "
+                 f"symbol_bytes={info['symbol_bytes']} workspace={info['workspace_bytes']}")
+            assert err <= 1e-5
+        del coeffs
