@@ -46,6 +46,7 @@ struct PassArgs {
   int64_t npen;      // pencils per component per right-hand side
   int64_t nrhs;
   int64_t ntiles;    // ceil(npen / P)
+  int rb;            // right-hand sides per workgroup
   // LEAF with mirrored symbol storage (Section II.C): per component a
   // (n_1+1) x ... x (n_d+1) array; along level l the first n_l/2+1 entries
   // are the even bins 2j of the 2n_l lattice, the rest the odd bins 2j+1,
@@ -68,15 +69,25 @@ template <typename Real, int L> struct Geo {
   static constexpr int W = NT / T;                     // strided tile width (pencils)
   static constexpr int P = NT / T;                     // contiguous tile (pencils)
   static constexpr int LP = L + 1;                     // padded LDS row
-  // leaf kernel: its own radix plan (FP64 lanes hold fewer entries), tile of
-  // PL pencils, NTL threads
+  static constexpr bool WS = (64 % T) == 0;    // contiguous pass: pencil inside one wavefront
+  // Leaf kernel: its own radix plan (FP64 lanes hold fewer entries). A tile
+  // is PL pencils (SL = PL * LT lanes, one symbol block); a workgroup takes
+  // one tile for RB right-hand sides (RB chosen per launch, <= RBMAX).
   using LSh = typename std::conditional<sizeof(Real) == 4 && Shape<L>::E <= 8, Shape<L>, LeafShape<L>>::type;
   static constexpr int LT = LSh::T;
   static constexpr int LE = LSh::E;
-  static constexpr int PL = (128 / LT) > 0 ? (128 / LT) : 1;
-  static constexpr int NTL = PL * LT;
-  static constexpr bool WS = (64 % T) == 0;    // contiguous pass: pencil inside one wavefront
+  static constexpr int SL = LT >= 64 ? LT : 64;
+  static constexpr int PL = SL / LT;
+  static constexpr int NTL = SL;  // threads per right-hand side
   static constexpr bool LWS = (64 % LT) == 0;  // leaf: pencil inside one wavefront
+  // LDS row of a (pencil, rhs) pair: LLP = LT (mod 32) complex entries, so
+  // neighbouring rows start in different banks
+  static constexpr int LLP = L + (((LT - L) % 32) + 32) % 32;
+  static constexpr int RB_LDS = (int)((64 * 1024) / ((size_t)PL * LLP * sizeof(cx<Real>)));
+  static constexpr int THR_CAP = (sizeof(Real) == 8 || L >= 256) ? 256 : 512;  // keeps the VGPR budget
+  static constexpr int RB_THR = SL >= THR_CAP ? 1 : THR_CAP / SL;
+  static constexpr int RBMAX_ = RB_LDS < RB_THR ? RB_LDS : RB_THR;
+  static constexpr int RBMAX = RBMAX_ >= 8 ? 8 : (RBMAX_ >= 4 ? 4 : (RBMAX_ >= 2 ? 2 : 1));
 };
 
 // Position of symbol entry (block component ab, home index m, lane) inside one
@@ -115,6 +126,11 @@ __global__ void __launch_bounds__(256) k_strided(PassArgs a) {
   const int64_t st = a.inner;
   const C* tw = (const C*)a.tw;
   C* lp = lds + c;
+  LaneTw<C, Sh> lt;
+  lt.load(t, tw);
+  C ph[E];  // split phases Phi[k] of this lane's entries
+#pragma unroll
+  for (int m = 0; m < E; ++m) ph[m] = tw[t + T * m];
   C h[E];
   if constexpr (MODE == 0) {
     const C* in = (const C*)a.in + q * a.in_bs + base;
@@ -124,7 +140,7 @@ __global__ void __launch_bounds__(256) k_strided(PassArgs a) {
       C w[E];
 #pragma unroll
       for (int m = 0; m < E; ++m) w[m] = h[m];
-      fft_pencil<-1, Sh>(w, lp, W, t, tw);
+      fft_pencil<-1, Sh>(w, lp, W, t, lt);
       if (act) {
         C* out = (C*)a.out + q * a.out_bs + base;
 #pragma unroll
@@ -134,8 +150,8 @@ __global__ void __launch_bounds__(256) k_strided(PassArgs a) {
     if (a.out1) {
       C w[E];
 #pragma unroll
-      for (int m = 0; m < E; ++m) w[m] = a.use_phase ? cmul(h[m], tw[t + T * m]) : h[m];
-      fft_pencil<-1, Sh>(w, lp, W, t, tw);
+      for (int m = 0; m < E; ++m) w[m] = a.use_phase ? cmul(h[m], ph[m]) : h[m];
+      fft_pencil<-1, Sh>(w, lp, W, t, lt);
       if (act) {
         C* out = (C*)a.out1 + q * a.out_bs + base;
 #pragma unroll
@@ -146,15 +162,15 @@ __global__ void __launch_bounds__(256) k_strided(PassArgs a) {
     const C* in = (const C*)a.in + q * a.in_bs + base;
 #pragma unroll
     for (int m = 0; m < E; ++m) h[m] = act ? in[(t + T * m) * st] : czero<C>();
-    fft_pencil<+1, Sh>(h, lp, W, t, tw);
+    fft_pencil<+1, Sh>(h, lp, W, t, lt);
     if (a.in1) {
       const C* in1 = (const C*)a.in1 + q * a.in_bs + base;
       C w[E];
 #pragma unroll
       for (int m = 0; m < E; ++m) w[m] = act ? in1[(t + T * m) * st] : czero<C>();
-      fft_pencil<+1, Sh>(w, lp, W, t, tw);
+      fft_pencil<+1, Sh>(w, lp, W, t, lt);
 #pragma unroll
-      for (int m = 0; m < E; ++m) h[m] = cadd(h[m], a.use_phase ? cmulc(w[m], tw[t + T * m]) : w[m]);
+      for (int m = 0; m < E; ++m) h[m] = cadd(h[m], a.use_phase ? cmulc(w[m], ph[m]) : w[m]);
     }
     if (act) {
       C* out = (C*)a.out + q * a.out_bs + base;
@@ -212,6 +228,11 @@ __global__ void __launch_bounds__(256) k_contig(PassArgs a) {
   const int nh = (int)((a.outer - p0) < P ? (a.outer - p0) : P);
   const C* tw = (const C*)a.tw;
   C* lp = lds + g * LP;
+  LaneTw<C, Sh> lt;
+  lt.load(t, tw);
+  C ph[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) ph[m] = tw[t + T * m];
   C h[E];
   tile_load<C, L, P, NT>(lds, (const C*)a.in + q * a.in_bs + p0 * L, nh, tid);
   __syncthreads();
@@ -223,18 +244,18 @@ __global__ void __launch_bounds__(256) k_contig(PassArgs a) {
       C w[E];
 #pragma unroll
       for (int m = 0; m < E; ++m) w[m] = h[m];
-      fft_pencil<-1, Sh, G::WS>(w, lp, 1, t, tw);
+      fft_pencil<-1, Sh, G::WS>(w, lp, 1, t, lt);
       store_home<C, L, T, E, P, NT>((C*)a.out + q * a.out_bs + p0 * L, lds, w, g, t, nh, tid);
     }
     if (a.out1) {
       C w[E];
 #pragma unroll
-      for (int m = 0; m < E; ++m) w[m] = a.use_phase ? cmul(h[m], tw[t + T * m]) : h[m];
-      fft_pencil<-1, Sh, G::WS>(w, lp, 1, t, tw);
+      for (int m = 0; m < E; ++m) w[m] = a.use_phase ? cmul(h[m], ph[m]) : h[m];
+      fft_pencil<-1, Sh, G::WS>(w, lp, 1, t, lt);
       store_home<C, L, T, E, P, NT>((C*)a.out1 + q * a.out_bs + p0 * L, lds, w, g, t, nh, tid);
     }
   } else {
-    fft_pencil<+1, Sh, G::WS>(h, lp, 1, t, tw);
+    fft_pencil<+1, Sh, G::WS>(h, lp, 1, t, lt);
     if (a.in1) {
       tile_load<C, L, P, NT>(lds, (const C*)a.in1 + q * a.in_bs + p0 * L, nh, tid);
       __syncthreads();
@@ -242,9 +263,9 @@ __global__ void __launch_bounds__(256) k_contig(PassArgs a) {
 #pragma unroll
       for (int m = 0; m < E; ++m) w[m] = lp[t + T * m];
       __syncthreads();
-      fft_pencil<+1, Sh, G::WS>(w, lp, 1, t, tw);
+      fft_pencil<+1, Sh, G::WS>(w, lp, 1, t, lt);
 #pragma unroll
-      for (int m = 0; m < E; ++m) h[m] = cadd(h[m], a.use_phase ? cmulc(w[m], tw[t + T * m]) : w[m]);
+      for (int m = 0; m < E; ++m) h[m] = cadd(h[m], a.use_phase ? cmulc(w[m], ph[m]) : w[m]);
     }
     store_home<C, L, T, E, P, NT>((C*)a.out + q * a.out_bs + p0 * L, lds, h, g, t, nh, tid);
   }
@@ -252,51 +273,64 @@ __global__ void __launch_bounds__(256) k_contig(PassArgs a) {
 
 // ---------------------------------------------------------------------------
 // Leaf: innermost level with the b x b diagonal block product (mulBrn).
-// Input / output per branch: (nrhs, B, npen, L). Symbols per branch q:
-// [p][tile][a*B + c][m][lane] (NPAR x ntiles x B*B x E x NTL), i.e. in the
-// order the lanes hold the transformed entries, so every symbol load of a
-// wavefront is one contiguous run.
-// Workgroups are numbered so that the right-hand sides of one tile are 8
-// apart: they land on the same XCD and share its L2 copy of the symbols.
+// Input / output per branch: (nrhs, B, npen, L). Both children of the last
+// level are transformed from the same registers (even: x, odd: Phi x),
+// multiplied by their symbol blocks, inverse transformed and merged:
+//     out = iFFT(S_0 FFT(x)) + conj(Phi) iFFT(S_1 FFT(Phi x)).
+// Lane (g, r, t) = tid: pencil g of the tile, right-hand side r of the
+// workgroup's RB, lane t of the pencil; the RB lanes of one (g, t) read the
+// same symbol addresses in one wavefront instruction, so a symbol block is
+// fetched once for all RB right-hand sides. Symbols per (branch, parity,
+// tile): [a*B + c][m/2][g*T + t][m%2] (see sym_offset), or mirrored storage.
+// Workgroups of one tile are numbered 8 apart, so all of a tile's
+// right-hand-side groups run on the same XCD and share its L2.
 // ---------------------------------------------------------------------------
 template <typename Real, int L, int B, int NPAR, bool MIR>
-__global__ void __launch_bounds__((Geo<Real, L>::NTL)) k_leaf(PassArgs a) {
+__global__ void __launch_bounds__((Geo<Real, L>::RBMAX * Geo<Real, L>::SL)) k_leaf(PassArgs a) {
   using C = cx<Real>;
   using G = Geo<Real, L>;
   using Sh = typename G::LSh;
   using C2 = typename PairOf<C>::type;
-  constexpr int T = G::LT, E = G::LE, P = G::PL, LP = G::LP, NT = G::NTL;
-  __shared__ C home[B * P * LP];
-  __shared__ C scr[P * LP];
+  constexpr int T = G::LT, E = G::LE, P = G::PL, LP = G::LLP, SL = G::SL;
+  extern __shared__ __align__(16) unsigned char leaf_smem[];
+  C* lds = reinterpret_cast<C*>(leaf_smem);
+  const int RB = a.rb;
   const int tid = threadIdx.x;
-  const int g = tid / T, t = tid % T;
+  const int t = tid % T;
+  const int gr = tid / T;
+  const int rl = gr % RB;
+  const int g = gr / RB;
+  const int row = g * RB + rl;
+  const int64_t nrg = (a.nrhs + RB - 1) / RB;
   const int64_t ntiles8 = (a.ntiles + 7) / 8;
   const int64_t id = blockIdx.x;
   const int64_t lo = id & 7;
   const int64_t t2 = id >> 3;
-  const int64_t r = t2 % a.nrhs;
-  const int64_t t3 = t2 / a.nrhs;
+  const int64_t rg = t2 % nrg;
+  const int64_t t3 = t2 / nrg;
   const int64_t tile = (t3 % ntiles8) * 8 + lo;
   const int64_t q = t3 / ntiles8;
   if (tile >= a.ntiles) return;  // whole workgroup exits together
   const int64_t p0 = tile * P;
   const int nh = (int)((a.npen - p0) < P ? (a.npen - p0) : P);
+  const int64_t r0 = rg * RB;
+  const int nr = (int)((a.nrhs - r0) < RB ? (a.nrhs - r0) : RB);
   const C* tw = (const C*)a.tw;
   const C* in = (const C*)a.in + q * a.in_bs;
   C* out = (C*)a.out + q * a.out_bs;
+  C* lp = lds + row * LP;
+  LaneTw<C, Sh> lt;
+  lt.load(t, tw);
 
+  // load: every lane reads its own entries k = t + T*m of its pencil for all
+  // components at once (runs of T consecutive entries per pencil)
+  const bool act = (g < nh) && (rl < nr);
+  const int64_t pbase = ((r0 + rl) * B * a.npen + p0 + g) * L + t;  // component 0
+  C x[B][E];
 #pragma unroll
   for (int c = 0; c < B; ++c)
-    tile_load<C, L, P, NT>(home + c * P * LP, in + ((r * B + c) * a.npen + p0) * L, nh, tid);
-  __syncthreads();
-
-  C acc[B][E];
 #pragma unroll
-  for (int c = 0; c < B; ++c)
-#pragma unroll
-    for (int m = 0; m < E; ++m) acc[c][m] = czero<C>();
-
-  C* lp = scr + g * LP;
+    for (int m = 0; m < E; ++m) x[c][m] = act ? in[pbase + (int64_t)c * a.npen * L + T * m] : czero<C>();
 
   // mirrored storage: this lane's pencil fixes the outer levels' stored index
   // and which of them are read mirrored
@@ -318,21 +352,11 @@ __global__ void __launch_bounds__((Geo<Real, L>::NTL)) k_leaf(PassArgs a) {
       mbase += (pl * (n / 2 + 1) + jj) * a.mst[l];
     }
   }
+  const int slane = g * T + t;  // lane inside the symbol block
 
-#pragma unroll
-  for (int p = 0; p < NPAR; ++p) {
-    C w[B][E];
-#pragma unroll
-    for (int c = 0; c < B; ++c)
-#pragma unroll
-      for (int m = 0; m < E; ++m) {
-        const C v = home[c * P * LP + g * LP + t + T * m];
-        w[c][m] = (p == 1) ? cmul(v, tw[t + T * m]) : v;
-      }
-#pragma unroll
-    for (int c = 0; c < B; ++c) fft_pencil<-1, Sh, G::LWS>(w[c], lp, 1, t, tw);
-    // mulBrn: per point, the b x b block of T[bId] times the b components
-    const C* sp = (const C*)a.sym + q * a.sym_bs + ((int64_t)p * a.ntiles + tile) * (B * B * E * NT);
+  // mulBrn for one child p: w[.][m] <- S_p[., .](m) w[.][m]
+  auto block_product = [&](C (&w)[B][E], int p) {
+    const C* sp = (const C*)a.sym + q * a.sym_bs + ((int64_t)p * a.ntiles + tile) * (B * B * E * SL);
     constexpr int MS = (E % 2 == 0) ? 2 : 1;  // entries per symbol load
 #pragma unroll
     for (int m0 = 0; m0 < E; m0 += MS) {
@@ -342,22 +366,22 @@ __global__ void __launch_bounds__((Geo<Real, L>::NTL)) k_leaf(PassArgs a) {
         if constexpr (MIR) {
           const int64_t n = L;
           const int ld = a.d - 1;
+          const uint32_t odd = (uint32_t)(a.odd_bits >> (ab * 6)) & 0x3fu;
 #pragma unroll
           for (int j = 0; j < MS; ++j) {
             const int64_t k = t + T * (m0 + j);
             const bool mir = 2 * k + p > n;
             const int64_t jj = mir ? (p ? n - 1 - k : n - k) : k;
             const uint32_t bits = mbits | ((uint32_t)mir << ld);
-            const uint32_t odd = (uint32_t)(a.odd_bits >> (ab * 6)) & 0x3fu;
             const C v = ((const C*)a.sym)[ab * a.mcomp + mbase + p * (n / 2 + 1) + jj];
             sm[j][ab] = (__builtin_popcount(bits & odd) & 1) ? mk<C>(-v.x, -v.y) : v;
           }
         } else if constexpr (MS == 2) {
-          const C2 v = *(const C2*)(sp + sym_offset(ab, m0, tid, E, NT));
+          const C2 v = *(const C2*)(sp + sym_offset(ab, m0, slane, E, SL));
           sm[0][ab] = mk<C>(v.x, v.y);
           sm[1][ab] = mk<C>(v.z, v.w);
         } else {
-          sm[0][ab] = sp[sym_offset(ab, m0, tid, E, NT)];
+          sm[0][ab] = sp[sym_offset(ab, m0, slane, E, SL)];
         }
       }
 #pragma unroll
@@ -374,24 +398,50 @@ __global__ void __launch_bounds__((Geo<Real, L>::NTL)) k_leaf(PassArgs a) {
         for (int ar = 0; ar < B; ++ar) w[ar][m0 + j] = o[ar];
       }
     }
+  };
+
+  if constexpr (NPAR == 2) {
+    // odd child: Phi x
+    C ph[E];
 #pragma unroll
-    for (int c = 0; c < B; ++c) fft_pencil<+1, Sh, G::LWS>(w[c], lp, 1, t, tw);
+    for (int m = 0; m < E; ++m) ph[m] = tw[t + T * m];
+    C w1[B][E];
 #pragma unroll
     for (int c = 0; c < B; ++c)
 #pragma unroll
-      for (int m = 0; m < E; ++m)
-        acc[c][m] = cadd(acc[c][m], (p == 1) ? cmulc(w[c][m], tw[t + T * m]) : w[c][m]);
+      for (int m = 0; m < E; ++m) w1[c][m] = cmul(x[c][m], ph[m]);
+#pragma unroll
+    for (int c = 0; c < B; ++c) {
+      fft_pencil<-1, Sh, G::LWS>(x[c], lp, 1, t, lt);
+      fft_pencil<-1, Sh, G::LWS>(w1[c], lp, 1, t, lt);
+    }
+    block_product(x, 0);
+    block_product(w1, 1);
+#pragma unroll
+    for (int c = 0; c < B; ++c) {
+      fft_pencil<+1, Sh, G::LWS>(x[c], lp, 1, t, lt);
+      fft_pencil<+1, Sh, G::LWS>(w1[c], lp, 1, t, lt);
+    }
+    // merge: even + conj(Phi) odd
+#pragma unroll
+    for (int c = 0; c < B; ++c)
+#pragma unroll
+      for (int m = 0; m < E; ++m) x[c][m] = cadd(x[c][m], cmulc(w1[c][m], ph[m]));
+  } else {
+#pragma unroll
+    for (int c = 0; c < B; ++c) fft_pencil<-1, Sh, G::LWS>(x[c], lp, 1, t, lt);
+    block_product(x, 0);
+#pragma unroll
+    for (int c = 0; c < B; ++c) fft_pencil<+1, Sh, G::LWS>(x[c], lp, 1, t, lt);
   }
 
-  __syncthreads();
+  // store: every lane writes its own entries
+  if (act) {
 #pragma unroll
-  for (int c = 0; c < B; ++c)
+    for (int c = 0; c < B; ++c)
 #pragma unroll
-    for (int m = 0; m < E; ++m) home[c * P * LP + g * LP + t + T * m] = acc[c][m];
-  __syncthreads();
-#pragma unroll
-  for (int c = 0; c < B; ++c)
-    tile_store<C, L, P, NT>(out + ((r * B + c) * a.npen + p0) * L, home + c * P * LP, nh, tid);
+      for (int m = 0; m < E; ++m) out[pbase + (int64_t)c * a.npen * L + T * m] = x[c][m];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -401,7 +451,8 @@ typedef hipError_t (*pass_fn)(const PassArgs&, hipStream_t);
 
 struct AxisOps {
   int L, T, E, W, P;   // strided / contiguous passes
-  int LT, LE, PL, NTL; // leaf: lanes per pencil, entries per lane, pencils per tile, threads
+  int LT, LE, PL, NTL; // leaf: lanes per pencil, entries per lane, pencils per tile, lanes per tile
+  int RBMAX;           // leaf: most right-hand sides per workgroup
   pass_fn strided[2];   // [0] FWD2, [1] INV2
   pass_fn contig[2];
   pass_fn leaf[5][3];   // [B][NPAR], null where not built
@@ -428,16 +479,21 @@ template <typename Real, int L, int MODE> hipError_t launch_contig(const PassArg
 template <typename Real, int L, int B, int NPAR, bool MIR = false>
 hipError_t launch_leaf(const PassArgs& a, hipStream_t s) {
   using G = Geo<Real, L>;
-  const int64_t blocks = a.nq * ((a.ntiles + 7) / 8) * a.nrhs * 8;
+  const int rb = a.rb < 1 ? 1 : (a.rb > G::RBMAX ? G::RBMAX : a.rb);
+  PassArgs b = a;
+  b.rb = rb;
+  const int64_t nrg = (a.nrhs + rb - 1) / rb;
+  const int64_t blocks = a.nq * ((a.ntiles + 7) / 8) * nrg * 8;
   if (blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_leaf<Real, L, B, NPAR, MIR>), dim3((unsigned)blocks), dim3(G::NTL), 0, s, a);
+  const size_t smem = (size_t)rb * G::PL * G::LLP * sizeof(cx<Real>);
+  hipLaunchKernelGGL((k_leaf<Real, L, B, NPAR, MIR>), dim3((unsigned)blocks), dim3(rb * G::SL), smem, s, b);
   return hipGetLastError();
 }
 
 template <typename Real, int L> const AxisOps* make_ops() {
   using G = Geo<Real, L>;
   static const AxisOps ops = {
-      L, G::T, G::E, G::W, G::P, G::LT, G::LE, G::PL, G::NTL,
+      L, G::T, G::E, G::W, G::P, G::LT, G::LE, G::PL, G::NTL, G::RBMAX,
       {launch_strided<Real, L, 0>, launch_strided<Real, L, 1>},
       {launch_contig<Real, L, 0>, launch_contig<Real, L, 1>},
       {{nullptr, nullptr, nullptr},

@@ -222,12 +222,22 @@ template <int L> struct LeafShape : Shape<L> {};
     static constexpr int rad(int s) { return rads[s]; }                        \
     static constexpr int ns(int s) { return s == 0 ? 1 : ns(s - 1) * rads[s - 1]; } \
   };
+SFFT_LEAF_SHAPE(6, 2, 3, 2)
+SFFT_LEAF_SHAPE(8, 2, 4, 2)
+SFFT_LEAF_SHAPE(10, 2, 5, 2)
+SFFT_LEAF_SHAPE(12, 4, 3, 4)
+SFFT_LEAF_SHAPE(24, 8, 3, 2, 4)
 SFFT_LEAF_SHAPE(32, 8, 4, 2, 4)
+SFFT_LEAF_SHAPE(40, 8, 5, 8)
+SFFT_LEAF_SHAPE(80, 16, 5, 4, 4)
+SFFT_LEAF_SHAPE(160, 32, 5, 4, 8)
+SFFT_LEAF_SHAPE(192, 32, 2, 4, 8, 3)
+SFFT_LEAF_SHAPE(768, 128, 2, 4, 4, 8, 3)
 SFFT_LEAF_SHAPE(48, 8, 2, 4, 2, 3)
 SFFT_LEAF_SHAPE(64, 16, 4, 4, 4)
 SFFT_LEAF_SHAPE(96, 16, 2, 4, 4, 3)
-SFFT_LEAF_SHAPE(128, 32, 4, 8, 4)
-SFFT_LEAF_SHAPE(256, 64, 4, 16, 4)
+SFFT_LEAF_SHAPE(128, 32, 4, 4, 2, 4)
+SFFT_LEAF_SHAPE(256, 64, 4, 4, 4, 4)
 SFFT_LEAF_SHAPE(384, 64, 2, 4, 4, 4, 3)
 SFFT_LEAF_SHAPE(512, 64, 8, 8, 8)
 SFFT_LEAF_SHAPE(1024, 128, 8, 8, 4, 4)
@@ -253,11 +263,39 @@ template <bool WS> __device__ __forceinline__ void xsync() {
   }
 }
 
+// Twiddles of every stage s >= 1 that a lane's butterflies need. They depend
+// only on the lane index t, so a kernel loads them once from the FP64-made
+// table and reuses them for all its pencils, instead of fetching them from
+// memory inside every stage.
+template <typename C, typename Sh> struct LaneTw {
+  static constexpr int per(int s) { return (Sh::L / Sh::rad(s) + Sh::T - 1) / Sh::T; }
+  static constexpr int off(int s) { return s <= 1 ? 0 : off(s - 1) + per(s - 1) * (Sh::rad(s - 1) - 1); }
+  static constexpr int N = Sh::S <= 1 ? 1 : off(Sh::S);
+  C w[N];
+
+  template <int s> __device__ __forceinline__ void load_stage(int t, const C* tw) {
+    if constexpr (s < Sh::S) {
+      constexpr int R = Sh::rad(s), Ns = Sh::ns(s), NB = Sh::L / R, TWS = Sh::L / (Ns * R);
+#pragma unroll
+      for (int u = 0; u < per(s); ++u) {
+        const int j = t + Sh::T * u;
+        const int k = (j < NB ? j : 0) % Ns;
+#pragma unroll
+        for (int r = 1; r < R; ++r) w[off(s) + u * (R - 1) + r - 1] = tw[2 * (r * k * TWS)];
+      }
+      load_stage<s + 1>(t, tw);
+    }
+  }
+  __device__ __forceinline__ void load(int t, const C* tw) {
+    if constexpr (Sh::S > 1) load_stage<1>(t, tw);
+  }
+};
+
 // One stage (and, recursively, the following ones) of a pencil transform.
 // lds: this pencil's LDS row, element k at lds[k * kst]. All lanes of the
 // workgroup (WS = false) or of the wavefront (WS = true) call this together.
 template <typename C, typename Sh, int DIR, int s, bool WS>
-__device__ __forceinline__ void fft_stage(C (&home)[Sh::E], C* lds, int kst, int t, const C* tw) {
+__device__ __forceinline__ void fft_stage(C (&home)[Sh::E], C* lds, int kst, int t, const LaneTw<C, Sh>& lt) {
   constexpr int L = Sh::L, T = Sh::T, S = Sh::S;
   constexpr int R = Sh::rad(s);
   constexpr int Ns = Sh::ns(s);
@@ -266,7 +304,6 @@ __device__ __forceinline__ void fft_stage(C (&home)[Sh::E], C* lds, int kst, int
   constexpr bool EVEN = (NB % T) == 0;
   constexpr bool FIRST_REG = (s == 0) && EVEN;
   constexpr bool LAST_REG = (s == S - 1) && EVEN;
-  constexpr int TWS = L / (Ns * R);  // twiddle stride in W_L units
 
   if constexpr (s == 0 && !FIRST_REG) {
 #pragma unroll
@@ -285,12 +322,10 @@ __device__ __forceinline__ void fft_stage(C (&home)[Sh::E], C* lds, int kst, int
         else v[u][r] = lds[(j + r * NB) * kst];
       }
       if constexpr (s > 0) {
-        const int k = j % Ns;
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          C w = tw[2 * (r * k * TWS)];
-          if constexpr (DIR > 0) w.y = -w.y;
-          v[u][r] = cmul(v[u][r], w);
+          const C w = lt.w[LaneTw<C, Sh>::off(s) + u * (R - 1) + r - 1];
+          v[u][r] = (DIR > 0) ? cmulc(v[u][r], w) : cmul(v[u][r], w);
         }
       }
       dft<R, DIR>(v[u]);
@@ -322,15 +357,15 @@ __device__ __forceinline__ void fft_stage(C (&home)[Sh::E], C* lds, int kst, int
       xsync<WS>();
     }
   }
-  if constexpr (s + 1 < S) fft_stage<C, Sh, DIR, s + 1, WS>(home, lds, kst, t, tw);
+  if constexpr (s + 1 < S) fft_stage<C, Sh, DIR, s + 1, WS>(home, lds, kst, t, lt);
 }
 
 // Unnormalised DFT of one pencil (DIR = -1 forward, +1 inverse).
 template <int DIR, typename Sh, bool WS = false, typename C>
-__device__ __forceinline__ void fft_pencil(C (&home)[Sh::E], C* lds, int kst, int t, const C* tw) {
+__device__ __forceinline__ void fft_pencil(C (&home)[Sh::E], C* lds, int kst, int t, const LaneTw<C, Sh>& lt) {
   static_assert(shape_ok<Sh>(), "bad radix plan");
   static_assert(!WS || (64 % Sh::T) == 0, "wave sync needs whole pencils per wavefront");
-  fft_stage<C, Sh, DIR, 0, WS>(home, lds, kst, t, tw);
+  fft_stage<C, Sh, DIR, 0, WS>(home, lds, kst, t, lt);
 }
 
 }  // namespace sfft

@@ -376,6 +376,10 @@ sfft_status run_leaf(const sfft_plan_s* p, const void* in, void* out, int64_t in
   a.npen = p->npen;
   a.nrhs = nrhs;
   a.ntiles = p->ntiles;
+  // right-hand sides per workgroup: they share each symbol load
+  int rb = 1;
+  while (rb < nrhs && rb < o->RBMAX) rb *= 2;
+  a.rb = rb;
   sfft::pass_fn f;
   if (p->compressed) {
     a.sym = p->sym;
