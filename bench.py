@@ -204,6 +204,58 @@ def bench_large(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_batch(args):
+    """Uneven-grid batch: 48x40x32, 64x64x32, 96x80x64 and 512x384, each with
+    scalar (i.i.d.) and 3x3 Green blocks, 8 right-hand sides each (64 in all),
+    complex64. One step = the whole batch, issued either as one apply per
+    problem or as one sfft_apply_multi graph launch."""
+    import numpy as np
+    import torch
+    import workloads as wl
+    import paper_2406_17981_amd as sf
+    probs = wl.batch_problems()
+    plans, xs, ys, tuned = [], [], [], []
+    for pr in probs:
+        plan = sf.Plan(pr["n"], pr["b"], torch.from_numpy(pr["coeffs"]).cuda(), dtype="c64",
+                       max_nrhs=pr["x"].shape[0])
+        tuned.append(plan.autotune(pr["x"].shape[0], use_cache=False))
+        plans.append(plan)
+        xs.append(torch.from_numpy(pr["x"]).to(torch.complex64).cuda())
+        ys.append(torch.empty_like(xs[-1]))
+    nrhs_total = sum(x.shape[0] for x in xs)
+    wss = [p.alloc_workspace(x.shape[0]) for p, x in zip(plans, xs)]
+
+    def seq():
+        for p, x, y, w in zip(plans, xs, ys, wss):
+            p.apply(x, y, w)
+
+    wsm = torch.empty(max(sf.workspace_size_multi(plans, [x.shape[0] for x in xs]), 1), dtype=torch.uint8,
+                      device="cuda")
+
+    def multi():
+        sf.apply_multi(plans, xs, ys, workspace=wsm)
+
+    res = {}
+    for name, fn in (("sequential_applies", seq), ("apply_multi_graph", multi)):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        res[name] = dict(ms_per_batch=round(ms, 4), matvecs_per_s=round(nrhs_total * 1e3 / ms, 1))
+        log(f"[batch {name}] {ms:.3f} ms per batch of {nrhs_total} RHS")
+    line = {"workload": "batch-8-problems-64rhs-c64",
+            "problems": [dict(grid=list(pr["n"]), b=pr["b"], nrhs=int(pr["x"].shape[0]),
+                              schedule=["auto", "breadth", "depth"][p.info()["schedule"]], tuned_us=round(t, 1))
+                         for pr, p, t in zip(probs, plans, tuned)],
+            "steps": args.steps, "warmup": args.warmup, "results": res,
+            "graph_speedup": round(res["sequential_applies"]["ms_per_batch"] / res["apply_multi_graph"]["ms_per_batch"], 3)}
+    print(json.dumps(line), flush=True)
+
+
 def time_plan(plan, x, y, ws, steps, warmup, profile_leaf=False):
     import torch
     for _ in range(warmup):
@@ -257,8 +309,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variants", default="all", choices=["all", "headline"])
     ap.add_argument("--pmc-probe", action="store_true", help="workload for rocprofv3 --pmc runs")
-    ap.add_argument("--workload", default="green64", choices=["green64", "large"],
-                    help="large: the 256x256x128 8-RHS parity configuration, split vs embed")
+    ap.add_argument("--workload", default="green64", choices=["green64", "large", "batch"],
+                    help="large: the 256x256x128 8-RHS configuration, split vs embed; "
+                         "batch: 8 uneven-grid problems, 64 RHS, one graph")
     ap.add_argument("--pmc-summarize", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON"))
     args = ap.parse_args()
 
@@ -270,6 +323,9 @@ def main():
         return
     if args.workload == "large":
         bench_large(args)
+        return
+    if args.workload == "batch":
+        bench_batch(args)
         return
 
     if args.gpus != 1:

@@ -126,9 +126,14 @@ sfft_status sfft_apply(sfft_plan plan, const void* x, void* y, int64_t nrhs, voi
                        size_t ws_bytes, void* stream);
 
 /* Several independent products in one call: problem i is plans[i] applied to
- * x[i] -> y[i] with nrhs[i] right-hand sides. Host arrays of device pointers.
- * Problems whose plans share level sizes, dtype and method are fused into the
- * same kernel launches. workspace: at least sfft_workspace_size_multi bytes. */
+ * x[i] -> y[i] with nrhs[i] right-hand sides (host arrays of device
+ * pointers; workspace at least sfft_workspace_size_multi bytes, problem i at
+ * the 256-byte aligned offset of the preceding problems' sizes). The batch
+ * is captured once into a HIP graph with every problem's chain on its own
+ * forked stream (so problems run side by side) and replayed by one graph
+ * launch on `stream`; the instantiated graph is cached for the same
+ * arguments and dropped when one of its plans is destroyed. SFFT_NO_GRAPH=1
+ * in the environment issues the problems one after another instead. */
 sfft_status sfft_workspace_size_multi(int nprob, const sfft_plan* plans, const int64_t* nrhs,
                                       size_t* bytes);
 sfft_status sfft_apply_multi(int nprob, const sfft_plan* plans, const void* const* x,
@@ -136,6 +141,19 @@ sfft_status sfft_apply_multi(int nprob, const sfft_plan* plans, const void* cons
                              void* stream);
 
 sfft_status sfft_plan_info(sfft_plan plan, sfft_info* info);
+
+/* Times the plan's candidate schedules (breadth-first and depth-first for
+ * SFFT_SPLIT with d > 1) and leaf right-hand-side groupings (1, 2, 4, 8 per
+ * workgroup, within the kernel's limit) at nrhs right-hand sides on `stream`,
+ * and keeps the fastest in the plan (sfft_workspace_size follows the chosen
+ * schedule). With use_cache != 0 a result stored for the same device,
+ * method, dtype, block size, grid, storage and nrhs in the JSON-lines file
+ * named by SFFT_TUNE_CACHE (default $HOME/.cache/sfft_autotune.jsonl) is
+ * reused without timing, and new results are appended to it. Allocates and
+ * frees its own scratch vectors; must not run concurrently with applies of
+ * the same plan. best_us (may be NULL) receives the best time in
+ * microseconds per apply, or -1 when the cache answered. */
+sfft_status sfft_plan_autotune(sfft_plan plan, int64_t nrhs, int use_cache, void* stream, double* best_us);
 
 /* Kernel classes for the profiling hooks. */
 typedef enum {

@@ -26,6 +26,7 @@ EXPORTS = [
     "sfft_plan_create", "sfft_workspace_size", "sfft_apply", "sfft_workspace_size_multi",
     "sfft_apply_multi", "sfft_plan_info", "sfft_plan_destroy", "sfft_status_string",
     "sfft_last_error", "sfft_length_supported", "sfft_profile_enable", "sfft_profile_read",
+    "sfft_plan_autotune",
 ]
 KIND_FORWARD, KIND_LEAF, KIND_INVERSE, KIND_COPY = range(4)
 
@@ -67,6 +68,7 @@ def _load():
     lib.sfft_length_supported.argtypes = [i64]
     lib.sfft_profile_enable.argtypes = [vp, C.c_uint]
     lib.sfft_profile_read.argtypes = [vp, C.c_int, C.POINTER(C.c_double), P64, C.c_int]
+    lib.sfft_plan_autotune.argtypes = [vp, i64, C.c_int, vp, C.POINTER(C.c_double)]
     for name in EXPORTS:
         fn = getattr(lib, name)
         if fn.restype is C.c_int or fn.restype is None:

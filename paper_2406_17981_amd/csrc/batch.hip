@@ -1,0 +1,351 @@
+// Multi-problem batches and the autotuner.
+//
+// sfft_apply_multi runs independent products (uneven grids, block sizes,
+// right-hand-side counts) as one HIP graph: every problem's pass chain is
+// captured on its own forked stream, so the problems' kernels are free to run
+// side by side, and the whole batch is replayed with a single graph launch.
+// Instantiated graphs are cached per argument set (plans, vectors, workspace);
+// a plan's graphs are dropped when the plan is destroyed.
+//
+// sfft_plan_autotune times the candidate schedules (breadth-first / depth-
+// first) and leaf right-hand-side groupings of a plan on the device and keeps
+// the fastest; results persist in a JSON-lines cache file (SFFT_TUNE_CACHE,
+// default $HOME/.cache/sfft_autotune.jsonl) keyed by device architecture,
+// method, dtype, block size, grid, symbol storage and right-hand sides.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "plan_internal.hpp"
+
+namespace {
+
+constexpr int kSideStreams = 4;
+constexpr size_t kMaxGraphs = 32;
+
+struct GraphEntry {
+  std::vector<uintptr_t> key;
+  std::vector<const sfft_plan_s*> plans;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  uint64_t last_use = 0;
+};
+
+std::mutex g_mu;
+std::vector<GraphEntry> g_graphs;
+uint64_t g_tick = 0;
+hipStream_t g_cap = nullptr;
+hipStream_t g_side[kSideStreams] = {nullptr};
+int g_dev = -1;
+
+void destroy_entry(GraphEntry& e) {
+  if (e.exec) (void)hipGraphExecDestroy(e.exec);
+  if (e.graph) (void)hipGraphDestroy(e.graph);
+  e.exec = nullptr;
+  e.graph = nullptr;
+}
+
+sfft_status ensure_streams() {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return sfft_rt_hip_fail(e, "hipGetDevice");
+  if (g_dev == dev && g_cap) return SFFT_OK;
+  if (g_cap) {
+    (void)hipStreamDestroy(g_cap);
+    for (auto& s : g_side) (void)hipStreamDestroy(s);
+  }
+  e = hipStreamCreateWithFlags(&g_cap, hipStreamNonBlocking);
+  if (e != hipSuccess) return sfft_rt_hip_fail(e, "capture stream");
+  for (auto& s : g_side) {
+    e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e != hipSuccess) return sfft_rt_hip_fail(e, "side stream");
+  }
+  g_dev = dev;
+  return SFFT_OK;
+}
+
+bool graphs_enabled() {
+  const char* v = std::getenv("SFFT_NO_GRAPH");
+  return !(v && v[0] && v[0] != '0');
+}
+
+// Captures the batch on g_cap with one forked stream per problem.
+sfft_status capture(int nprob, const sfft_plan* plans, const void* const* x, void* const* y, const int64_t* nrhs,
+                    char* ws, const std::vector<size_t>& off, const std::vector<size_t>& wsz, hipGraph_t* out) {
+  std::vector<unsigned> masks(nprob);
+  for (int i = 0; i < nprob; ++i) {  // profiling event pairs are not captured
+    masks[i] = plans[i]->prof_mask;
+    plans[i]->prof_mask = 0;
+  }
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> done(nprob, nullptr);
+  sfft_status s = SFFT_OK;
+  hipError_t e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+  for (int i = 0; i < nprob && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&done[i], hipEventDisableTiming);
+  if (e != hipSuccess) s = sfft_rt_hip_fail(e, "batch events");
+  bool capturing = false;
+  if (s == SFFT_OK) {
+    e = hipStreamBeginCapture(g_cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) s = sfft_rt_hip_fail(e, "begin capture");
+    else capturing = true;
+  }
+  if (s == SFFT_OK) {
+    e = hipEventRecord(fork, g_cap);
+    if (e != hipSuccess) s = sfft_rt_hip_fail(e, "fork");
+  }
+  for (int i = 0; i < nprob && s == SFFT_OK; ++i) {
+    hipStream_t si = g_side[i % kSideStreams];
+    e = hipStreamWaitEvent(si, fork, 0);
+    if (e != hipSuccess) {
+      s = sfft_rt_hip_fail(e, "fork wait");
+      break;
+    }
+    s = sfft_rt_apply_one(plans[i], x[i], y[i], nrhs[i], wsz[i] ? ws + off[i] : nullptr, wsz[i], si);
+    if (s != SFFT_OK) break;
+    e = hipEventRecord(done[i], si);
+    if (e != hipSuccess) s = sfft_rt_hip_fail(e, "join record");
+  }
+  for (int i = 0; i < nprob && s == SFFT_OK; ++i) {
+    e = hipStreamWaitEvent(g_cap, done[i], 0);
+    if (e != hipSuccess) s = sfft_rt_hip_fail(e, "join wait");
+  }
+  if (capturing) {
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(g_cap, &g);
+    if (s == SFFT_OK && e != hipSuccess) s = sfft_rt_hip_fail(e, "end capture");
+    if (s == SFFT_OK) *out = g;
+    else if (g) (void)hipGraphDestroy(g);
+  }
+  if (fork) (void)hipEventDestroy(fork);
+  for (auto ev : done)
+    if (ev) (void)hipEventDestroy(ev);
+  for (int i = 0; i < nprob; ++i) plans[i]->prof_mask = masks[i];
+  return s;
+}
+
+std::string tune_cache_path() {
+  const char* p = std::getenv("SFFT_TUNE_CACHE");
+  if (p && p[0]) return p;
+  const char* h = std::getenv("HOME");
+  return std::string(h ? h : ".") + "/.cache/sfft_autotune.jsonl";
+}
+
+std::string tune_key(const sfft_plan_s* p, int64_t nrhs) {
+  hipDeviceProp_t prop;
+  int dev = 0;
+  std::string arch = "unknown";
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
+  std::ostringstream k;
+  k << arch << "|" << (p->method == SFFT_SPLIT ? "split" : "embed") << "|" << (p->dtype == SFFT_C64 ? "c64" : "c128")
+    << "|b" << p->b << "|";
+  for (int l = 0; l < p->d; ++l) k << (l ? "x" : "") << p->n[l];
+  k << "|nrhs" << nrhs << "|mirror" << p->compressed;
+  return k.str();
+}
+
+bool tune_lookup(const std::string& key, int* sched, int* rb) {
+  std::ifstream f(tune_cache_path());
+  std::string line;
+  bool found = false;
+  while (std::getline(f, line)) {  // later lines win
+    const std::string tag = "\"key\": \"" + key + "\"";
+    if (line.find(tag) == std::string::npos) continue;
+    int s = 0, r = 0;
+    const size_t ps = line.find("\"sched\": "), pr = line.find("\"rb\": ");
+    if (ps == std::string::npos || pr == std::string::npos) continue;
+    s = std::atoi(line.c_str() + ps + 9);
+    r = std::atoi(line.c_str() + pr + 6);
+    if (s >= SFFT_SCHED_BREADTH && s <= SFFT_SCHED_DEPTH && r >= 0) {
+      *sched = s;
+      *rb = r;
+      found = true;
+    }
+  }
+  return found;
+}
+
+void tune_store(const std::string& key, int sched, int rb, double us) {
+  std::ofstream f(tune_cache_path(), std::ios::app);
+  if (!f) return;  // a read-only home leaves tuning per process
+  f << "{\"key\": \"" << key << "\", \"sched\": " << sched << ", \"rb\": " << rb << ", \"us\": " << us << "}\n";
+}
+
+}  // namespace
+
+void sfft_rt_forget_plan(const sfft_plan_s* p) {
+  std::lock_guard<std::mutex> g(g_mu);
+  for (size_t i = 0; i < g_graphs.size();) {
+    bool uses = false;
+    for (auto q : g_graphs[i].plans) uses |= (q == p);
+    if (uses) {
+      destroy_entry(g_graphs[i]);
+      g_graphs.erase(g_graphs.begin() + i);
+    } else {
+      ++i;
+    }
+  }
+}
+
+extern "C" {
+
+sfft_status sfft_apply_multi(int nprob, const sfft_plan* plans, const void* const* x, void* const* y,
+                             const int64_t* nrhs, void* workspace, size_t ws_bytes, void* stream) {
+  if (nprob < 0 || (nprob > 0 && (!plans || !x || !y || !nrhs))) return sfft_rt_fail(SFFT_INVALID_ARG, "null argument");
+  size_t need = 0;
+  sfft_status s = sfft_workspace_size_multi(nprob, plans, nrhs, &need);
+  if (s != SFFT_OK) return s;
+  if (need > 0 && (!workspace || ws_bytes < need)) return sfft_rt_fail(SFFT_INVALID_ARG, "workspace too small");
+  std::vector<size_t> off(nprob), wsz(nprob);
+  size_t o = 0;
+  for (int i = 0; i < nprob; ++i) {
+    wsz[i] = sfft_rt_align256(sfft_rt_workspace_elems(plans[i], nrhs[i]) * plans[i]->esz);
+    off[i] = o;
+    o += wsz[i];
+  }
+  hipStream_t st = (hipStream_t)stream;
+  if (nprob <= 1 || !graphs_enabled()) {
+    for (int i = 0; i < nprob; ++i) {
+      s = sfft_rt_apply_one(plans[i], x[i], y[i], nrhs[i], wsz[i] ? (char*)workspace + off[i] : nullptr, wsz[i], st);
+      if (s != SFFT_OK) return s;
+    }
+    return SFFT_OK;
+  }
+  std::vector<uintptr_t> key;
+  key.push_back((uintptr_t)nprob);
+  key.push_back((uintptr_t)workspace);
+  for (int i = 0; i < nprob; ++i) {
+    key.push_back((uintptr_t)plans[i]);
+    key.push_back((uintptr_t)x[i]);
+    key.push_back((uintptr_t)y[i]);
+    key.push_back((uintptr_t)nrhs[i]);
+    key.push_back((uintptr_t)plans[i]->sched);
+    key.push_back((uintptr_t)plans[i]->rb_pref);
+  }
+  std::lock_guard<std::mutex> g(g_mu);
+  if ((s = ensure_streams()) != SFFT_OK) return s;
+  for (auto& e : g_graphs) {
+    if (e.key == key) {
+      e.last_use = ++g_tick;
+      hipError_t he = hipGraphLaunch(e.exec, st);
+      if (he != hipSuccess) return sfft_rt_hip_fail(he, "graph launch");
+      return SFFT_OK;
+    }
+  }
+  // argument checks happen outside capture so an invalid call never starts one
+  for (int i = 0; i < nprob; ++i) {
+    if (!plans[i] || !x[i] || !y[i] || nrhs[i] < 1) return sfft_rt_fail(SFFT_INVALID_ARG, "bad problem entry");
+  }
+  GraphEntry ent;
+  ent.key = key;
+  for (int i = 0; i < nprob; ++i) ent.plans.push_back(plans[i]);
+  s = capture(nprob, plans, x, y, nrhs, (char*)workspace, off, wsz, &ent.graph);
+  if (s != SFFT_OK) return s;
+  hipError_t he = hipGraphInstantiate(&ent.exec, ent.graph, nullptr, nullptr, 0);
+  if (he != hipSuccess) {
+    destroy_entry(ent);
+    return sfft_rt_hip_fail(he, "graph instantiate");
+  }
+  if (g_graphs.size() >= kMaxGraphs) {  // evict the least recently used
+    size_t victim = 0;
+    for (size_t i = 1; i < g_graphs.size(); ++i)
+      if (g_graphs[i].last_use < g_graphs[victim].last_use) victim = i;
+    destroy_entry(g_graphs[victim]);
+    g_graphs.erase(g_graphs.begin() + victim);
+  }
+  ent.last_use = ++g_tick;
+  g_graphs.push_back(ent);
+  he = hipGraphLaunch(g_graphs.back().exec, st);
+  if (he != hipSuccess) return sfft_rt_hip_fail(he, "graph launch");
+  return SFFT_OK;
+}
+
+sfft_status sfft_plan_autotune(sfft_plan plan, int64_t nrhs, int use_cache, void* stream, double* best_us) {
+  if (!plan) return sfft_rt_fail(SFFT_INVALID_ARG, "plan is null");
+  if (nrhs < 1) return sfft_rt_fail(SFFT_INVALID_ARG, "nrhs must be >= 1");
+  hipStream_t st = (hipStream_t)stream;
+  const std::string key = tune_key(plan, nrhs);
+  int sched = 0, rb = 0;
+  if (use_cache && tune_lookup(key, &sched, &rb)) {
+    if (plan->method == SFFT_SPLIT) plan->sched = sched;
+    plan->rb_pref = rb;
+    if (best_us) *best_us = -1.0;
+    return SFFT_OK;
+  }
+  std::vector<std::pair<int, int>> cand;
+  std::vector<int> scheds;
+  if (plan->method == SFFT_SPLIT && plan->d > 1) scheds = {SFFT_SCHED_BREADTH, SFFT_SCHED_DEPTH};
+  else scheds = {plan->sched};
+  const int rbmax = sfft_rt_leaf_rbmax(plan);
+  for (int sc : scheds)
+    for (int r = 1; r <= rbmax && (r == 1 || r <= 2 * nrhs - 1); r *= 2) cand.push_back({sc, r});
+  const size_t vbytes = (size_t)(nrhs * plan->b * plan->s) * plan->esz;
+  const int old_sched = plan->sched, old_rb = plan->rb_pref;
+  size_t wsmax = 0;
+  for (int sc : scheds) {
+    plan->sched = sc;
+    const size_t w = sfft_rt_workspace_elems(plan, nrhs) * plan->esz;
+    wsmax = w > wsmax ? w : wsmax;
+  }
+  plan->sched = old_sched;
+  void *x = nullptr, *y = nullptr, *ws = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  sfft_status s = SFFT_OK;
+  hipError_t he = hipMalloc(&x, vbytes);
+  if (he == hipSuccess) he = hipMalloc(&y, vbytes);
+  if (he == hipSuccess && wsmax) he = hipMalloc(&ws, wsmax);
+  if (he == hipSuccess) he = hipMemsetAsync(x, 0, vbytes, st);
+  if (he == hipSuccess) he = hipEventCreate(&e0);
+  if (he == hipSuccess) he = hipEventCreate(&e1);
+  if (he != hipSuccess) s = sfft_rt_hip_fail(he, "autotune buffers");
+  double best = 1e300;
+  int bs = old_sched, br = old_rb;
+  for (auto& c : cand) {
+    if (s != SFFT_OK) break;
+    plan->sched = c.first;
+    plan->rb_pref = c.second;
+    s = sfft_rt_apply_one(plan, x, y, nrhs, ws, wsmax, st);  // warm-up
+    const int reps = 3;
+    if (s == SFFT_OK) he = hipEventRecord(e0, st);
+    for (int i = 0; i < reps && s == SFFT_OK; ++i) s = sfft_rt_apply_one(plan, x, y, nrhs, ws, wsmax, st);
+    if (s != SFFT_OK) break;
+    he = hipEventRecord(e1, st);
+    if (he == hipSuccess) he = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+    if (he != hipSuccess) {
+      s = sfft_rt_hip_fail(he, "autotune timing");
+      break;
+    }
+    const double us = 1e3 * ms / reps;
+    if (us < best) {
+      best = us;
+      bs = c.first;
+      br = c.second;
+    }
+  }
+  (void)hipStreamSynchronize(st);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (x) (void)hipFree(x);
+  if (y) (void)hipFree(y);
+  if (ws) (void)hipFree(ws);
+  if (s != SFFT_OK) {
+    plan->sched = old_sched;
+    plan->rb_pref = old_rb;
+    return s;
+  }
+  plan->sched = bs;
+  plan->rb_pref = br;
+  if (use_cache) tune_store(key, bs, br, best);
+  if (best_us) *best_us = best;
+  return SFFT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,80 @@
+// Internal plan structure and runtime entry points shared by runtime.hip
+// (plan creation, schedules, C ABI) and batch.hip (graph-batched multi-problem
+// apply, autotuner). Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/sfft.h"
+#include "axis_kernels.hpp"
+
+constexpr int kMaxD = 6;
+
+// A plan: level sizes, block size, dtype, method, schedule, FP64-generated
+// symbols in the compute dtype and per-level twiddle tables (device memory
+// owned by the plan), plus an optional workspace pool and profiling events.
+struct sfft_plan_s {
+  int d = 0;
+  int64_t n[kMaxD] = {0};
+  int b = 1;
+  int dtype = SFFT_C64;
+  int method = SFFT_SPLIT;
+  int sched = SFFT_SCHED_BREADTH;
+  int compressed = 0;
+  int64_t max_nrhs = 1;
+  int64_t s = 1;     // grid points
+  size_t esz = 8;    // bytes per complex entry
+  int64_t L[kMaxD];  // pencil length per level (n_l split, 2 n_l embed)
+  const sfft::AxisOps* ops[kMaxD] = {nullptr};
+  void* tw[kMaxD] = {nullptr};
+  void* sym = nullptr;
+  size_t sym_bytes = 0;
+  int64_t sym_bs = 0;  // symbol entries per leaf branch prefix
+  int64_t ntiles = 0;  // leaf tiles per component per rhs
+  int64_t npen = 0;    // leaf pencils per component per rhs
+  // mirrored symbol storage (compressed = 1)
+  int64_t mst[kMaxD] = {0};
+  int64_t mcomp = 0;
+  uint64_t odd_bits = 0;
+  // right-hand sides per leaf workgroup chosen by the autotuner (0: automatic)
+  int rb_pref = 0;
+  size_t table_bytes = 0;
+  std::mutex pool_mu;
+  void* pool = nullptr;
+  size_t pool_bytes = 0;
+  // profiling hooks: event pairs around launches of the kinds in prof_mask
+  unsigned prof_mask = 0;
+  struct Rec {
+    int kind;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> prof_recs;
+  std::vector<hipEvent_t> prof_free;
+
+  ~sfft_plan_s() {
+    for (auto& r : prof_recs) {
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+    for (auto e : prof_free) (void)hipEventDestroy(e);
+    for (int l = 0; l < kMaxD; ++l)
+      if (tw[l]) (void)hipFree(tw[l]);
+    if (sym) (void)hipFree(sym);
+    if (pool) (void)hipFree(pool);
+  }
+};
+
+sfft_status sfft_rt_fail(sfft_status s, const std::string& msg);
+sfft_status sfft_rt_hip_fail(hipError_t e, const char* what);
+size_t sfft_rt_workspace_elems(const sfft_plan_s* p, int64_t nrhs);
+sfft_status sfft_rt_apply_one(sfft_plan_s* p, const void* x, void* y, int64_t nrhs, void* ws, size_t ws_bytes,
+                              hipStream_t st);
+int sfft_rt_leaf_rbmax(const sfft_plan_s* p);
+// drops cached graphs that reference the plan (called before it is freed)
+void sfft_rt_forget_plan(const sfft_plan_s* p);
+
+inline size_t sfft_rt_align256(size_t x) { return (x + 255) & ~size_t(255); }

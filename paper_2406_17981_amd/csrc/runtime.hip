@@ -21,8 +21,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/sfft.h"
-#include "axis_kernels.hpp"
+#include "plan_internal.hpp"
 
 using sfft::AxisOps;
 using sfft::PassArgs;
@@ -32,8 +31,6 @@ using sfft::PassArgs;
 #undef SFFT_X
 
 namespace {
-
-constexpr int kMaxD = 6;
 
 const AxisOps* find_ops(int dtype, int64_t L) {
   switch (L) {
@@ -233,57 +230,6 @@ unsigned grid_for(int64_t total, int block = 256) {
 
 }  // namespace
 
-// ---------------------------------------------------------------------------
-// Plan
-// ---------------------------------------------------------------------------
-struct sfft_plan_s {
-  int d = 0;
-  int64_t n[kMaxD] = {0};
-  int b = 1;
-  int dtype = SFFT_C64;
-  int method = SFFT_SPLIT;
-  int sched = SFFT_SCHED_BREADTH;
-  int compressed = 0;
-  int64_t max_nrhs = 1;
-  int64_t s = 1;     // grid points
-  size_t esz = 8;    // bytes per complex entry
-  int64_t L[kMaxD];  // pencil length per level (n_l split, 2 n_l embed)
-  const AxisOps* ops[kMaxD] = {nullptr};
-  void* tw[kMaxD] = {nullptr};
-  void* sym = nullptr;
-  size_t sym_bytes = 0;
-  int64_t sym_bs = 0;  // symbol entries per leaf branch prefix
-  int64_t ntiles = 0;  // leaf tiles per component per rhs
-  int64_t npen = 0;    // leaf pencils per component per rhs
-  // mirrored symbol storage (compressed = 1)
-  int64_t mst[kMaxD] = {0};
-  int64_t mcomp = 0;
-  uint64_t odd_bits = 0;
-  size_t table_bytes = 0;
-  std::mutex pool_mu;
-  void* pool = nullptr;
-  size_t pool_bytes = 0;
-  // profiling hooks: event pairs around launches of the kinds in prof_mask
-  unsigned prof_mask = 0;
-  struct Rec {
-    int kind;
-    hipEvent_t a, b;
-  };
-  std::vector<Rec> prof_recs;
-  std::vector<hipEvent_t> prof_free;
-
-  ~sfft_plan_s() {
-    for (auto& r : prof_recs) {
-      (void)hipEventDestroy(r.a);
-      (void)hipEventDestroy(r.b);
-    }
-    for (auto e : prof_free) (void)hipEventDestroy(e);
-    for (int l = 0; l < kMaxD; ++l)
-      if (tw[l]) (void)hipFree(tw[l]);
-    if (sym) (void)hipFree(sym);
-    if (pool) (void)hipFree(pool);
-  }
-};
 
 namespace {
 
@@ -296,8 +242,6 @@ size_t workspace_elems(const sfft_plan_s* p, int64_t nrhs) {
   if (p->sched == SFFT_SCHED_DEPTH) return (size_t)((p->d - 1) * V);
   return (size_t)(((int64_t(1) << p->d) - 2) * V);
 }
-
-size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Pass geometry of level l (0-based) for vectors (nv, L_0, ..., L_{d-1}).
 void level_geom(const sfft_plan_s* p, int l, int64_t nv, int64_t& outer, int64_t& inner) {
@@ -378,7 +322,11 @@ sfft_status run_leaf(const sfft_plan_s* p, const void* in, void* out, int64_t in
   a.ntiles = p->ntiles;
   // right-hand sides per workgroup: they share each symbol load
   int rb = 1;
-  while (rb < nrhs && rb < o->RBMAX) rb *= 2;
+  if (p->rb_pref > 0) {
+    rb = p->rb_pref < o->RBMAX ? p->rb_pref : o->RBMAX;
+  } else {
+    while (rb < nrhs && rb < o->RBMAX) rb *= 2;
+  }
   a.rb = rb;
   sfft::pass_fn f;
   if (p->compressed) {
@@ -667,6 +615,16 @@ sfft_status apply_one(sfft_plan_s* p, const void* x, void* y, int64_t nrhs, void
 
 }  // namespace
 
+// Entry points shared with the batched / autotuning code (plan_internal.hpp).
+sfft_status sfft_rt_fail(sfft_status s, const std::string& msg) { return fail(s, msg); }
+sfft_status sfft_rt_hip_fail(hipError_t e, const char* what) { return hip_fail(e, what); }
+size_t sfft_rt_workspace_elems(const sfft_plan_s* p, int64_t nrhs) { return workspace_elems(p, nrhs); }
+sfft_status sfft_rt_apply_one(sfft_plan_s* p, const void* x, void* y, int64_t nrhs, void* ws, size_t ws_bytes,
+                              hipStream_t st) {
+  return apply_one(p, x, y, nrhs, ws, ws_bytes, st);
+}
+int sfft_rt_leaf_rbmax(const sfft_plan_s* p) { return p->ops[p->d - 1]->RBMAX; }
+
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
@@ -799,26 +757,9 @@ sfft_status sfft_workspace_size_multi(int nprob, const sfft_plan* plans, const i
   size_t total = 0;
   for (int i = 0; i < nprob; ++i) {
     if (!plans[i] || nrhs[i] < 1) return fail(SFFT_INVALID_ARG, "bad problem entry");
-    total += align256(workspace_elems(plans[i], nrhs[i]) * plans[i]->esz);
+    total += sfft_rt_align256(workspace_elems(plans[i], nrhs[i]) * plans[i]->esz);
   }
   *bytes = total;
-  return SFFT_OK;
-}
-
-sfft_status sfft_apply_multi(int nprob, const sfft_plan* plans, const void* const* x, void* const* y,
-                             const int64_t* nrhs, void* workspace, size_t ws_bytes, void* stream) {
-  if (nprob < 0 || (nprob > 0 && (!plans || !x || !y || !nrhs))) return fail(SFFT_INVALID_ARG, "null argument");
-  size_t need = 0;
-  sfft_status s = sfft_workspace_size_multi(nprob, plans, nrhs, &need);
-  if (s != SFFT_OK) return s;
-  if (need > 0 && (!workspace || ws_bytes < need)) return fail(SFFT_INVALID_ARG, "workspace too small");
-  size_t off = 0;
-  for (int i = 0; i < nprob; ++i) {
-    const size_t w = align256(workspace_elems(plans[i], nrhs[i]) * plans[i]->esz);
-    s = apply_one(plans[i], x[i], y[i], nrhs[i], w ? (char*)workspace + off : nullptr, w, (hipStream_t)stream);
-    if (s != SFFT_OK) return s;
-    off += w;
-  }
   return SFFT_OK;
 }
 
@@ -877,6 +818,7 @@ sfft_status sfft_profile_read(sfft_plan plan, int kind, double* total_ms, int64_
 
 sfft_status sfft_plan_destroy(sfft_plan plan) {
   if (!plan) return fail(SFFT_INVALID_ARG, "plan is null");
+  sfft_rt_forget_plan(plan);
   delete plan;
   return SFFT_OK;
 }

@@ -133,6 +133,15 @@ class Plan:
 
     __call__ = apply
 
+    def autotune(self, nrhs: int = 1, use_cache: bool = True, stream=None) -> float:
+        """Pick the fastest schedule / leaf grouping for nrhs right-hand sides on
+        the device (microseconds per apply, -1 when taken from the cache)."""
+        best = C.c_double()
+        N.check(N.lib.sfft_plan_autotune(self.handle, int(nrhs), int(use_cache),
+                                         C.c_void_p(_stream_handle(stream)), C.byref(best)),
+                "sfft_plan_autotune")
+        return float(best.value)
+
     # -- profiling hooks -------------------------------------------------
     def profile(self, kinds=("leaf",)):
         """Bracket later launches of the given kernel kinds with HIP events."""

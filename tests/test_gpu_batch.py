@@ -1,0 +1,117 @@
+"""GPU: multi-problem batches (one HIP graph over uneven grids) and the
+autotuner, through the C ABI, against single applies and the FP64 oracle."""
+
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"c128": 1e-12, "c64": 1e-5}
+TDT = {"c128": torch.complex128, "c64": torch.complex64}
+
+
+@pytest.fixture(scope="module")
+def sf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2406_17981_amd as sf
+    return sf
+
+
+def _problems():
+    # uneven grids, both block sizes, both dtypes, mirrored storage, 1..5 RHS
+    specs = [((12, 10, 16), 3, "c64", 3, None, "breadth"),
+             ((24, 40), 1, "c128", 2, None, "depth"),
+             ((8, 6, 10), 3, "c128", 1, "green", "depth"),
+             ((48,), 1, "c64", 5, None, "breadth"),
+             ((16, 12, 8), 1, "c64", 2, None, "depth")]
+    out = []
+    for i, (n, b, dt, nrhs, kind, sched) in enumerate(specs):
+        coeffs = wl.green_coeffs(n, 0.9) if kind == "green" else wl.iid_coeffs(40 + i, n, b)
+        x = wl.vectors(60 + i, n, b, nrhs)
+        out.append(dict(n=n, b=b, dtype=dt, coeffs=coeffs, x=x, kind=kind, sched=sched))
+    return out
+
+
+def _plans(sf, probs):
+    plans, xs, ys = [], [], []
+    for pr in probs:
+        par = wl.green_parity(len(pr["n"])) if pr["kind"] == "green" else None
+        plans.append(sf.Plan(pr["n"], pr["b"], torch.from_numpy(pr["coeffs"]).cuda(), dtype=pr["dtype"],
+                             parity=par, max_nrhs=pr["x"].shape[0], schedule=pr["sched"]))
+        xs.append(torch.from_numpy(pr["x"]).to(TDT[pr["dtype"]]).cuda())
+        ys.append(torch.zeros_like(xs[-1]))
+    return plans, xs, ys
+
+
+def test_apply_multi_graph_matches_single_applies_and_oracle(sf):
+    probs = _problems()
+    plans, xs, ys = _plans(sf, probs)
+    ws = torch.empty(max(sf.workspace_size_multi(plans, [x.shape[0] for x in xs]), 1), dtype=torch.uint8,
+                     device="cuda")
+    singles = []
+    for p, x in zip(plans, xs):
+        singles.append(p.apply(x, workspace=p.alloc_workspace(x.shape[0])))
+    for rep in range(3):  # first call captures the graph, later calls replay it
+        for y in ys:
+            y.zero_()
+        torch.cuda.synchronize()
+        sf.apply_multi(plans, xs, ys, workspace=ws)
+        torch.cuda.synchronize()
+        for i, (pr, y, ysingle) in enumerate(zip(probs, ys, singles)):
+            assert torch.equal(y, ysingle), (rep, i)
+    for pr, y in zip(probs, ys):
+        want = oracle.embed_matvec(pr["coeffs"], pr["x"])
+        assert wl.relative_l2(y.cpu().numpy().astype(np.complex128), want) <= TOL[pr["dtype"]]
+    # destroying a plan drops its graph; a new batch without it still works
+    plans[0].close()
+    rest = plans[1:]
+    ws2 = torch.empty(max(sf.workspace_size_multi(rest, [x.shape[0] for x in xs[1:]]), 1), dtype=torch.uint8,
+                      device="cuda")
+    for y in ys[1:]:
+        y.zero_()
+    sf.apply_multi(rest, xs[1:], ys[1:], workspace=ws2)
+    torch.cuda.synchronize()
+    for y, ysingle in zip(ys[1:], singles[1:]):
+        assert torch.equal(y, ysingle)
+    for p in rest:
+        p.close()
+
+
+def test_apply_multi_without_graphs(sf, monkeypatch):
+    probs = _problems()[:3]
+    plans, xs, ys = _plans(sf, probs)
+    monkeypatch.setenv("SFFT_NO_GRAPH", "1")
+    sf.apply_multi(plans, xs, ys)
+    torch.cuda.synchronize()
+    for pr, y in zip(probs, ys):
+        want = oracle.embed_matvec(pr["coeffs"], pr["x"])
+        assert wl.relative_l2(y.cpu().numpy().astype(np.complex128), want) <= TOL[pr["dtype"]]
+    for p in plans:
+        p.close()
+
+
+def test_autotune_keeps_results_and_uses_cache(sf, tmp_path, monkeypatch):
+    monkeypatch.setenv("SFFT_TUNE_CACHE", str(tmp_path / "tune.jsonl"))
+    n, b, nrhs = (16, 24, 32), 3, 4
+    coeffs = wl.green_coeffs(n, 0.8)
+    x = wl.vectors(70, n, b, nrhs)
+    want = oracle.embed_matvec(coeffs, x)
+    plan = sf.Plan(n, b, torch.from_numpy(coeffs).cuda(), dtype="c64", max_nrhs=nrhs)
+    us = plan.autotune(nrhs)
+    assert us > 0
+    y = plan.apply(torch.from_numpy(x).to(torch.complex64).cuda(), workspace=plan.alloc_workspace(nrhs))
+    torch.cuda.synchronize()
+    assert wl.relative_l2(y.cpu().numpy().astype(np.complex128), want) <= 1e-5
+    assert (tmp_path / "tune.jsonl").exists()
+    plan2 = sf.Plan(n, b, torch.from_numpy(coeffs).cuda(), dtype="c64", max_nrhs=nrhs)
+    assert plan2.autotune(nrhs) == -1.0  # answered from the cache
+    assert plan2.info()["schedule"] == plan.info()["schedule"]
+    plan.close()
+    plan2.close()
