@@ -256,6 +256,48 @@ def bench_batch(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_serve(args):
+    """Serving: Poisson arrivals (mean 200 req/s, seed 401), half d=2 grids
+    {128..1024}^2 and half d=3 {32..128}^3, 3x3 Green kernels with k ~ U[0.5,1.5],
+    each request a 30-step Arnoldi chain of matvecs. Continuous batching in
+    complex64 with mirrored symbols under an HBM budget, against the plain
+    FP64 path (one request at a time, full symbols) on the same stream."""
+    import torch
+    import workloads as wl
+    from paper_2406_17981_amd import serve
+    reqs = serve.poisson_requests(401, 200.0, args.requests)
+    coeff_fn = lambda n, k: wl.green_coeffs_device(n, k, device="cuda")  # noqa: E731
+    for n in ((8, 8), (4, 4, 4)):  # first-use warm-up of the coefficient generator's device ops
+        coeff_fn(n, 1.0)
+    torch.cuda.synchronize()
+    out = {}
+    for name, mk, max_active, nreq in (
+            ("batched_c64", lambda: serve.GpuExecutor(coeff_fn, wl.green_parity, dtype="c64", mirrored=True), 256,
+             len(reqs)),
+            ("single_fp64", lambda: serve.SingleRequestExecutor(coeff_fn, None, dtype="c128", mirrored=False), 1,
+             len(reqs) if args.single_requests is None else min(len(reqs), args.single_requests))):
+        rs = serve.poisson_requests(401, 200.0, nreq)
+        ex = mk()
+        srv = serve.Server(ex, budget_bytes=int(args.budget_gb * (1 << 30)), max_active=max_active)
+        log(f"[serve {name}] {nreq} requests")
+        t0 = time.perf_counter()
+        done = srv.run(rs)
+        torch.cuda.synchronize()
+        summ = serve.latency_summary(done)
+        summ.update(wall_s=round(time.perf_counter() - t0, 3), server_steps=srv.steps_run,
+                    host_s_admit=round(srv.time_in["admit"], 3), host_s_step=round(srv.time_in["step"], 3),
+                    host_s_finish=round(srv.time_in["finish"], 3),
+                    mean_batch=round(sum(srv.batch_sizes) / max(len(srv.batch_sizes), 1), 2),
+                    peak_reserved_gb=round(srv.peak_reserved / 2 ** 30, 2))
+        out[name] = {k: (round(v, 5) if isinstance(v, float) else v) for k, v in summ.items()}
+        log(f"[serve {name}] p50 {summ['p50_s']:.3f} s p99 {summ['p99_s']:.3f} s, "
+            f"{summ['matvecs_per_s']:.0f} matvecs/s")
+        del ex, srv
+        torch.cuda.empty_cache()
+    print(json.dumps({"workload": "serve-poisson200-green-b3-arnoldi30", "results": out,
+                      "budget_gb": args.budget_gb}), flush=True)
+
+
 def time_plan(plan, x, y, ws, steps, warmup, profile_leaf=False):
     import torch
     for _ in range(warmup):
@@ -309,7 +351,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variants", default="all", choices=["all", "headline"])
     ap.add_argument("--pmc-probe", action="store_true", help="workload for rocprofv3 --pmc runs")
-    ap.add_argument("--workload", default="green64", choices=["green64", "large", "batch"],
+    ap.add_argument("--requests", type=int, default=400, help="serve: requests in the stream")
+    ap.add_argument("--single-requests", type=int, default=None,
+                    help="serve: requests for the FP64 path (default: the same stream)")
+    ap.add_argument("--budget-gb", type=float, default=64.0, help="serve: HBM budget")
+    ap.add_argument("--workload", default="green64", choices=["green64", "large", "batch", "serve"],
                     help="large: the 256x256x128 8-RHS configuration, split vs embed; "
                          "batch: 8 uneven-grid problems, 64 RHS, one graph")
     ap.add_argument("--pmc-summarize", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON"))
@@ -326,6 +372,9 @@ def main():
         return
     if args.workload == "batch":
         bench_batch(args)
+        return
+    if args.workload == "serve":
+        bench_serve(args)
         return
 
     if args.gpus != 1:

@@ -142,6 +142,29 @@ sfft_status sfft_apply_multi(int nprob, const sfft_plan* plans, const void* cons
 
 sfft_status sfft_plan_info(sfft_plan plan, sfft_info* info);
 
+/* One step of independent Arnoldi processes (Krylov chains of matvecs, the
+ * iterative-solver setting of the paper's introduction). For every job the
+ * new vector w (typically T v_{m-1}) is orthogonalised against the basis
+ * v_0..v_{m-1} by classical Gram-Schmidt applied twice, then normalised:
+ *     hcol[i] = <v_i, w> (both passes summed), hcol[m] = ||w||, vout = w/||w||.
+ * m = 0 only normalises (the start vector). Reductions accumulate in FP64 in
+ * a fixed order, so results are bitwise independent of the other jobs.
+ * All pointers are device pointers; vectors are of `dtype` (one dtype per
+ * call); hcol is complex128. scratch: sfft_arnoldi_scratch_size bytes. */
+typedef struct {
+  const void* V;   /* basis v_0..v_{m-1}, v_i at V + i*ldv entries */
+  int64_t ldv;     /* entries between basis vectors (>= n) */
+  int64_t m;       /* basis vectors, 0 <= m <= 64 */
+  void* w;         /* n entries, overwritten by its orthogonalised form */
+  void* vout;      /* receives w / ||w|| (may be w or the basis slot v_m) */
+  int64_t n;       /* entries per vector */
+  void* hcol;      /* m + 1 complex128 entries */
+} sfft_arnoldi_job;
+
+sfft_status sfft_arnoldi_scratch_size(int njobs, const sfft_arnoldi_job* jobs, size_t* bytes);
+sfft_status sfft_arnoldi_step_multi(int njobs, const sfft_arnoldi_job* jobs, int dtype, void* scratch,
+                                    size_t scratch_bytes, void* stream);
+
 /* Times the plan's candidate schedules (breadth-first and depth-first for
  * SFFT_SPLIT with d > 1) and leaf right-hand-side groupings (1, 2, 4, 8 per
  * workgroup, within the kernel's limit) at nrhs right-hand sides on `stream`,

@@ -26,7 +26,7 @@ EXPORTS = [
     "sfft_plan_create", "sfft_workspace_size", "sfft_apply", "sfft_workspace_size_multi",
     "sfft_apply_multi", "sfft_plan_info", "sfft_plan_destroy", "sfft_status_string",
     "sfft_last_error", "sfft_length_supported", "sfft_profile_enable", "sfft_profile_read",
-    "sfft_plan_autotune",
+    "sfft_plan_autotune", "sfft_arnoldi_scratch_size", "sfft_arnoldi_step_multi",
 ]
 KIND_FORWARD, KIND_LEAF, KIND_INVERSE, KIND_COPY = range(4)
 
@@ -37,6 +37,13 @@ class SfftInfo(C.Structure):
         ("method", C.c_int), ("schedule", C.c_int), ("compressed", C.c_int),
         ("max_nrhs", C.c_int64), ("symbol_bytes", C.c_size_t), ("table_bytes", C.c_size_t),
         ("workspace_bytes", C.c_size_t), ("vector_elems", C.c_int64),
+    ]
+
+
+class ArnoldiJob(C.Structure):
+    _fields_ = [
+        ("V", C.c_void_p), ("ldv", C.c_int64), ("m", C.c_int64), ("w", C.c_void_p),
+        ("vout", C.c_void_p), ("n", C.c_int64), ("hcol", C.c_void_p),
     ]
 
 
@@ -69,6 +76,8 @@ def _load():
     lib.sfft_profile_enable.argtypes = [vp, C.c_uint]
     lib.sfft_profile_read.argtypes = [vp, C.c_int, C.POINTER(C.c_double), P64, C.c_int]
     lib.sfft_plan_autotune.argtypes = [vp, i64, C.c_int, vp, C.POINTER(C.c_double)]
+    lib.sfft_arnoldi_scratch_size.argtypes = [C.c_int, C.POINTER(ArnoldiJob), C.POINTER(sz)]
+    lib.sfft_arnoldi_step_multi.argtypes = [C.c_int, C.POINTER(ArnoldiJob), C.c_int, vp, sz, vp]
     for name in EXPORTS:
         fn = getattr(lib, name)
         if fn.restype is C.c_int or fn.restype is None:

@@ -1,0 +1,319 @@
+"""Continuous-batching server for Krylov chains of block-Toeplitz matvecs.
+
+Each request is a GMRES-style Arnoldi chain on its own operator T (a 3x3
+Green-function block-Toeplitz matrix on a d = 2 or 3 grid): v_0 = b/||b||,
+then `steps` times w = T v_j, orthogonalise w against v_0..v_j, normalise.
+The server
+
+* admits arrived requests first-come first-served while their device memory
+  (plan symbols and tables, workspace, the Krylov basis, and the transient
+  coefficient / FP64 symbol scratch of plan creation) fits an HBM budget;
+  requests that do not fit wait in the queue;
+* advances every active request by one Arnoldi step per server step: the
+  matvecs of all active requests are issued over several streams so their
+  kernels overlap on the device, then one sfft_arnoldi_step_multi call
+  orthogonalises all of them;
+* admits new requests between steps as slots and memory free up (continuous
+  batching), and records arrival, admission and completion times.
+
+Every kernel is deterministic and works on one request's buffers only, so a
+request's results are bitwise the same alone and in any mix.
+
+The device work is behind an executor interface so the scheduler can be
+tested on the host with a mock executor.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import math
+import time
+from dataclasses import dataclass
+from typing import Callable, List, Optional, Sequence
+
+import numpy as np
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float                 # seconds after the stream starts
+    n: tuple                       # grid
+    k: float                       # Green-function wavenumber
+    steps: int = 30                # matvecs in the chain
+    seed: int = 0                  # seeds the start vector
+    # filled by the server
+    admitted: Optional[float] = None
+    done: Optional[float] = None
+    result: Optional[dict] = None
+
+    @property
+    def latency(self) -> Optional[float]:
+        return None if self.done is None else self.done - self.arrival
+
+
+def poisson_requests(seed: int, rate: float, count: int, steps: int = 30,
+                     d2_sizes=(128, 256, 512, 1024), d3_sizes=(32, 64, 96, 128),
+                     k_range=(0.5, 1.5)) -> List[Request]:
+    """Poisson arrivals (exponential gaps, mean 1/rate); half d = 2 grids, half
+    d = 3, sizes uniform over the given sets, k uniform over k_range."""
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, size=count))
+    out = []
+    for i in range(count):
+        if rng.random() < 0.5:
+            nn = int(rng.choice(d2_sizes))
+            n = (nn, nn)
+        else:
+            nn = int(rng.choice(d3_sizes))
+            n = (nn, nn, nn)
+        out.append(Request(rid=i, arrival=float(t[i]), n=n, k=float(rng.uniform(*k_range)), steps=steps,
+                           seed=4000 + i))
+    return out
+
+
+class Executor:
+    """Device side of the server (one implementation per backend)."""
+
+    def bytes_needed(self, req: Request) -> tuple:
+        """(resident bytes, extra transient bytes during admission)."""
+        raise NotImplementedError
+
+    def admit(self, req: Request) -> object:
+        raise NotImplementedError
+
+    def step(self, slots: Sequence[object]) -> None:
+        """One Arnoldi step for each slot."""
+        raise NotImplementedError
+
+    def finish(self, slot: object) -> dict:
+        raise NotImplementedError
+
+    def release(self, slot: object) -> None:
+        raise NotImplementedError
+
+
+@dataclass
+class _Slot:
+    req: Request
+    handle: object
+    reserved: int
+    done_steps: int = 0
+
+
+class Server:
+    """Admission by HBM budget, continuous batching, completion bookkeeping."""
+
+    def __init__(self, executor: Executor, budget_bytes: int, max_active: int = 256,
+                 clock: Callable[[], float] = time.perf_counter, sleep: Callable[[float], None] = time.sleep):
+        self.ex = executor
+        self.budget = int(budget_bytes)
+        self.max_active = max_active
+        self.clock = clock
+        self.sleep = sleep
+        self.reserved = 0
+        self.peak_reserved = 0
+        self.steps_run = 0
+        self.batch_sizes: List[int] = []
+        self.time_in = dict(admit=0.0, step=0.0, finish=0.0)  # host seconds per phase
+
+    def _try_admit(self, req: Request, now: float, active: List[_Slot]) -> bool:
+        resident, transient = self.ex.bytes_needed(req)
+        if resident + transient > self.budget:
+            raise ValueError(f"request {req.rid} needs {resident + transient} bytes, budget {self.budget}")
+        if len(active) >= self.max_active or self.reserved + resident + transient > self.budget:
+            return False
+        self.reserved += resident + transient
+        self.peak_reserved = max(self.peak_reserved, self.reserved)
+        t = self.clock()
+        handle = self.ex.admit(req)
+        self.time_in["admit"] += self.clock() - t
+        self.reserved -= transient
+        req.admitted = now
+        active.append(_Slot(req, handle, resident))
+        return True
+
+    def run(self, requests: Sequence[Request]) -> List[Request]:
+        pending = sorted(requests, key=lambda r: r.arrival)
+        queue: List[Request] = []
+        active: List[_Slot] = []
+        finished: List[Request] = []
+        t0 = self.clock()
+        i = 0
+        while i < len(pending) or queue or active:
+            now = self.clock() - t0
+            while i < len(pending) and pending[i].arrival <= now:
+                queue.append(pending[i])
+                i += 1
+            while queue and self._try_admit(queue[0], self.clock() - t0, active):
+                queue.pop(0)
+            if not active:
+                if i < len(pending):
+                    self.sleep(max(0.0, pending[i].arrival - (self.clock() - t0)))
+                continue
+            t = self.clock()
+            self.ex.step([s.handle for s in active])
+            self.time_in["step"] += self.clock() - t
+            self.steps_run += 1
+            self.batch_sizes.append(len(active))
+            still = []
+            for s in active:
+                s.done_steps += 1
+                if s.done_steps >= s.req.steps:
+                    t = self.clock()
+                    s.req.result = self.ex.finish(s.handle)
+                    s.req.done = self.clock() - t0
+                    self.ex.release(s.handle)
+                    self.time_in["finish"] += self.clock() - t
+                    self.reserved -= s.reserved
+                    finished.append(s.req)
+                else:
+                    still.append(s)
+            active = still
+        return finished
+
+
+def latency_summary(reqs: Sequence[Request]) -> dict:
+    lat = np.array([r.latency for r in reqs if r.latency is not None])
+    if lat.size == 0:
+        return {}
+    span = max(r.done for r in reqs) - min(r.arrival for r in reqs)
+    mv = sum(r.steps for r in reqs)
+    return dict(requests=int(lat.size), p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
+                mean_s=float(lat.mean()), max_s=float(lat.max()), span_s=float(span),
+                requests_per_s=float(lat.size / span), matvecs_per_s=float(mv / span))
+
+
+# ---------------------------------------------------------------------------
+# GPU executor
+# ---------------------------------------------------------------------------
+
+class GpuExecutor(Executor):
+    """Plans (3x3 blocks), a Krylov basis of steps+1 vectors and a Hessenberg
+    matrix per request; matvecs over `nstreams` streams.
+
+    coeff_fn(n, k) returns the request's complex128 device coefficient array
+    (3, 3, 2n_1-1, ...); parity_fn(d) its (3, 3, d) symmetry mask, used when
+    `mirrored` (symbols stored mirrored)."""
+
+    def __init__(self, coeff_fn, parity_fn=None, dtype: str = "c64", nstreams: int = 4, mirrored: bool = True,
+                 schedule: str = "depth", keep_basis: bool = False):
+        import torch
+        from . import _native as N
+        from .plan import Plan
+        self.torch = torch
+        self.N = N
+        self.Plan = Plan
+        self.coeff_fn = coeff_fn
+        self.parity_fn = parity_fn
+        self.keep_basis = keep_basis
+        if mirrored and parity_fn is None:
+            raise ValueError("mirrored storage needs parity_fn")
+        self.dtype = dtype
+        self.tdt = torch.complex64 if dtype == "c64" else torch.complex128
+        self.esz = 8 if dtype == "c64" else 16
+        self.mirrored = mirrored
+        self.schedule = schedule
+        self.streams = [torch.cuda.Stream() for _ in range(nstreams)]
+        self.main = torch.cuda.current_stream()
+        # plan creation (coefficients, FP64 symbols) runs on its own stream, so
+        # its completion wait does not drain the other requests' queued steps
+        self.admit_stream = torch.cuda.Stream()
+        self._scratch = None
+
+    def bytes_needed(self, req: Request) -> tuple:
+        n, d, b = req.n, len(req.n), 3
+        s = math.prod(n)
+        V = b * s * self.esz
+        sym = 9 * math.prod(v + 1 for v in n) * self.esz if self.mirrored else 2 ** d * 9 * s * self.esz
+        ws = (d - 1) * V if self.schedule == "depth" else (2 ** d - 2) * V
+        resident = sym + ws + (req.steps + 2) * V + (1 << 20)
+        transient = 9 * math.prod(2 * v - 1 for v in n) * 16 + math.prod(2 * v for v in n) * 16
+        return resident, transient
+
+    def admit(self, req: Request) -> dict:
+        torch = self.torch
+        n, b = req.n, 3
+        with torch.cuda.stream(self.admit_stream):
+            coeffs = self.coeff_fn(n, req.k)
+            par = self.parity_fn(len(n)) if self.mirrored else None
+            plan = self.Plan(n, b, coeffs, dtype=self.dtype, parity=par, max_nrhs=1, schedule=self.schedule,
+                             stream=self.admit_stream)
+            del coeffs
+        vlen = b * math.prod(n)
+        basis = torch.empty((req.steps + 1, vlen), dtype=self.tdt, device="cuda")
+        # start vector b: complex normal, drawn on the device from the request's seed
+        g = torch.Generator(device="cuda").manual_seed(req.seed)
+        real = self.tdt.to_real()
+        basis[0].copy_(torch.complex(torch.randn(vlen, generator=g, dtype=real, device="cuda"),
+                                     torch.randn(vlen, generator=g, dtype=real, device="cuda")))
+        # Hessenberg matrix stored by columns: Hc[j] is column j (contiguous);
+        # Hc[steps][0] receives ||b||
+        Hc = torch.zeros((req.steps + 1, req.steps + 1), dtype=torch.complex128, device="cuda")
+        slot = dict(req=req, plan=plan, basis=basis, w=torch.empty(vlen, dtype=self.tdt, device="cuda"), Hc=Hc,
+                    ws=plan.alloc_workspace(1), j=0, shape=(1, b) + tuple(n))
+        # v_0 = b / ||b|| (an Arnoldi job with an empty basis)
+        self._arnoldi([dict(V=basis, m=0, w=basis[0], vout=basis[0], hcol=Hc[req.steps])])
+        return slot
+
+    def _arnoldi(self, jobs):
+        N = self.N
+        arr = (N.ArnoldiJob * len(jobs))()
+        for a, jb in zip(arr, jobs):
+            a.V = jb["V"].data_ptr()
+            a.ldv = jb["V"].shape[1]
+            a.m = jb["m"]
+            a.w = jb["w"].data_ptr()
+            a.vout = jb["vout"].data_ptr()
+            a.n = jb["w"].numel()
+            a.hcol = jb["hcol"].data_ptr()
+        need = C.c_size_t()
+        N.check(N.lib.sfft_arnoldi_scratch_size(len(jobs), arr, C.byref(need)), "sfft_arnoldi_scratch_size")
+        if self._scratch is None or self._scratch.numel() < need.value:
+            self._scratch = self.torch.empty(max(int(need.value), 1 << 20), dtype=self.torch.uint8, device="cuda")
+        code = N.C64 if self.dtype == "c64" else N.C128
+        st = self.main.cuda_stream
+        N.check(N.lib.sfft_arnoldi_step_multi(len(jobs), arr, code, C.c_void_p(self._scratch.data_ptr()),
+                                              self._scratch.numel(), C.c_void_p(st)), "sfft_arnoldi_step_multi")
+
+    def step(self, slots) -> None:
+        torch = self.torch
+        ev = torch.cuda.Event()
+        ev.record(self.main)
+        for i, s in enumerate(slots):  # w = T v_j, spread over streams
+            st = self.streams[i % len(self.streams)]
+            st.wait_event(ev)
+            s["plan"].apply(s["basis"][s["j"]].view(s["shape"]), s["w"].view(s["shape"]), s["ws"], stream=st)
+        for st in self.streams:
+            self.main.wait_stream(st)
+        jobs = []
+        for s in slots:
+            j = s["j"]
+            jobs.append(dict(V=s["basis"], m=j + 1, w=s["w"], vout=s["basis"][j + 1], hcol=s["Hc"][j]))
+            s["j"] = j + 1
+        self._arnoldi(jobs)
+
+    def finish(self, slot) -> dict:
+        self.torch.cuda.current_stream().synchronize()
+        req = slot["req"]
+        Hc = slot["Hc"].cpu().numpy()
+        out = dict(H=Hc[:req.steps].T.copy(), start_norm=float(Hc[req.steps, 0].real))
+        if self.keep_basis:
+            out["basis"] = slot["basis"].cpu().numpy()
+        return out
+
+    def release(self, slot) -> None:
+        slot["plan"].close()
+        slot.clear()
+
+
+class SingleRequestExecutor(GpuExecutor):
+    """The plain path: one request at a time, no overlap (used with
+    max_active=1), same kernels; typically FP64 and full symbols."""
+
+    def step(self, slots) -> None:
+        for s in slots:
+            s["plan"].apply(s["basis"][s["j"]].view(s["shape"]), s["w"].view(s["shape"]), s["ws"], stream=self.main)
+            j = s["j"]
+            self._arnoldi([dict(V=s["basis"], m=j + 1, w=s["w"], vout=s["basis"][j + 1], hcol=s["Hc"][j])])
+            s["j"] = j + 1

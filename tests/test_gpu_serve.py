@@ -1,0 +1,66 @@
+"""GPU: the continuous-batching server's Krylov chains are correct Arnoldi
+processes of the requested operators, and each request's results are
+bitwise the same alone and in a mix of concurrent requests."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def serve():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2406_17981_amd import serve
+    return serve
+
+
+def _coeff_fn(n, k):
+    return wl.green_coeffs_device(n, k, device="cuda")
+
+
+def _requests(serve, steps=8):
+    R = serve.Request
+    return [R(rid=0, arrival=0.0, n=(16, 16, 16), k=0.9, steps=steps, seed=11),
+            R(rid=1, arrival=0.0, n=(32, 32), k=1.2, steps=steps, seed=12),
+            R(rid=2, arrival=0.001, n=(20, 24, 12), k=0.6, steps=steps, seed=13),
+            R(rid=3, arrival=0.002, n=(64, 48), k=1.4, steps=steps, seed=14)]
+
+
+def _run(serve, reqs, dtype="c64", mirrored=True, max_active=16):
+    ex = serve.GpuExecutor(_coeff_fn, wl.green_parity, dtype=dtype, mirrored=mirrored, keep_basis=True)
+    srv = serve.Server(ex, budget_bytes=8 << 30, max_active=max_active)
+    return {r.rid: r for r in srv.run(reqs)}
+
+
+@pytest.mark.parametrize("dtype,mirrored,tol", [("c64", True, 2e-5), ("c128", False, 1e-12)])
+def test_chains_satisfy_the_arnoldi_relation(serve, dtype, mirrored, tol):
+    done = _run(serve, _requests(serve), dtype, mirrored)
+    for rid, r in done.items():
+        H = r.result["H"]                       # (steps+1, steps)
+        V = r.result["basis"].astype(np.complex128)   # (steps+1, 3*prod(n))
+        m = r.steps
+        # orthonormal basis
+        G = V.conj() @ V.T
+        assert np.abs(G - np.eye(m + 1)).max() <= 50 * tol, rid
+        # T V_m = V_{m+1} H, with T applied by the FP64 oracle
+        coeffs = wl.green_coeffs(r.n, r.k)
+        X = V[:m].reshape((m, 3) + tuple(r.n))
+        TV = oracle.embed_matvec(coeffs, X).reshape(m, -1)
+        rel = np.linalg.norm(TV - H.T @ V) / np.linalg.norm(TV)
+        assert rel <= 10 * tol, (rid, rel)
+        assert np.allclose(np.tril(H, -2), 0)   # upper Hessenberg
+
+
+def test_results_identical_alone_and_in_the_mix(serve):
+    mixed = _run(serve, _requests(serve))
+    for r in _requests(serve):
+        r.arrival = 0.0
+        alone = _run(serve, [r], max_active=1)[r.rid]
+        assert np.array_equal(alone.result["H"], mixed[r.rid].result["H"]), r.rid
+        assert np.array_equal(alone.result["basis"], mixed[r.rid].result["basis"]), r.rid

@@ -1,0 +1,120 @@
+"""Host-side tests of the continuous-batching scheduler with a mock executor:
+admission by budget, queueing, FIFO order, slot reuse, step counts."""
+
+import pytest
+
+from paper_2406_17981_amd.serve import Executor, Request, Server, latency_summary, poisson_requests
+
+
+class FakeClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+    def sleep(self, dt):
+        self.t += max(dt, 0.0)
+
+
+class MockExecutor(Executor):
+    """Memory = 10 units per grid point count class; every step costs 1 ms of
+    fake time; records the server's view of reserved memory."""
+
+    def __init__(self, clock, server_ref, sizes):
+        self.clock = clock
+        self.server_ref = server_ref
+        self.sizes = sizes
+        self.log = []
+        self.steps = {}
+
+    def bytes_needed(self, req):
+        return self.sizes[req.n], 5
+
+    def admit(self, req):
+        srv = self.server_ref[0]
+        assert srv.reserved <= srv.budget
+        self.log.append(("admit", req.rid, self.clock()))
+        self.steps[req.rid] = 0
+        return req
+
+    def step(self, slots):
+        srv = self.server_ref[0]
+        assert srv.reserved <= srv.budget
+        for r in slots:
+            self.steps[r.rid] += 1
+        self.clock.t += 1e-3
+
+    def finish(self, slot):
+        self.log.append(("finish", slot.rid, self.clock()))
+        return dict(steps=self.steps[slot.rid])
+
+    def release(self, slot):
+        pass
+
+
+def _make(budget, sizes, max_active=256):
+    clock = FakeClock()
+    ref = [None]
+    ex = MockExecutor(clock, ref, sizes)
+    srv = Server(ex, budget, max_active=max_active, clock=clock, sleep=clock.sleep)
+    ref[0] = srv
+    return srv, ex, clock
+
+
+def test_all_requests_finish_with_their_step_counts():
+    reqs = poisson_requests(401, 200.0, 60, steps=7)
+    sizes = {r.n: 10 for r in reqs}
+    srv, ex, _ = _make(10_000, sizes)
+    done = srv.run(reqs)
+    assert sorted(r.rid for r in done) == list(range(60))
+    for r in done:
+        assert r.result["steps"] == 7
+        assert r.done >= r.admitted >= r.arrival
+    s = latency_summary(done)
+    assert s["requests"] == 60 and s["p99_s"] >= s["p50_s"] > 0
+
+
+def test_budget_limits_concurrency_and_queues_fifo():
+    reqs = [Request(rid=i, arrival=0.0001 * i, n=(8, 8), k=1.0, steps=5) for i in range(10)]
+    srv, ex, _ = _make(budget=3 * 10 + 5, sizes={(8, 8): 10})
+    done = srv.run(reqs)
+    assert max(srv.batch_sizes) == 3          # only three fit at once
+    assert srv.peak_reserved <= srv.budget
+    admits = [rid for ev, rid, _ in ex.log if ev == "admit"]
+    assert admits == list(range(10))          # first come, first served
+    assert len(done) == 10
+
+
+def test_continuous_batching_admits_between_steps():
+    # a long request is running when short ones arrive: they join it mid-chain
+    reqs = [Request(rid=0, arrival=0.0, n=(4, 4), k=1.0, steps=50),
+            Request(rid=1, arrival=0.010, n=(4, 4), k=1.0, steps=5),
+            Request(rid=2, arrival=0.020, n=(4, 4), k=1.0, steps=5)]
+    srv, ex, _ = _make(budget=1000, sizes={(4, 4): 10})
+    done = {r.rid: r for r in srv.run(reqs)}
+    assert done[1].admitted < done[0].done and done[1].done < done[0].done
+    assert 2 in srv.batch_sizes and 1 in srv.batch_sizes
+
+
+def test_max_active_slots_are_reused():
+    reqs = [Request(rid=i, arrival=0.0, n=(4, 4), k=1.0, steps=3) for i in range(7)]
+    srv, ex, _ = _make(budget=10**9, sizes={(4, 4): 10}, max_active=2)
+    done = srv.run(reqs)
+    assert len(done) == 7 and max(srv.batch_sizes) == 2
+
+
+def test_request_larger_than_budget_is_an_error():
+    reqs = [Request(rid=0, arrival=0.0, n=(64, 64), k=1.0, steps=3)]
+    srv, ex, _ = _make(budget=100, sizes={(64, 64): 1000})
+    with pytest.raises(ValueError):
+        srv.run(reqs)
+
+
+def test_poisson_stream_statistics():
+    reqs = poisson_requests(401, 200.0, 4000)
+    gaps = [b.arrival - a.arrival for a, b in zip(reqs, reqs[1:])]
+    assert abs(sum(gaps) / len(gaps) - 1 / 200.0) < 0.1 / 200.0
+    d2 = sum(1 for r in reqs if len(r.n) == 2)
+    assert 0.45 < d2 / len(reqs) < 0.55
+    assert all(0.5 <= r.k <= 1.5 for r in reqs)

@@ -109,6 +109,33 @@ def green_coeffs(n: Sequence[int], k: float = 0.7, self_term: float = 2.0) -> np
     return out
 
 
+def green_coeffs_device(n: Sequence[int], k: float = 0.7, self_term: float = 2.0, device="cuda"):
+    """green_coeffs evaluated with torch on a device (complex128), for callers
+    that need many large coefficient arrays quickly (the serving workload)."""
+    import torch
+    n = _grid(n)
+    if len(n) > 3:
+        raise ValueError("3-vector kernels need d <= 3")
+    axes = [torch.arange(-(v - 1), v, dtype=torch.float64, device=device) for v in n]
+    grids = torch.meshgrid(*axes, indexing="ij")
+    shape = grids[0].shape
+    comps = list(grids) + [torch.zeros(shape, dtype=torch.float64, device=device)] * (3 - len(n))
+    dist = torch.sqrt(comps[0] ** 2 + comps[1] ** 2 + comps[2] ** 2)
+    zero = dist == 0
+    safe = torch.where(zero, torch.ones_like(dist), dist)
+    g = torch.polar(1.0 / safe, k * safe)
+    out = torch.empty((3, 3) + tuple(shape), dtype=torch.complex128, device=device)
+    for a in range(3):
+        for c in range(a, 3):
+            rr = comps[a] * comps[c] / (safe * safe)
+            val = g * ((1.0 if a == c else 0.0) - rr)
+            val = torch.where(zero, torch.full_like(val, self_term if a == c else 0.0), val)
+            out[a, c] = val
+            if c != a:
+                out[c, a] = val
+    return out
+
+
 def skew_coeffs(n: Sequence[int], k: float = 1.3) -> np.ndarray:
     """Skew-symmetric 3x3 kernel t(r) = exp(i k |r|)/|r| * [rhat]_x with t(0) = 0.
 
