@@ -88,6 +88,11 @@ template <typename Real, int L> struct Geo {
   static constexpr int RB_THR = SL >= THR_CAP ? 1 : THR_CAP / SL;
   static constexpr int RBMAX_ = RB_LDS < RB_THR ? RB_LDS : RB_THR;
   static constexpr int RBMAX = RBMAX_ >= 8 ? 8 : (RBMAX_ >= 4 ? 4 : (RBMAX_ >= 2 ? 2 : 1));
+  // LDS rows per (pencil, rhs) lane group: plans with two or more exchanges
+  // transform all NPAR*B pencils of a lane in lockstep (one row each); with a
+  // single exchange the pencils go one after another through one row, which
+  // keeps LDS per workgroup (and so occupancy) low
+  template <int B, int NPAR> static constexpr int leaf_rows() { return LSh::S >= 3 ? NPAR * B : 1; }
 };
 
 // Position of symbol entry (block component ab, home index m, lane) inside one
@@ -318,7 +323,8 @@ __global__ void __launch_bounds__((Geo<Real, L>::RBMAX * Geo<Real, L>::SL)) k_le
   const C* tw = (const C*)a.tw;
   const C* in = (const C*)a.in + q * a.in_bs;
   C* out = (C*)a.out + q * a.out_bs;
-  C* lp = lds + row * LP;
+  constexpr int NROW = G::template leaf_rows<B, NPAR>();
+  C* lp = lds + row * NROW * LP;
   LaneTw<C, Sh> lt;
   lt.load(t, tw);
 
@@ -400,39 +406,51 @@ __global__ void __launch_bounds__((Geo<Real, L>::RBMAX * Geo<Real, L>::SL)) k_le
     }
   };
 
+  // all children x components transformed together (one LDS row each)
+  constexpr int NP = NPAR * B;
+  C h[NP][E];
   if constexpr (NPAR == 2) {
-    // odd child: Phi x
     C ph[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) ph[m] = tw[t + T * m];
-    C w1[B][E];
 #pragma unroll
     for (int c = 0; c < B; ++c)
 #pragma unroll
-      for (int m = 0; m < E; ++m) w1[c][m] = cmul(x[c][m], ph[m]);
+      for (int m = 0; m < E; ++m) {
+        h[c][m] = x[c][m];
+        h[B + c][m] = cmul(x[c][m], ph[m]);  // odd child: Phi x
+      }
+  } else {
 #pragma unroll
-    for (int c = 0; c < B; ++c) {
-      fft_pencil<-1, Sh, G::LWS>(x[c], lp, 1, t, lt);
-      fft_pencil<-1, Sh, G::LWS>(w1[c], lp, 1, t, lt);
-    }
-    block_product(x, 0);
-    block_product(w1, 1);
+    for (int c = 0; c < B; ++c)
 #pragma unroll
-    for (int c = 0; c < B; ++c) {
-      fft_pencil<+1, Sh, G::LWS>(x[c], lp, 1, t, lt);
-      fft_pencil<+1, Sh, G::LWS>(w1[c], lp, 1, t, lt);
-    }
+      for (int m = 0; m < E; ++m) h[c][m] = x[c][m];
+  }
+  if constexpr (NROW == NP) {
+    fft_pencils<-1, Sh, G::LWS, NP>(h, lp, LP, 1, t, lt);
+  } else {
+#pragma unroll
+    for (int c = 0; c < NP; ++c) fft_pencil<-1, Sh, G::LWS>(h[c], lp, 1, t, lt);
+  }
+  block_product(*reinterpret_cast<C(*)[B][E]>(&h[0]), 0);
+  if constexpr (NPAR == 2) block_product(*reinterpret_cast<C(*)[B][E]>(&h[B]), 1);
+  if constexpr (NROW == NP) {
+    fft_pencils<+1, Sh, G::LWS, NP>(h, lp, LP, 1, t, lt);
+  } else {
+#pragma unroll
+    for (int c = 0; c < NP; ++c) fft_pencil<+1, Sh, G::LWS>(h[c], lp, 1, t, lt);
+  }
+  if constexpr (NPAR == 2) {
     // merge: even + conj(Phi) odd
 #pragma unroll
     for (int c = 0; c < B; ++c)
 #pragma unroll
-      for (int m = 0; m < E; ++m) x[c][m] = cadd(x[c][m], cmulc(w1[c][m], ph[m]));
+      for (int m = 0; m < E; ++m) x[c][m] = cadd(h[c][m], cmulc(h[B + c][m], tw[t + T * m]));
   } else {
 #pragma unroll
-    for (int c = 0; c < B; ++c) fft_pencil<-1, Sh, G::LWS>(x[c], lp, 1, t, lt);
-    block_product(x, 0);
+    for (int c = 0; c < B; ++c)
 #pragma unroll
-    for (int c = 0; c < B; ++c) fft_pencil<+1, Sh, G::LWS>(x[c], lp, 1, t, lt);
+      for (int m = 0; m < E; ++m) x[c][m] = h[c][m];
   }
 
   // store: every lane writes its own entries
@@ -479,13 +497,16 @@ template <typename Real, int L, int MODE> hipError_t launch_contig(const PassArg
 template <typename Real, int L, int B, int NPAR, bool MIR = false>
 hipError_t launch_leaf(const PassArgs& a, hipStream_t s) {
   using G = Geo<Real, L>;
-  const int rb = a.rb < 1 ? 1 : (a.rb > G::RBMAX ? G::RBMAX : a.rb);
+  constexpr size_t row_bytes = (size_t)G::PL * G::LLP * sizeof(cx<Real>) * G::template leaf_rows<B, NPAR>();
+  constexpr int rb_lds = (int)((64 * 1024) / row_bytes) > 0 ? (int)((64 * 1024) / row_bytes) : 1;
+  int rb = a.rb < 1 ? 1 : (a.rb > G::RBMAX ? G::RBMAX : a.rb);
+  while (rb > rb_lds) rb /= 2;
   PassArgs b = a;
   b.rb = rb;
   const int64_t nrg = (a.nrhs + rb - 1) / rb;
   const int64_t blocks = a.nq * ((a.ntiles + 7) / 8) * nrg * 8;
   if (blocks <= 0) return hipSuccess;
-  const size_t smem = (size_t)rb * G::PL * G::LLP * sizeof(cx<Real>);
+  const size_t smem = (size_t)rb * row_bytes;
   hipLaunchKernelGGL((k_leaf<Real, L, B, NPAR, MIR>), dim3((unsigned)blocks), dim3(rb * G::SL), smem, s, b);
   return hipGetLastError();
 }

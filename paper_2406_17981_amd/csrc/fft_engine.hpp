@@ -368,4 +368,94 @@ __device__ __forceinline__ void fft_pencil(C (&home)[Sh::E], C* lds, int kst, in
   fft_stage<C, Sh, DIR, 0, WS>(home, lds, kst, t, lt);
 }
 
+// NP pencils of one lane advanced stage by stage together: pencil p's LDS row
+// is lds + p * pstride. Every exchange fences once for all NP pencils, and the
+// NP independent butterfly chains give the scheduler work to overlap with
+// LDS and memory latency.
+template <typename C, typename Sh, int DIR, int s, bool WS, int NP>
+__device__ __forceinline__ void fft_stage_multi(C (&home)[NP][Sh::E], C* lds, int pstride, int kst, int t,
+                                                const LaneTw<C, Sh>& lt) {
+  constexpr int L = Sh::L, T = Sh::T, S = Sh::S;
+  constexpr int R = Sh::rad(s);
+  constexpr int Ns = Sh::ns(s);
+  constexpr int NB = L / R;
+  constexpr int PER = (NB + T - 1) / T;
+  constexpr bool EVEN = (NB % T) == 0;
+  constexpr bool FIRST_REG = (s == 0) && EVEN;
+  constexpr bool LAST_REG = (s == S - 1) && EVEN;
+
+  if constexpr (s == 0 && !FIRST_REG) {
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+      for (int m = 0; m < Sh::E; ++m) lds[p * pstride + (t + T * m) * kst] = home[p][m];
+    xsync<WS>();
+  }
+
+  C v[NP][PER][R];
+#pragma unroll
+  for (int p = 0; p < NP; ++p)
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int j = t + T * u;
+      if (EVEN || j < NB) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          if constexpr (FIRST_REG) v[p][u][r] = home[p][u + r * (NB / T)];
+          else v[p][u][r] = lds[p * pstride + (j + r * NB) * kst];
+        }
+        if constexpr (s > 0) {
+#pragma unroll
+          for (int r = 1; r < R; ++r) {
+            const C w = lt.w[LaneTw<C, Sh>::off(s) + u * (R - 1) + r - 1];
+            v[p][u][r] = (DIR > 0) ? cmulc(v[p][u][r], w) : cmul(v[p][u][r], w);
+          }
+        }
+        dft<R, DIR>(v[p][u]);
+      }
+    }
+
+  if constexpr (LAST_REG) {
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+      for (int u = 0; u < PER; ++u)
+#pragma unroll
+        for (int q = 0; q < R; ++q) home[p][u + q * (NB / T)] = v[p][u][q];
+    if constexpr (!FIRST_REG) xsync<WS>();
+  } else {
+    if constexpr (!FIRST_REG) xsync<WS>();
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int j = t + T * u;
+        if (EVEN || j < NB) {
+          const int k = j % Ns;
+          const int base = (j / Ns) * Ns * R + k;
+#pragma unroll
+          for (int q = 0; q < R; ++q) lds[p * pstride + (base + q * Ns) * kst] = v[p][u][q];
+        }
+      }
+    xsync<WS>();
+    if constexpr (s == S - 1) {
+#pragma unroll
+      for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int m = 0; m < Sh::E; ++m) home[p][m] = lds[p * pstride + (t + T * m) * kst];
+      xsync<WS>();
+    }
+  }
+  if constexpr (s + 1 < S) fft_stage_multi<C, Sh, DIR, s + 1, WS, NP>(home, lds, pstride, kst, t, lt);
+}
+
+// Unnormalised DFTs of NP pencils of the same lane (DIR = -1 forward, +1 inverse).
+template <int DIR, typename Sh, bool WS, int NP, typename C>
+__device__ __forceinline__ void fft_pencils(C (&home)[NP][Sh::E], C* lds, int pstride, int kst, int t,
+                                            const LaneTw<C, Sh>& lt) {
+  static_assert(shape_ok<Sh>(), "bad radix plan");
+  static_assert(!WS || (64 % Sh::T) == 0, "wave sync needs whole pencils per wavefront");
+  fft_stage_multi<C, Sh, DIR, 0, WS, NP>(home, lds, pstride, kst, t, lt);
+}
+
 }  // namespace sfft
