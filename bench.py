@@ -177,7 +177,7 @@ def bench_large(args):
             ws = plan.alloc_workspace(nrhs)
             torch.cuda.synchronize()
             held = free0 - torch.cuda.mem_get_info()[0]
-            ms, _ = time_plan(plan, x, y, ws, args.steps, args.warmup)
+            ms, leaf = time_plan(plan, x, y, ws, args.steps, args.warmup, profile_leaf=method == "split")
             info = plan.info()
             vb = 2 * x.numel() * 8
             out[f"{kname}_{label}"] = dict(ms_per_apply=round(ms, 4), matvecs_per_s=round(nrhs * 1e3 / ms, 1),
@@ -186,6 +186,16 @@ def bench_large(args):
                                            symbol_bytes=info["symbol_bytes"],
                                            workspace_bytes=info["workspace_bytes"],
                                            measured_plan_and_workspace_bytes=int(held))
+            if leaf is not None and leaf[1] > 0:
+                # every launch of an apply together reads and writes each of the
+                # 2^(d-1) level-(d-1) branch vectors once and reads the stored symbols once
+                per_apply = leaf[1] / args.steps
+                alg = (2 ** (len(n) - 1) * 2 * (vb // 2) + info["symbol_bytes"]) / per_apply
+                avg_s = leaf[0] / leaf[1] * 1e-3
+                out[f"{kname}_{label}"]["leaf"] = dict(
+                    avg_launch_us=round(avg_s * 1e6, 1), launches_per_apply=per_apply,
+                    algorithmic_bytes_per_launch=int(alg), achieved_gbs=round(alg / avg_s / 1e9, 1),
+                    frac=round(alg / avg_s / 1e9 / HBM_PEAK_GBS, 4))
             log(f"[large {kname} {label}] {ms:.3f} ms per apply of {nrhs} RHS")
             plan.close()
             del ws
@@ -320,6 +330,33 @@ def time_plan(plan, x, y, ws, steps, warmup, profile_leaf=False):
     return (t1 - t0) * 1e3 / steps, leaf
 
 
+def time_plan_cold(plan, x, y, ws, reps, scrub_bytes=1 << 30):
+    """Cold-cache timing: before every apply, a 1 GiB fill evicts the 256 MB
+    memory-side cache, so symbols and vectors stream from HBM. Returns the
+    mean apply time (ms, events around the apply only) and the leaf record."""
+    import torch
+    scrub = torch.empty(scrub_bytes // 4, dtype=torch.float32, device="cuda")
+    st = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(reps)]
+    plan.apply(x, y, ws)
+    torch.cuda.synchronize()
+    plan.profile(("leaf",))
+    plan.profile_read("leaf", reset=True)
+    for i in range(reps):
+        scrub.fill_(float(i))
+        ev[i][0].record(st)
+        plan.apply(x, y, ws)
+        ev[i][1].record(st)
+    torch.cuda.synchronize()
+    leaf = plan.profile_read("leaf", reset=True)
+    plan.profile(())
+    ms = sum(a.elapsed_time(b) for a, b in ev) / reps
+    del scrub
+    torch.cuda.empty_cache()
+    return ms, leaf
+
+
 def cpu_baseline(coeffs, x, budget_s):
     """The FP64 oracle's circulant-embedding matvec timed on the host cores."""
     import oracle
@@ -408,6 +445,7 @@ def main():
     if args.variants == "headline":
         variants = variants[:1]
     headline_leaf = None
+    cold = None
     for vmethod, dtype in variants:
         method = "split" if vmethod.startswith("split") else "embed"
         parity = wl.green_parity(3) if vmethod == "split_mirrored" else None
@@ -422,6 +460,8 @@ def main():
         head = (vmethod, dtype) == variants[0]
         log(f"[{vmethod} {dtype}] timing {args.steps} steps after {args.warmup} warmup")
         ms, leaf = time_plan(plan, x, y, ws, args.steps, args.warmup, profile_leaf=head)
+        if head:
+            cold = time_plan_cold(plan, x, y, ws, max(10, min(args.steps, 50)))
         vbytes = nrhs * b * s * esz
         dev_bytes = info["symbol_bytes"] + info["table_bytes"] + info["workspace_bytes"] + 2 * vbytes
         results[f"{vmethod}_{dtype}"] = dict(
@@ -445,6 +485,14 @@ def main():
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(leaf_kernel),
                     kernel=leaf_kernel, avg_launch_us=round(leaf_avg_s * 1e6, 2),
                     launches=leaf_cnt, algorithmic_bytes_per_launch=int(leaf_alg_bytes))
+
+    cold_ms, (cold_leaf_ms, cold_cnt) = cold
+    cold_leaf_s = cold_leaf_ms / max(cold_cnt, 1) * 1e-3
+    roofline["cold"] = dict(avg_launch_us=round(cold_leaf_s * 1e6, 2),
+                            achieved=round(leaf_alg_bytes / cold_leaf_s / 1e9, 1),
+                            frac=round(leaf_alg_bytes / cold_leaf_s / 1e9 / HBM_PEAK_GBS, 4),
+                            ms_per_matvec=round(cold_ms / nrhs, 5), launches=cold_cnt,
+                            note="1 GiB fill before each apply evicts the memory-side cache")
 
     copy_gbs = stream_copy_gbs()
     roofline["stream_copy_gbs"] = round(copy_gbs, 1)
