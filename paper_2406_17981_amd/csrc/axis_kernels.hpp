@@ -136,11 +136,14 @@ __global__ void __launch_bounds__(256) k_strided(PassArgs a) {
   C ph[E];  // split phases Phi[k] of this lane's entries
 #pragma unroll
   for (int m = 0; m < E; ++m) ph[m] = tw[t + T * m];
+  // loads are unconditional: an inactive column reads column 0 (base is 0
+  // there), transforms it in its own LDS column and stores nothing, so no
+  // load waits inside a branch
   C h[E];
   if constexpr (MODE == 0) {
     const C* in = (const C*)a.in + q * a.in_bs + base;
 #pragma unroll
-    for (int m = 0; m < E; ++m) h[m] = act ? in[(t + T * m) * st] : czero<C>();
+    for (int m = 0; m < E; ++m) h[m] = in[(t + T * m) * st];
     if (a.out) {
       C w[E];
 #pragma unroll
@@ -166,13 +169,15 @@ __global__ void __launch_bounds__(256) k_strided(PassArgs a) {
   } else {
     const C* in = (const C*)a.in + q * a.in_bs + base;
 #pragma unroll
-    for (int m = 0; m < E; ++m) h[m] = act ? in[(t + T * m) * st] : czero<C>();
+    for (int m = 0; m < E; ++m) h[m] = in[(t + T * m) * st];
+    C w[E];
+    if (a.in1) {  // both children requested before either transform
+      const C* in1 = (const C*)a.in1 + q * a.in_bs + base;
+#pragma unroll
+      for (int m = 0; m < E; ++m) w[m] = in1[(t + T * m) * st];
+    }
     fft_pencil<+1, Sh>(h, lp, W, t, lt);
     if (a.in1) {
-      const C* in1 = (const C*)a.in1 + q * a.in_bs + base;
-      C w[E];
-#pragma unroll
-      for (int m = 0; m < E; ++m) w[m] = act ? in1[(t + T * m) * st] : czero<C>();
       fft_pencil<+1, Sh>(w, lp, W, t, lt);
 #pragma unroll
       for (int m = 0; m < E; ++m) h[m] = cadd(h[m], a.use_phase ? cmulc(w[m], ph[m]) : w[m]);
@@ -332,11 +337,15 @@ __global__ void __launch_bounds__((Geo<Real, L>::RBMAX * Geo<Real, L>::SL)) k_le
   // components at once (runs of T consecutive entries per pencil)
   const bool act = (g < nh) && (rl < nr);
   const int64_t pbase = ((r0 + rl) * B * a.npen + p0 + g) * L + t;  // component 0
+  // loads are unconditional: an inactive (pencil, rhs) row reads pencil 0 of
+  // right-hand side 0, works on its own LDS row and stores nothing, so no load
+  // waits inside a branch
+  const int64_t lbase = act ? pbase : t;
   C x[B][E];
 #pragma unroll
   for (int c = 0; c < B; ++c)
 #pragma unroll
-    for (int m = 0; m < E; ++m) x[c][m] = act ? in[pbase + (int64_t)c * a.npen * L + T * m] : czero<C>();
+    for (int m = 0; m < E; ++m) x[c][m] = in[lbase + (int64_t)c * a.npen * L + T * m];
 
   // mirrored storage: this lane's pencil fixes the outer levels' stored index
   // and which of them are read mirrored
@@ -409,10 +418,14 @@ __global__ void __launch_bounds__((Geo<Real, L>::RBMAX * Geo<Real, L>::SL)) k_le
   // all children x components transformed together (one LDS row each)
   constexpr int NP = NPAR * B;
   C h[NP][E];
+  // split phases Phi[t + T m] = Phi[t] Phi[T m]: one per-lane value and E
+  // lane-uniform table entries, so the merge needs no second per-lane fetch
+  const C ph0 = NPAR == 2 ? tw[t] : czero<C>();
+  auto phase = [&](int m) -> C { return m == 0 ? ph0 : cmul(ph0, tw[T * m]); };
   if constexpr (NPAR == 2) {
     C ph[E];
 #pragma unroll
-    for (int m = 0; m < E; ++m) ph[m] = tw[t + T * m];
+    for (int m = 0; m < E; ++m) ph[m] = phase(m);
 #pragma unroll
     for (int c = 0; c < B; ++c)
 #pragma unroll
@@ -445,7 +458,7 @@ __global__ void __launch_bounds__((Geo<Real, L>::RBMAX * Geo<Real, L>::SL)) k_le
 #pragma unroll
     for (int c = 0; c < B; ++c)
 #pragma unroll
-      for (int m = 0; m < E; ++m) x[c][m] = cadd(h[c][m], cmulc(h[B + c][m], tw[t + T * m]));
+      for (int m = 0; m < E; ++m) x[c][m] = cadd(h[c][m], cmulc(h[B + c][m], phase(m)));
   } else {
 #pragma unroll
     for (int c = 0; c < B; ++c)
