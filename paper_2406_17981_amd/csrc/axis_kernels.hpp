@@ -28,6 +28,28 @@
 
 namespace sfft {
 
+// Division of 32-bit numerators by a fixed divisor d >= 1 with a multiply-high
+// and shifts (Granlund and Montgomery, "Division by invariant integers using
+// multiplication", 1994): l = ceil(log2 d), m = floor(2^32 (2^l - d) / d) + 1,
+//   n / d = (t + ((n - t) >> min(l, 1))) >> max(l - 1, 0),  t = mulhi(m, n).
+struct FastDiv {
+  uint32_t d, m, s1, s2;
+  static FastDiv make(uint32_t d) {
+    uint32_t l = 0;
+    while (l < 32 && (1ull << l) < d) ++l;
+    FastDiv f;
+    f.d = d;
+    f.m = (uint32_t)((((1ull << l) - d) << 32) / d + 1);
+    f.s1 = l < 1 ? l : 1;
+    f.s2 = l > 1 ? l - 1 : 0;
+    return f;
+  }
+  __device__ __forceinline__ uint32_t div(uint32_t n) const {
+    const uint32_t t = __umulhi(m, n);
+    return (t + ((n - t) >> s1)) >> s2;
+  }
+};
+
 struct PassArgs {
   const void* in;    // branch q input at in + q*in_bs (elements)
   const void* in1;   // INV2: odd child, same branch stride as in
@@ -58,6 +80,9 @@ struct PassArgs {
   int64_t mst[6];    // strides of the stored array
   int64_t mcomp;     // stored entries per component
   uint64_t odd_bits; // bit (ab*6 + l): component ab is odd along level l (b*b <= 9, d <= 6)
+  // filled by the launchers: block and column decoding without 64-bit division
+  FastDiv fd_a, fd_b;  // strided: tiles per branch, inner; leaf: rhs groups, tile groups of 8
+  int idx32;           // every decoded index fits in 32 bits
 };
 
 // Launch geometry per length.
@@ -121,12 +146,23 @@ __global__ void __launch_bounds__(256) k_strided(PassArgs a) {
   const int tid = threadIdx.x;
   const int c = tid % W, t = tid / W;
   const int64_t cols = a.outer * a.inner;
-  const int64_t ntile = (cols + W - 1) / W;
-  const int64_t q = blockIdx.x / ntile;
-  const int64_t col = (blockIdx.x % ntile) * W + c;
+  int64_t q, col, o, i;
+  if (a.idx32) {
+    const uint32_t bq = a.fd_a.div(blockIdx.x);
+    q = bq;
+    col = (int64_t)(blockIdx.x - bq * a.fd_a.d) * W + c;
+    const uint32_t oc = a.fd_b.div((uint32_t)col);
+    o = oc;
+    i = (uint32_t)col - oc * a.fd_b.d;
+  } else {
+    const int64_t ntile = (cols + W - 1) / W;
+    q = blockIdx.x / ntile;
+    col = (blockIdx.x % ntile) * W + c;
+    o = col / a.inner;
+    i = col - o * a.inner;
+  }
   const bool act = col < cols;
-  const int64_t o = act ? col / a.inner : 0;
-  const int64_t i = act ? col - o * a.inner : 0;
+  if (!act) o = i = 0;
   const int64_t base = o * L * a.inner + i;
   const int64_t st = a.inner;
   const C* tw = (const C*)a.tw;
@@ -232,9 +268,16 @@ __global__ void __launch_bounds__(256) k_contig(PassArgs a) {
   __shared__ C lds[P * LP];
   const int tid = threadIdx.x;
   const int g = tid / T, t = tid % T;
-  const int64_t ntile = (a.outer + P - 1) / P;
-  const int64_t q = blockIdx.x / ntile;
-  const int64_t p0 = (blockIdx.x % ntile) * P;
+  int64_t q, p0;
+  if (a.idx32) {
+    const uint32_t bq = a.fd_a.div(blockIdx.x);
+    q = bq;
+    p0 = (int64_t)(blockIdx.x - bq * a.fd_a.d) * P;
+  } else {
+    const int64_t ntile = (a.outer + P - 1) / P;
+    q = blockIdx.x / ntile;
+    p0 = (blockIdx.x % ntile) * P;
+  }
   const int nh = (int)((a.outer - p0) < P ? (a.outer - p0) : P);
   const C* tw = (const C*)a.tw;
   C* lp = lds + g * LP;
@@ -311,15 +354,24 @@ __global__ void __launch_bounds__((Geo<Real, L>::RBMAX * Geo<Real, L>::SL)) k_le
   const int rl = gr % RB;
   const int g = gr / RB;
   const int row = g * RB + rl;
-  const int64_t nrg = (a.nrhs + RB - 1) / RB;
-  const int64_t ntiles8 = (a.ntiles + 7) / 8;
-  const int64_t id = blockIdx.x;
-  const int64_t lo = id & 7;
-  const int64_t t2 = id >> 3;
-  const int64_t rg = t2 % nrg;
-  const int64_t t3 = t2 / nrg;
-  const int64_t tile = (t3 % ntiles8) * 8 + lo;
-  const int64_t q = t3 / ntiles8;
+  const int64_t lo = blockIdx.x & 7;
+  int64_t rg, tile, q;
+  if (a.idx32) {
+    const uint32_t t2 = blockIdx.x >> 3;
+    const uint32_t t3 = a.fd_a.div(t2);
+    rg = t2 - t3 * a.fd_a.d;
+    const uint32_t t4 = a.fd_b.div(t3);
+    tile = (int64_t)(t3 - t4 * a.fd_b.d) * 8 + lo;
+    q = t4;
+  } else {
+    const int64_t nrg = (a.nrhs + RB - 1) / RB;
+    const int64_t ntiles8 = (a.ntiles + 7) / 8;
+    const int64_t t2 = blockIdx.x >> 3;
+    rg = t2 % nrg;
+    const int64_t t3 = t2 / nrg;
+    tile = (t3 % ntiles8) * 8 + lo;
+    q = t3 / ntiles8;
+  }
   if (tile >= a.ntiles) return;  // whole workgroup exits together
   const int64_t p0 = tile * P;
   const int nh = (int)((a.npen - p0) < P ? (a.npen - p0) : P);
@@ -490,20 +542,33 @@ struct AxisOps {
   pass_fn leaf_mirror[5];  // [B], NPAR = 2, mirrored symbol storage
 };
 
+constexpr int64_t kIdx32 = (int64_t)1 << 31;
+
 template <typename Real, int L, int MODE> hipError_t launch_strided(const PassArgs& a, hipStream_t s) {
   using G = Geo<Real, L>;
   const int64_t cols = a.outer * a.inner;
-  const int64_t blocks = a.nq * ((cols + G::W - 1) / G::W);
+  const int64_t ntile = (cols + G::W - 1) / G::W;
+  const int64_t blocks = a.nq * ntile;
   if (blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_strided<Real, L, MODE>), dim3((unsigned)blocks), dim3(G::NT), 0, s, a);
+  PassArgs b = a;
+  b.idx32 = blocks < kIdx32 && ntile * G::W < kIdx32;
+  if (b.idx32) {
+    b.fd_a = FastDiv::make((uint32_t)ntile);
+    b.fd_b = FastDiv::make((uint32_t)a.inner);
+  }
+  hipLaunchKernelGGL((k_strided<Real, L, MODE>), dim3((unsigned)blocks), dim3(G::NT), 0, s, b);
   return hipGetLastError();
 }
 
 template <typename Real, int L, int MODE> hipError_t launch_contig(const PassArgs& a, hipStream_t s) {
   using G = Geo<Real, L>;
-  const int64_t blocks = a.nq * ((a.outer + G::P - 1) / G::P);
+  const int64_t ntile = (a.outer + G::P - 1) / G::P;
+  const int64_t blocks = a.nq * ntile;
   if (blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_contig<Real, L, MODE>), dim3((unsigned)blocks), dim3(G::NT), 0, s, a);
+  PassArgs b = a;
+  b.idx32 = blocks < kIdx32;
+  if (b.idx32) b.fd_a = FastDiv::make((uint32_t)ntile);
+  hipLaunchKernelGGL((k_contig<Real, L, MODE>), dim3((unsigned)blocks), dim3(G::NT), 0, s, b);
   return hipGetLastError();
 }
 
@@ -519,6 +584,11 @@ hipError_t launch_leaf(const PassArgs& a, hipStream_t s) {
   const int64_t nrg = (a.nrhs + rb - 1) / rb;
   const int64_t blocks = a.nq * ((a.ntiles + 7) / 8) * nrg * 8;
   if (blocks <= 0) return hipSuccess;
+  b.idx32 = blocks < kIdx32;
+  if (b.idx32) {
+    b.fd_a = FastDiv::make((uint32_t)nrg);
+    b.fd_b = FastDiv::make((uint32_t)((a.ntiles + 7) / 8));
+  }
   const size_t smem = (size_t)rb * row_bytes;
   hipLaunchKernelGGL((k_leaf<Real, L, B, NPAR, MIR>), dim3((unsigned)blocks), dim3(rb * G::SL), smem, s, b);
   return hipGetLastError();
