@@ -160,6 +160,7 @@ def bench_large(args):
     y = torch.empty_like(x)
     del x_host
     out = {}
+    fp64_check = {}
     for kname in ("green", "skew"):
         coeffs = wl.green_coeffs(n, cfg["k"]) if kname == "green" else wl.skew_coeffs(n, cfg["k"])
         par = wl.green_parity(3) if kname == "green" else wl.skew_parity(3)
@@ -197,14 +198,29 @@ def bench_large(args):
                     algorithmic_bytes_per_launch=int(alg), achieved_gbs=round(alg / avg_s / 1e9, 1),
                     frac=round(alg / avg_s / 1e9 / HBM_PEAK_GBS, 4))
             log(f"[large {kname} {label}] {ms:.3f} ms per apply of {nrhs} RHS")
+            if kname == "green" and label == "split_depth":
+                y_c64 = y.clone()
             plan.close()
             del ws
+            torch.cuda.empty_cache()
+        if kname == "green":
+            # FP64 residual of the complex64 product: the same product through a
+            # complex128 plan, compared on the device in FP64
+            plan = sf.Plan(n, 3, cd, dtype="c128", method="split", max_nrhs=nrhs, schedule="depth")
+            x128 = x.to(torch.complex128)
+            y128 = plan.apply(x128, workspace=plan.alloc_workspace(nrhs))
+            rel = (torch.linalg.vector_norm(y_c64.to(torch.complex128) - y128)
+                   / torch.linalg.vector_norm(y128)).item()
+            fp64_check = {"green_split_depth_rel_l2_c64_vs_c128": float(f"{rel:.3e}")}
+            log(f"[large green] rel L2 of the c64 product against the c128 product: {rel:.3e}")
+            plan.close()
+            del x128, y128, y_c64
             torch.cuda.empty_cache()
         del cd
         torch.cuda.empty_cache()
     g = out
     line = {"workload": "green/skew-256x256x128-b3-8rhs-c64", "grid": list(n), "b": 3, "nrhs": nrhs,
-            "steps": args.steps, "warmup": args.warmup, "results": g,
+            "steps": args.steps, "warmup": args.warmup, "results": g, "fp64_residual": fp64_check,
             "split_depth_vs_embed": {
                 "speedup": round(g["green_embed"]["ms_per_apply"] / g["green_split_depth"]["ms_per_apply"], 3),
                 "device_bytes_ratio_embed_over_split": round(g["green_embed"]["device_bytes"]

@@ -94,6 +94,8 @@ typedef struct {
  *   out       host: receives the plan handle (NULL on failure).
  *   d         levels, 1 <= d <= 6.
  *   n         host: d level sizes; each must have built kernels (as must 2 n_l).
+ *             A level of size 1 (offset 0 only) is dropped internally; at least
+ *             one level must be larger (else SFFT_UNSUPPORTED).
  *   b         block size (1 or 3).
  *   coeffs    device, complex128 (b, b, 2n_1-1, ..., 2n_d-1); read during the
  *             call only (the stream is synchronised before return, the caller
@@ -113,10 +115,13 @@ sfft_status sfft_plan_create(sfft_plan* out, int d, const int64_t* n, int b, con
                              int dtype, int method, const int32_t* parity, int64_t max_nrhs,
                              int schedule, void* stream);
 
-/* Device bytes of workspace sfft_apply needs for nrhs right-hand sides. */
+/* Device bytes of workspace sfft_apply needs for nrhs >= 0 right-hand sides
+ * (0 for nrhs = 0). */
 sfft_status sfft_workspace_size(sfft_plan plan, int64_t nrhs, size_t* bytes);
 
 /* y = T x for nrhs right-hand sides (Algorithm 1, or the embedding baseline).
+ *   nrhs       >= 0; nrhs = 0 is an empty batch: SFFT_OK, nothing is touched
+ *              (x, y and workspace may then be NULL).
  *   x, y       device (nrhs, b, n...) of the plan dtype; y must not overlap x.
  *   workspace  device, at least sfft_workspace_size bytes, 256-byte aligned,
  *              caller owned; NULL makes the plan allocate (and keep) its own,
@@ -133,7 +138,8 @@ sfft_status sfft_apply(sfft_plan plan, const void* x, void* y, int64_t nrhs, voi
  * forked stream (so problems run side by side) and replayed by one graph
  * launch on `stream`; the instantiated graph is cached for the same
  * arguments and dropped when one of its plans is destroyed. SFFT_NO_GRAPH=1
- * in the environment issues the problems one after another instead. */
+ * in the environment issues the problems one after another instead. A problem
+ * with nrhs[i] = 0 is skipped (its x[i], y[i] may be NULL). */
 sfft_status sfft_workspace_size_multi(int nprob, const sfft_plan* plans, const int64_t* nrhs,
                                       size_t* bytes);
 sfft_status sfft_apply_multi(int nprob, const sfft_plan* plans, const void* const* x,

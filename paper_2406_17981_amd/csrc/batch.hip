@@ -205,7 +205,7 @@ sfft_status sfft_apply_multi(int nprob, const sfft_plan* plans, const void* cons
   std::vector<size_t> off(nprob), wsz(nprob);
   size_t o = 0;
   for (int i = 0; i < nprob; ++i) {
-    wsz[i] = sfft_rt_align256(sfft_rt_workspace_elems(plans[i], nrhs[i]) * plans[i]->esz);
+    wsz[i] = nrhs[i] > 0 ? sfft_rt_align256(sfft_rt_workspace_elems(plans[i], nrhs[i]) * plans[i]->esz) : 0;
     off[i] = o;
     o += wsz[i];
   }
@@ -240,7 +240,8 @@ sfft_status sfft_apply_multi(int nprob, const sfft_plan* plans, const void* cons
   }
   // argument checks happen outside capture so an invalid call never starts one
   for (int i = 0; i < nprob; ++i) {
-    if (!plans[i] || !x[i] || !y[i] || nrhs[i] < 1) return sfft_rt_fail(SFFT_INVALID_ARG, "bad problem entry");
+    if (!plans[i] || nrhs[i] < 0 || (nrhs[i] > 0 && (!x[i] || !y[i])))
+      return sfft_rt_fail(SFFT_INVALID_ARG, "bad problem entry");
   }
   GraphEntry ent;
   ent.key = key;

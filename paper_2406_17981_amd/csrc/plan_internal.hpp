@@ -20,6 +20,8 @@ constexpr int kMaxD = 6;
 struct sfft_plan_s {
   int d = 0;
   int64_t n[kMaxD] = {0};
+  int user_d = 0;               // the caller's levels (size-1 levels are dropped from d, n)
+  int64_t user_n[kMaxD] = {0};
   int b = 1;
   int dtype = SFFT_C64;
   int method = SFFT_SPLIT;

@@ -582,8 +582,9 @@ bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb) {
 
 sfft_status apply_one(sfft_plan_s* p, const void* x, void* y, int64_t nrhs, void* ws, size_t ws_bytes,
                       hipStream_t st) {
+  if (nrhs < 0) return fail(SFFT_INVALID_ARG, "nrhs must be >= 0");
+  if (nrhs == 0) return SFFT_OK;  // empty batch: nothing is read or written
   if (!x || !y) return fail(SFFT_INVALID_ARG, "x and y must be non-null device pointers");
-  if (nrhs < 1) return fail(SFFT_INVALID_ARG, "nrhs must be >= 1");
   const size_t vbytes = (size_t)vec_elems(p, nrhs) * p->esz;
   if (ranges_overlap(x, vbytes, y, vbytes)) return fail(SFFT_INVALID_ARG, "y must not overlap x");
   const size_t need = workspace_elems(p, nrhs) * p->esz;
@@ -659,29 +660,52 @@ sfft_status sfft_plan_create(sfft_plan* out, int d, const int64_t* n, int b, con
   if (method != SFFT_SPLIT && method != SFFT_EMBED) return fail(SFFT_INVALID_ARG, "bad method");
   if (schedule < SFFT_SCHED_AUTO || schedule > SFFT_SCHED_DEPTH) return fail(SFFT_INVALID_ARG, "bad schedule");
   if (max_nrhs < 1) return fail(SFFT_INVALID_ARG, "max_nrhs must be >= 1");
-  for (int l = 0; l < d; ++l) {
+  for (int l = 0; l < d; ++l)
     if (n[l] < 1) return fail(SFFT_INVALID_ARG, "level sizes must be >= 1");
+  if (parity)
+    for (int i = 0; i < b * b * d; ++i)
+      if (parity[i] < SFFT_PARITY_NONE || parity[i] > SFFT_PARITY_ODD)
+        return fail(SFFT_INVALID_ARG, "bad parity entry");
+  // A level of size 1 has the single offset 0: the operator is block Toeplitz
+  // over the other levels, with the same memory layout for coefficients and
+  // vectors, so such levels are dropped (with their parity entries).
+  const int user_d = d;
+  const int64_t* user_n = n;
+  int64_t n_eff[kMaxD];
+  std::vector<int32_t> par_eff;
+  {
+    int k = 0;
+    for (int l = 0; l < d; ++l)
+      if (n[l] > 1) n_eff[k++] = n[l];
+    if (k == 0) return fail(SFFT_UNSUPPORTED, "every level has size 1 (a single grid point)");
+    if (parity) {
+      for (int ab = 0; ab < b * b; ++ab)
+        for (int l = 0; l < d; ++l)
+          if (n[l] > 1) par_eff.push_back(parity[ab * d + l]);
+      parity = par_eff.data();
+    }
+    d = k;
+    n = n_eff;
+  }
+  for (int l = 0; l < d; ++l) {
     if (!find_ops(dtype, 2 * n[l]))
       return fail(SFFT_UNSUPPORTED, "no kernels for length " + std::to_string(2 * n[l]));
     if (method == SFFT_SPLIT && !find_ops(dtype, n[l]))
       return fail(SFFT_UNSUPPORTED, "no kernels for length " + std::to_string(n[l]));
   }
   bool mirror = false;
-  if (parity) {
+  if (parity && method == SFFT_SPLIT) {
     for (int i = 0; i < b * b * d; ++i)
-      if (parity[i] < SFFT_PARITY_NONE || parity[i] > SFFT_PARITY_ODD)
-        return fail(SFFT_INVALID_ARG, "bad parity entry");
-    if (method == SFFT_SPLIT) {
-      for (int i = 0; i < b * b * d; ++i)
-        if (parity[i] == SFFT_PARITY_NONE)
-          return fail(SFFT_UNSUPPORTED, "mirrored storage needs every (component, level) even or odd");
-      mirror = true;
-    }
+      if (parity[i] == SFFT_PARITY_NONE)
+        return fail(SFFT_UNSUPPORTED, "mirrored storage needs every (component, level) even or odd");
+    mirror = true;
   }
 
   sfft_plan_s* p = new sfft_plan_s();
   hipStream_t st = (hipStream_t)stream;
   p->d = d;
+  p->user_d = user_d;
+  for (int l = 0; l < user_d; ++l) p->user_n[l] = user_n[l];
   p->b = b;
   p->dtype = dtype;
   p->method = method;
@@ -741,8 +765,8 @@ sfft_status sfft_plan_create(sfft_plan* out, int d, const int64_t* n, int b, con
 
 sfft_status sfft_workspace_size(sfft_plan plan, int64_t nrhs, size_t* bytes) {
   if (!plan || !bytes) return fail(SFFT_INVALID_ARG, "null argument");
-  if (nrhs < 1) return fail(SFFT_INVALID_ARG, "nrhs must be >= 1");
-  *bytes = workspace_elems(plan, nrhs) * plan->esz;
+  if (nrhs < 0) return fail(SFFT_INVALID_ARG, "nrhs must be >= 0");
+  *bytes = nrhs == 0 ? 0 : workspace_elems(plan, nrhs) * plan->esz;
   return SFFT_OK;
 }
 
@@ -756,8 +780,8 @@ sfft_status sfft_workspace_size_multi(int nprob, const sfft_plan* plans, const i
   if (nprob < 0 || (nprob > 0 && (!plans || !nrhs)) || !bytes) return fail(SFFT_INVALID_ARG, "null argument");
   size_t total = 0;
   for (int i = 0; i < nprob; ++i) {
-    if (!plans[i] || nrhs[i] < 1) return fail(SFFT_INVALID_ARG, "bad problem entry");
-    total += sfft_rt_align256(workspace_elems(plans[i], nrhs[i]) * plans[i]->esz);
+    if (!plans[i] || nrhs[i] < 0) return fail(SFFT_INVALID_ARG, "bad problem entry");
+    if (nrhs[i] > 0) total += sfft_rt_align256(workspace_elems(plans[i], nrhs[i]) * plans[i]->esz);
   }
   *bytes = total;
   return SFFT_OK;
@@ -766,8 +790,8 @@ sfft_status sfft_workspace_size_multi(int nprob, const sfft_plan* plans, const i
 sfft_status sfft_plan_info(sfft_plan plan, sfft_info* info) {
   if (!plan || !info) return fail(SFFT_INVALID_ARG, "null argument");
   std::memset(info, 0, sizeof(*info));
-  info->d = plan->d;
-  for (int l = 0; l < plan->d; ++l) info->n[l] = plan->n[l];
+  info->d = plan->user_d;
+  for (int l = 0; l < plan->user_d; ++l) info->n[l] = plan->user_n[l];
   info->b = plan->b;
   info->dtype = plan->dtype;
   info->method = plan->method;

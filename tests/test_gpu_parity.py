@@ -264,3 +264,53 @@ def test_large_green_and_skew_full_size(sf, large_points):
                  f"symbol_bytes={info['symbol_bytes']} workspace={info['workspace_bytes']}")
             assert err <= 1e-5
         del coeffs
+
+
+# ---------------------------------------------------------------------------
+# Degenerate and empty inputs
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("grid,b", [((1, 12, 10), 3), ((6, 1, 8), 1), ((16, 1), 3), ((1, 1, 24), 1)])
+def test_levels_of_size_one(sf, grid, b, dtype):
+    """A level of size 1 only has offset 0; the product still equals the
+    dense definition (the plan drops such levels internally)."""
+    coeffs = wl.iid_coeffs(31, grid, b)
+    x = wl.vectors(32, grid, b, 2)
+    want = oracle.dense_matvec(coeffs, x)
+    got = _run(sf, coeffs, x, dtype, "split")
+    assert wl.relative_l2(got, want) <= TOL[dtype]
+    plan = sf.Plan(grid, b, torch.from_numpy(coeffs).cuda(), dtype=dtype)
+    assert plan.info()["n"] == tuple(grid) and plan.info()["d"] == len(grid)
+    plan.close()
+
+
+def test_single_point_grid_is_rejected(sf):
+    grid = (1, 1)
+    with pytest.raises(sf.SfftError, match="UNSUPPORTED"):
+        sf.Plan(grid, 1, torch.from_numpy(wl.iid_coeffs(1, grid, 1)).cuda(), dtype="c64")
+
+
+def test_empty_batch_is_a_no_op(sf):
+    import ctypes as C
+    from paper_2406_17981_amd import _native as N
+    grid, b = (8, 6, 10), 3
+    coeffs = wl.iid_coeffs(41, grid, b)
+    plan = sf.Plan(grid, b, torch.from_numpy(coeffs).cuda(), dtype="c64")
+    assert plan.workspace_size(0) == 0
+    # through the C ABI with NULL buffers
+    assert N.lib.sfft_apply(plan.handle, None, None, 0, None, 0, None) == 0
+    # through the binding with (0, b, *n) tensors
+    x0 = torch.empty((0, b) + grid, dtype=torch.complex64, device="cuda")
+    y0 = plan.apply(x0)
+    assert tuple(y0.shape) == (0, b) + grid
+    # an empty problem inside a batch leaves the others intact
+    x = wl.vectors(42, grid, b, 2)
+    xd = torch.from_numpy(x.astype(np.complex64)).cuda()
+    y = torch.empty_like(xd)
+    y_empty = torch.empty_like(x0)
+    sf.apply_multi([plan, plan], [x0, xd], [y_empty, y])
+    torch.cuda.synchronize()
+    got = y.cpu().numpy().astype(np.complex128)
+    assert wl.relative_l2(got, oracle.embed_matvec(coeffs, x)) <= TOL["c64"]
+    assert N.lib.sfft_apply(plan.handle, None, None, -1, None, 0, None) != 0
+    plan.close()

@@ -113,6 +113,21 @@ def test_split_alg1_matches_dense(n, b):
     assert wl.relative_l2(got, want) < 1e-13
 
 
+@pytest.mark.parametrize("n,b", [((1, 5, 4), 3), ((4, 1, 3), 1), ((6, 1), 2)])
+def test_size_one_level_reduces_to_fewer_levels(n, b):
+    """A level of size 1 has the single offset 0, so the operator is the
+    block-Toeplitz operator of the remaining levels with that coefficient
+    slice (same memory layout); all three oracle paths agree with it."""
+    c = wl.iid_coeffs(71, n, b)
+    x = wl.vectors(72, n, b, 2)
+    keep = tuple(v for v in n if v > 1)
+    c2 = c.reshape((b, b) + tuple(2 * v - 1 for v in keep))
+    x2 = x.reshape((2, b) + keep)
+    want = oracle.dense_matvec(c2, x2).reshape(x.shape)
+    for got in (oracle.dense_matvec(c, x), oracle.embed_matvec(c, x), oracle.split_alg1(c, x)):
+        assert wl.relative_l2(got, want) < 1e-13
+
+
 def test_plain_16_config_three_ways():
     """The 16^3 scalar problem: dense, embedding and Algorithm 1 agree."""
     t, x = wl.plain_16()
