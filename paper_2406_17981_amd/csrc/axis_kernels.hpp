@@ -420,6 +420,18 @@ __global__ void __launch_bounds__((Geo<Real, L>::RBMAX * Geo<Real, L>::SL)) k_le
     }
   }
   const int slane = g * T + t;  // lane inside the symbol block
+  // mirrored storage: bit ab of osign is set when component ab enters this
+  // lane's pencil negated through the outer levels' mirrors; bit ab of lodd
+  // when component ab is odd along the last level (lane-uniform)
+  uint32_t osign = 0, lodd = 0;
+  if constexpr (MIR) {
+#pragma unroll
+    for (int ab = 0; ab < B * B; ++ab) {
+      const uint32_t odd = (uint32_t)(a.odd_bits >> (ab * 6)) & 0x3fu;
+      osign |= (uint32_t)(__builtin_popcount(mbits & odd) & 1) << ab;
+      lodd |= ((odd >> (a.d - 1)) & 1u) << ab;
+    }
+  }
 
   // mulBrn for one child p: w[.][m] <- S_p[., .](m) w[.][m]
   auto block_product = [&](C (&w)[B][E], int p) {
@@ -428,21 +440,32 @@ __global__ void __launch_bounds__((Geo<Real, L>::RBMAX * Geo<Real, L>::SL)) k_le
 #pragma unroll
     for (int m0 = 0; m0 < E; m0 += MS) {
       C sm[MS][B * B];
+      if constexpr (MIR) {
+        // stored index along the last level and the sign flips, shared by all
+        // block components
+        // 32-bit byte offsets from a lane-uniform base per component (plan
+        // creation keeps one stored component below 4 GiB)
+        uint32_t off[MS];
+        uint32_t flip[MS];
+#pragma unroll
+        for (int j = 0; j < MS; ++j) {
+          const int k = t + T * (m0 + j);
+          const bool mir = 2 * k + p > L;
+          off[j] = ((uint32_t)mbase + (uint32_t)(p * (L / 2 + 1) + (mir ? (p ? L - 1 - k : L - k) : k))) *
+                   (uint32_t)sizeof(C);
+          flip[j] = osign ^ (mir ? lodd : 0u);
+        }
+#pragma unroll
+        for (int ab = 0; ab < B * B; ++ab) {
+          const char* base = (const char*)a.sym + ab * a.mcomp * (int64_t)sizeof(C);
+#pragma unroll
+          for (int j = 0; j < MS; ++j)
+            sm[j][ab] = cneg_if(*(const C*)(base + off[j]), (flip[j] >> ab) & 1u);
+        }
+      }
 #pragma unroll
       for (int ab = 0; ab < B * B; ++ab) {
         if constexpr (MIR) {
-          const int64_t n = L;
-          const int ld = a.d - 1;
-          const uint32_t odd = (uint32_t)(a.odd_bits >> (ab * 6)) & 0x3fu;
-#pragma unroll
-          for (int j = 0; j < MS; ++j) {
-            const int64_t k = t + T * (m0 + j);
-            const bool mir = 2 * k + p > n;
-            const int64_t jj = mir ? (p ? n - 1 - k : n - k) : k;
-            const uint32_t bits = mbits | ((uint32_t)mir << ld);
-            const C v = ((const C*)a.sym)[ab * a.mcomp + mbase + p * (n / 2 + 1) + jj];
-            sm[j][ab] = (__builtin_popcount(bits & odd) & 1) ? mk<C>(-v.x, -v.y) : v;
-          }
         } else if constexpr (MS == 2) {
           const C2 v = *(const C2*)(sp + sym_offset(ab, m0, slane, E, SL));
           sm[0][ab] = mk<C>(v.x, v.y);

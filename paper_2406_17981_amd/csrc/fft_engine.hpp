@@ -41,6 +41,16 @@ template <typename C> __device__ __forceinline__ C cmulc(C a, C b) {
 }
 template <typename C> __device__ __forceinline__ C cscale(C a, decltype(C::x) s) { return mk<C>(a.x * s, a.y * s); }
 template <typename C> __device__ __forceinline__ C czero() { return mk<C>(0, 0); }
+// -a when s is 1, a when s is 0 (sign bits flipped, no compare or select)
+__device__ __forceinline__ float2 cneg_if(float2 a, uint32_t s) {
+  const uint32_t m = s << 31;
+  return make_float2(__uint_as_float(__float_as_uint(a.x) ^ m), __uint_as_float(__float_as_uint(a.y) ^ m));
+}
+__device__ __forceinline__ double2 cneg_if(double2 a, uint32_t s) {
+  const unsigned long long m = (unsigned long long)s << 63;
+  return make_double2(__longlong_as_double(__double_as_longlong(a.x) ^ (long long)m),
+                      __longlong_as_double(__double_as_longlong(a.y) ^ (long long)m));
+}
 // (DIR * i) * a, DIR = -1 forward, +1 inverse
 template <int DIR, typename C> __device__ __forceinline__ C mul_di(C a) {
   if constexpr (DIR > 0) return mk<C>(-a.y, a.x);

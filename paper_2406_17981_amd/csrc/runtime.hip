@@ -698,6 +698,10 @@ sfft_status sfft_plan_create(sfft_plan* out, int d, const int64_t* n, int b, con
     for (int i = 0; i < b * b * d; ++i)
       if (parity[i] == SFFT_PARITY_NONE)
         return fail(SFFT_UNSUPPORTED, "mirrored storage needs every (component, level) even or odd");
+    double bytes = dtype == SFFT_C64 ? 8 : 16;  // the leaf addresses one component with 32-bit offsets
+    for (int l = 0; l < d; ++l) bytes *= (double)(n[l] + 1);
+    if (bytes >= 4294967296.0)
+      return fail(SFFT_UNSUPPORTED, "mirrored storage holds at most 4 GiB per block component");
     mirror = true;
   }
 
