@@ -187,6 +187,8 @@ def bench_large(args):
                                            symbol_bytes=info["symbol_bytes"],
                                            workspace_bytes=info["workspace_bytes"],
                                            measured_plan_and_workspace_bytes=int(held))
+            lat = apply_latencies(plan, x, y, ws, max(args.steps, 10))
+            out[f"{kname}_{label}"]["apply_ms_p10_p50_p90"] = [round(v / 1e3, 4) for v in lat]
             if leaf is not None and leaf[1] > 0:
                 # every launch of an apply together reads and writes each of the
                 # 2^(d-1) level-(d-1) branch vectors once and reads the stored symbols once
@@ -346,6 +348,30 @@ def time_plan(plan, x, y, ws, steps, warmup, profile_leaf=False):
     return (t1 - t0) * 1e3 / steps, leaf
 
 
+def apply_latencies(plan, x, y, ws, reps, scrub_bytes=0):
+    """Per-apply device time (HIP events around each apply on the current
+    stream), optionally after a fill of scrub_bytes that evicts the
+    memory-side cache; returns (p10, p50, p90) in microseconds."""
+    import numpy as np
+    import torch
+    scrub = torch.empty(max(scrub_bytes // 4, 1), dtype=torch.float32, device="cuda")
+    st = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    plan.apply(x, y, ws)
+    torch.cuda.synchronize()
+    for i in range(reps):
+        if scrub_bytes:
+            scrub.fill_(float(i))
+        ev[i][0].record(st)
+        plan.apply(x, y, ws)
+        ev[i][1].record(st)
+    torch.cuda.synchronize()
+    us = np.array([a.elapsed_time(b) * 1e3 for a, b in ev])
+    del scrub
+    torch.cuda.empty_cache()
+    return tuple(round(float(v), 2) for v in np.percentile(us, [10, 50, 90]))
+
+
 def time_plan_cold(plan, x, y, ws, reps, scrub_bytes=1 << 30):
     """Cold-cache timing: before every apply, a 1 GiB fill evicts the 256 MB
     memory-side cache, so symbols and vectors stream from HBM. Returns the
@@ -461,7 +487,7 @@ def main():
     if args.variants == "headline":
         variants = variants[:1]
     headline_leaf = None
-    cold = None
+    cold = lat_warm = lat_cold = None
     for vmethod, dtype in variants:
         method = "split" if vmethod.startswith("split") else "embed"
         parity = wl.green_parity(3) if vmethod == "split_mirrored" else None
@@ -478,6 +504,8 @@ def main():
         ms, leaf = time_plan(plan, x, y, ws, args.steps, args.warmup, profile_leaf=head)
         if head:
             cold = time_plan_cold(plan, x, y, ws, max(10, min(args.steps, 50)))
+            lat_warm = apply_latencies(plan, x, y, ws, 100)
+            lat_cold = apply_latencies(plan, x, y, ws, 50, scrub_bytes=1 << 30)
         vbytes = nrhs * b * s * esz
         dev_bytes = info["symbol_bytes"] + info["table_bytes"] + info["workspace_bytes"] + 2 * vbytes
         results[f"{vmethod}_{dtype}"] = dict(
@@ -541,6 +569,9 @@ def main():
                    "method": "split", "schedule": head["schedule"],
                    "kernel": "3x3 Green blocks exp(ik|r|)/|r| (I - rr^T), k=0.7, self 2I"},
         "roofline": roofline,
+        "latency_us": {"warm": dict(zip(("p10", "p50", "p90"), lat_warm)),
+                       "cold": dict(zip(("p10", "p50", "p90"), lat_cold)),
+                       "note": "device time per apply (events around each apply); cold: after a 1 GiB fill"},
         "cpu_baseline": cpu,
         "variants": {k: {kk: (round(vv, 6) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                      for k, v in results.items()},
