@@ -194,7 +194,10 @@ typedef enum {
 
 /* Bracket every later launch of the kinds set in mask (bit k = kind k) with a
  * pair of HIP events recorded on the apply stream; mask 0 stops recording.
- * Not for concurrent applies of one plan. */
+ * Records accumulate until read with reset (about 2 events per launch);
+ * concurrent applies of one plan may record (the record list is locked), but
+ * enabling or disabling while applies run races with them. Launches inside
+ * sfft_apply_multi's captured graphs are not recorded. */
 sfft_status sfft_profile_enable(sfft_plan plan, unsigned mask);
 /* Waits for the recorded events of one kind and returns their summed
  * duration in milliseconds and the launch count; reset != 0 clears them. */

@@ -49,7 +49,10 @@ struct sfft_plan_s {
   void* pool = nullptr;
   size_t pool_bytes = 0;
   // profiling hooks: event pairs around launches of the kinds in prof_mask
+  // (records and the free list are guarded by prof_mu, so applies of one plan
+  // from several host threads may profile at once)
   unsigned prof_mask = 0;
+  std::mutex prof_mu;
   struct Rec {
     int kind;
     hipEvent_t a, b;

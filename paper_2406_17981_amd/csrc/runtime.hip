@@ -279,14 +279,19 @@ struct ProfScope {
   hipEvent_t a = nullptr, b = nullptr;
   ProfScope(const sfft_plan_s* pc, int k, hipStream_t s) : p(const_cast<sfft_plan_s*>(pc)), st(s), kind(k) {
     if (p->prof_mask & (1u << k)) {
-      a = take_event(p);
-      b = take_event(p);
+      {
+        std::lock_guard<std::mutex> g(p->prof_mu);
+        a = take_event(p);
+        b = take_event(p);
+      }
       if (a && b) (void)hipEventRecord(a, st);
     }
   }
   ~ProfScope() {
+    if (!a && !b) return;
+    if (a && b) (void)hipEventRecord(b, st);
+    std::lock_guard<std::mutex> g(p->prof_mu);
     if (a && b) {
-      (void)hipEventRecord(b, st);
       p->prof_recs.push_back({kind, a, b});
     } else {
       if (a) p->prof_free.push_back(a);
@@ -433,10 +438,11 @@ sfft_status embed_apply(const sfft_plan_s* p, const void* x, void* y, int64_t nr
   {
     ProfScope ps(p, SFFT_KIND_COPY, st);
     if (p->dtype == SFFT_C64)
-    hipLaunchKernelGGL(k_pad<float2>, dim3(grid_for(big)), dim3(256), 0, st, (const float2*)x, (float2*)ws, dm, big);
-  else
-    hipLaunchKernelGGL(k_pad<double2>, dim3(grid_for(big)), dim3(256), 0, st, (const double2*)x, (double2*)ws, dm,
-                       big);
+      hipLaunchKernelGGL(k_pad<float2>, dim3(grid_for(big)), dim3(256), 0, st, (const float2*)x, (float2*)ws, dm,
+                         big);
+    else
+      hipLaunchKernelGGL(k_pad<double2>, dim3(grid_for(big)), dim3(256), 0, st, (const double2*)x, (double2*)ws,
+                         dm, big);
   }
   HIP_TRY(hipGetLastError(), "pad launch");
   sfft_status s;
@@ -458,11 +464,11 @@ sfft_status embed_apply(const sfft_plan_s* p, const void* x, void* y, int64_t nr
   {
     ProfScope ps(p, SFFT_KIND_COPY, st);
     if (p->dtype == SFFT_C64)
-    hipLaunchKernelGGL(k_project<float2>, dim3(grid_for(small)), dim3(256), 0, st, (const float2*)ws, (float2*)y, dm,
-                       small);
-  else
-    hipLaunchKernelGGL(k_project<double2>, dim3(grid_for(small)), dim3(256), 0, st, (const double2*)ws, (double2*)y,
-                       dm, small);
+      hipLaunchKernelGGL(k_project<float2>, dim3(grid_for(small)), dim3(256), 0, st, (const float2*)ws, (float2*)y,
+                         dm, small);
+    else
+      hipLaunchKernelGGL(k_project<double2>, dim3(grid_for(small)), dim3(256), 0, st, (const double2*)ws,
+                         (double2*)y, dm, small);
   }
   HIP_TRY(hipGetLastError(), "project launch");
   return SFFT_OK;
@@ -817,6 +823,7 @@ sfft_status sfft_profile_enable(sfft_plan plan, unsigned mask) {
 
 sfft_status sfft_profile_read(sfft_plan plan, int kind, double* total_ms, int64_t* launches, int reset) {
   if (!plan || !total_ms || !launches) return fail(SFFT_INVALID_ARG, "null argument");
+  std::lock_guard<std::mutex> g(plan->prof_mu);
   double tot = 0.0;
   int64_t cnt = 0;
   for (auto& r : plan->prof_recs) {
