@@ -290,6 +290,7 @@ def bench_serve(args):
     each request a 30-step Arnoldi chain of matvecs. Continuous batching in
     complex64 with mirrored symbols under an HBM budget, against the plain
     FP64 path (one request at a time, full symbols) on the same stream."""
+    import numpy as np
     import torch
     import workloads as wl
     from paper_2406_17981_amd import serve
@@ -312,6 +313,8 @@ def bench_serve(args):
         done = srv.run(rs)
         torch.cuda.synchronize()
         summ = serve.latency_summary(done)
+        gm = [r.result["gmres_residual"] for r in done if r.result]
+        summ["gmres_residual_median"] = float(f"{float(np.median(gm)):.3e}") if gm else None
         summ.update(wall_s=round(time.perf_counter() - t0, 3), server_steps=srv.steps_run,
                     host_s_admit=round(srv.time_in["admit"], 3), host_s_step=round(srv.time_in["step"], 3),
                     host_s_finish=round(srv.time_in["finish"], 3),

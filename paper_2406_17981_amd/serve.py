@@ -14,7 +14,10 @@ The server
   kernels overlap on the device, then one sfft_arnoldi_step_multi call
   orthogonalises all of them;
 * admits new requests between steps as slots and memory free up (continuous
-  batching), and records arrival, admission and completion times.
+  batching), and records arrival, admission and completion times;
+* finishes a request with the GMRES solve of T x = b on its chain: the small
+  least-squares problem min ||beta e_1 - H y|| on the host and x = V y on the
+  device.
 
 Every kernel is deterministic and works on one request's buffers only, so a
 request's results are bitwise the same alone and in any mix.
@@ -294,12 +297,27 @@ class GpuExecutor(Executor):
         self._arnoldi(jobs)
 
     def finish(self, slot) -> dict:
-        self.torch.cuda.current_stream().synchronize()
+        """GMRES on the finished chain: y = argmin ||beta e_1 - H y|| (a small
+        host least-squares problem), x = V_m y on the device; returns H, beta,
+        y, the residual estimate ||beta e_1 - H y|| / beta and, when kept, the
+        basis and x."""
+        torch = self.torch
+        torch.cuda.current_stream().synchronize()
         req = slot["req"]
+        m = req.steps
         Hc = slot["Hc"].cpu().numpy()
-        out = dict(H=Hc[:req.steps].T.copy(), start_norm=float(Hc[req.steps, 0].real))
+        H = Hc[:m].T.copy()                      # (m+1, m) upper Hessenberg
+        beta = float(Hc[m, 0].real)              # ||b||
+        rhs = np.zeros(m + 1, dtype=np.complex128)
+        rhs[0] = beta
+        y = np.linalg.lstsq(H, rhs, rcond=None)[0]
+        res = float(np.linalg.norm(rhs - H @ y) / beta) if beta > 0 else 0.0
+        out = dict(H=H, start_norm=beta, y=y, gmres_residual=res)
         if self.keep_basis:
-            out["basis"] = slot["basis"].cpu().numpy()
+            V = slot["basis"]
+            out["basis"] = V.cpu().numpy()
+            yd = torch.from_numpy(y).to(device=V.device)
+            out["x"] = (V[:m].to(torch.complex128).transpose(0, 1) @ yd).cpu().numpy()
         return out
 
     def release(self, slot) -> None:

@@ -64,3 +64,29 @@ def test_results_identical_alone_and_in_the_mix(serve):
         alone = _run(serve, [r], max_active=1)[r.rid]
         assert np.array_equal(alone.result["H"], mixed[r.rid].result["H"]), r.rid
         assert np.array_equal(alone.result["basis"], mixed[r.rid].result["basis"]), r.rid
+
+
+@pytest.mark.parametrize("dtype,mirrored,tol", [("c64", True, 1e-4), ("c128", False, 1e-10)])
+def test_gmres_solution_residual_matches_estimate(serve, dtype, mirrored, tol):
+    """x = V_m y from the least-squares problem: its true residual ||b - T x||,
+    with T applied by the FP64 oracle, equals the Hessenberg estimate, and the
+    estimate does not grow with the number of steps (GMRES minimises it)."""
+    done = _run(serve, _requests(serve, steps=10), dtype, mirrored)
+    for rid, r in done.items():
+        res = r.result
+        V = res["basis"].astype(np.complex128)
+        b = res["start_norm"] * V[0]
+        coeffs = wl.green_coeffs(r.n, r.k)
+        Tx = oracle.embed_matvec(coeffs, res["x"].reshape((3,) + tuple(r.n))).reshape(-1)
+        true = np.linalg.norm(b - Tx) / np.linalg.norm(b)
+        assert abs(true - res["gmres_residual"]) <= tol, (rid, true, res["gmres_residual"])
+        H = res["H"]
+        prev = 1.0 + 1e-12
+        for m in range(1, r.steps + 1):
+            rhs = np.zeros(m + 1, dtype=np.complex128)
+            rhs[0] = res["start_norm"]
+            Hm = H[:m + 1, :m]
+            y = np.linalg.lstsq(Hm, rhs, rcond=None)[0]
+            est = np.linalg.norm(rhs - Hm @ y) / res["start_norm"]
+            assert est <= prev + 1e-12, (rid, m)
+            prev = est
