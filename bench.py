@@ -522,6 +522,20 @@ def main():
         del x, y, ws
         torch.cuda.empty_cache()
 
+    if args.variants == "all":
+        # context: the same operator on 8 right-hand sides per apply (the leaf
+        # fetches each symbol block once for the right-hand sides of a workgroup)
+        x8 = torch.from_numpy(wl.vectors(203, n, b, 8).astype(np.complex64)).cuda()
+        plan = sf.Plan(n, b, coeffs_d, dtype="c64", method="split", max_nrhs=8, schedule=args.schedule)
+        y8 = torch.empty_like(x8)
+        ws8 = plan.alloc_workspace(8)
+        ms8, _ = time_plan(plan, x8, y8, ws8, max(args.steps // 4, 10), args.warmup)
+        results["split_c64_8rhs"] = dict(matvecs_per_s=8e3 / ms8, ms_per_apply=ms8,
+                                         schedule=["auto", "breadth", "depth"][plan.info()["schedule"]])
+        plan.close()
+        del x8, y8, ws8
+        torch.cuda.empty_cache()
+
     (leaf_ms, leaf_cnt), info, vbytes, ms = headline_leaf
     leaf_avg_s = leaf_ms / max(leaf_cnt, 1) * 1e-3
     nbr = 2 ** (d - 1)  # leaf launch: every branch prefix of levels 1..d-1
