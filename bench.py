@@ -426,8 +426,12 @@ def cpu_baseline(coeffs, x, budget_s):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed applies (default 1000 for the headline workload, 10 large, 50 batch)")
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed applies first (default 2000 for the headline workload, whose "
+                         "applies are short and would otherwise run before the GPU clocks ramp up; "
+                         "2 large, 5 batch)")
     ap.add_argument("--schedule", default="auto", choices=["auto", "breadth", "depth"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -442,6 +446,11 @@ def main():
                          "batch: 8 uneven-grid problems, 64 RHS, one graph")
     ap.add_argument("--pmc-summarize", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON"))
     args = ap.parse_args()
+    steps_default, warmup_default = {"large": (10, 2), "batch": (50, 5)}.get(args.workload, (1000, 2000))
+    if args.steps is None:
+        args.steps = steps_default
+    if args.warmup is None:
+        args.warmup = warmup_default
 
     if args.pmc_summarize:
         pmc_summarize(*args.pmc_summarize)
@@ -486,7 +495,7 @@ def main():
     results = {}
     outputs = {}
     variants = [("split", "c64"), ("split", "c128"), ("embed", "c64"), ("embed", "c128"),
-                ("split_mirrored", "c64"), ("split_mirrored", "c128")]
+                ("split_mirrored", "c64"), ("split_mirrored", "c128"), ("split_all9", "c64")]
     if args.variants == "headline":
         variants = variants[:1]
     headline_leaf = None
@@ -496,8 +505,13 @@ def main():
         parity = wl.green_parity(3) if vmethod == "split_mirrored" else None
         tdt = torch.complex64 if dtype == "c64" else torch.complex128
         esz = 8 if dtype == "c64" else 16
+        # split_all9: the symbols of all 9 block components, as for a kernel
+        # without block symmetry (the Green blocks are symmetric: 6 are stored)
+        if vmethod == "split_all9":
+            os.environ["SFFT_NO_BLOCK_SYMMETRY"] = "1"
         plan = sf.Plan(n, b, coeffs_d, dtype=dtype, method=method, max_nrhs=nrhs,
                        schedule=args.schedule, parity=parity)
+        os.environ.pop("SFFT_NO_BLOCK_SYMMETRY", None)
         info = plan.info()
         x = torch.from_numpy(x_host).to(tdt).cuda()
         y = torch.empty_like(x)
@@ -514,7 +528,8 @@ def main():
         results[f"{vmethod}_{dtype}"] = dict(
             matvecs_per_s=nrhs * 1e3 / ms, ms_per_matvec=ms, schedule=["auto", "breadth", "depth"][info["schedule"]],
             device_bytes=dev_bytes, symbol_bytes=info["symbol_bytes"],
-            workspace_bytes=info["workspace_bytes"], vector_bytes=vbytes)
+            workspace_bytes=info["workspace_bytes"], vector_bytes=vbytes,
+            block_symmetry=info["block_symmetry"])
         outputs[f"{vmethod}_{dtype}"] = y.cpu().numpy().astype(np.complex128)
         if head:
             headline_leaf = (leaf, info, vbytes, ms)

@@ -82,6 +82,8 @@ typedef struct {
   size_t table_bytes;      /* device bytes of twiddle tables */
   size_t workspace_bytes;  /* sfft_workspace_size at max_nrhs */
   int64_t vector_elems;    /* b * prod(n_l): entries of one right-hand side */
+  int block_symmetry;      /* 0, or 1 / 2 when t[a,c] = t[c,a] / -t[c,a] at every offset:
+                              the symbol then stores the b(b+1)/2 components a <= c */
 } sfft_info;
 
 /* Build a plan and its Fourier-space symbols.

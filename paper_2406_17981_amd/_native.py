@@ -36,7 +36,7 @@ class SfftInfo(C.Structure):
         ("d", C.c_int), ("n", C.c_int64 * 8), ("b", C.c_int), ("dtype", C.c_int),
         ("method", C.c_int), ("schedule", C.c_int), ("compressed", C.c_int),
         ("max_nrhs", C.c_int64), ("symbol_bytes", C.c_size_t), ("table_bytes", C.c_size_t),
-        ("workspace_bytes", C.c_size_t), ("vector_elems", C.c_int64),
+        ("workspace_bytes", C.c_size_t), ("vector_elems", C.c_int64), ("block_symmetry", C.c_int),
     ]
 
 

@@ -79,7 +79,7 @@ struct PassArgs {
   int64_t mn[6];     // level sizes
   int64_t mst[6];    // strides of the stored array
   int64_t mcomp;     // stored entries per component
-  uint64_t odd_bits; // bit (ab*6 + l): component ab is odd along level l (b*b <= 9, d <= 6)
+  uint64_t odd_bits; // bit (k*6 + l): stored component k is odd along level l (k < 9, d <= 6)
   // filled by the launchers: block and column decoding without 64-bit division
   FastDiv fd_a, fd_b;  // strided: tiles per branch, inner; leaf: rhs groups, tile groups of 8
   int idx32;           // every decoded index fits in 32 bits
@@ -118,6 +118,21 @@ template <typename Real, int L> struct Geo {
   // single exchange the pencils go one after another through one row, which
   // keeps LDS per workgroup (and so occupancy) low
   template <int B, int NPAR> static constexpr int leaf_rows() { return LSh::S >= 3 ? NPAR * B : 1; }
+};
+
+// Stored block components. BS = 0: all B*B components, index a*B + c.
+// BS = 1 (t(r)[a,c] = t(r)[c,a] at every offset) and BS = 2 (t(r)[a,c] =
+// -t(r)[c,a]): the B(B+1)/2 components a <= c, the product reading (a, c)
+// with a > c from (c, a), negated for BS = 2. The symbol inherits the
+// relation component by component (the transforms are linear).
+template <int B, int BS> struct BlockSym {
+  static constexpr int NS = BS == 0 ? B * B : B * (B + 1) / 2;
+  static constexpr int idx(int a, int c) {
+    if (BS == 0) return a * B + c;
+    const int i = a < c ? a : c, j = a < c ? c : a;
+    return i * B - i * (i - 1) / 2 + (j - i);
+  }
+  static constexpr bool neg(int a, int c) { return BS == 2 && a > c; }
 };
 
 // Position of symbol entry (block component ab, home index m, lane) inside one
@@ -334,17 +349,20 @@ __global__ void __launch_bounds__(256) k_contig(PassArgs a) {
 // workgroup's RB, lane t of the pencil; the RB lanes of one (g, t) read the
 // same symbol addresses in one wavefront instruction, so a symbol block is
 // fetched once for all RB right-hand sides. Symbols per (branch, parity,
-// tile): [a*B + c][m/2][g*T + t][m%2] (see sym_offset), or mirrored storage.
+// tile): [k][m/2][g*T + t][m%2] over the stored block components k
+// (BlockSym, sym_offset), or mirrored storage.
 // Workgroups of one tile are numbered 8 apart, so all of a tile's
 // right-hand-side groups run on the same XCD and share its L2.
 // ---------------------------------------------------------------------------
-template <typename Real, int L, int B, int NPAR, bool MIR>
+template <typename Real, int L, int B, int NPAR, bool MIR, int BS>
 __global__ void __launch_bounds__((Geo<Real, L>::RBMAX * Geo<Real, L>::SL)) k_leaf(PassArgs a) {
   using C = cx<Real>;
   using G = Geo<Real, L>;
   using Sh = typename G::LSh;
   using C2 = typename PairOf<C>::type;
   constexpr int T = G::LT, E = G::LE, P = G::PL, LP = G::LLP, SL = G::SL;
+  using BSy = BlockSym<B, BS>;
+  constexpr int NS = BSy::NS;  // stored block components
   extern __shared__ __align__(16) unsigned char leaf_smem[];
   C* lds = reinterpret_cast<C*>(leaf_smem);
   const int RB = a.rb;
@@ -420,26 +438,26 @@ __global__ void __launch_bounds__((Geo<Real, L>::RBMAX * Geo<Real, L>::SL)) k_le
     }
   }
   const int slane = g * T + t;  // lane inside the symbol block
-  // mirrored storage: bit ab of osign is set when component ab enters this
-  // lane's pencil negated through the outer levels' mirrors; bit ab of lodd
-  // when component ab is odd along the last level (lane-uniform)
+  // mirrored storage: bit k of osign is set when stored component k enters
+  // this lane's pencil negated through the outer levels' mirrors; bit k of
+  // lodd when component k is odd along the last level (lane-uniform)
   uint32_t osign = 0, lodd = 0;
   if constexpr (MIR) {
 #pragma unroll
-    for (int ab = 0; ab < B * B; ++ab) {
-      const uint32_t odd = (uint32_t)(a.odd_bits >> (ab * 6)) & 0x3fu;
-      osign |= (uint32_t)(__builtin_popcount(mbits & odd) & 1) << ab;
-      lodd |= ((odd >> (a.d - 1)) & 1u) << ab;
+    for (int k = 0; k < NS; ++k) {
+      const uint32_t odd = (uint32_t)(a.odd_bits >> (k * 6)) & 0x3fu;
+      osign |= (uint32_t)(__builtin_popcount(mbits & odd) & 1) << k;
+      lodd |= ((odd >> (a.d - 1)) & 1u) << k;
     }
   }
 
   // mulBrn for one child p: w[.][m] <- S_p[., .](m) w[.][m]
   auto block_product = [&](C (&w)[B][E], int p) {
-    const C* sp = (const C*)a.sym + q * a.sym_bs + ((int64_t)p * a.ntiles + tile) * (B * B * E * SL);
+    const C* sp = (const C*)a.sym + q * a.sym_bs + ((int64_t)p * a.ntiles + tile) * (NS * E * SL);
     constexpr int MS = (E % 2 == 0) ? 2 : 1;  // entries per symbol load
 #pragma unroll
     for (int m0 = 0; m0 < E; m0 += MS) {
-      C sm[MS][B * B];
+      C sm[MS][NS];
       if constexpr (MIR) {
         // stored index along the last level and the sign flips, shared by all
         // block components
@@ -456,22 +474,22 @@ __global__ void __launch_bounds__((Geo<Real, L>::RBMAX * Geo<Real, L>::SL)) k_le
           flip[j] = osign ^ (mir ? lodd : 0u);
         }
 #pragma unroll
-        for (int ab = 0; ab < B * B; ++ab) {
-          const char* base = (const char*)a.sym + ab * a.mcomp * (int64_t)sizeof(C);
+        for (int k = 0; k < NS; ++k) {
+          const char* base = (const char*)a.sym + k * a.mcomp * (int64_t)sizeof(C);
 #pragma unroll
           for (int j = 0; j < MS; ++j)
-            sm[j][ab] = cneg_if(*(const C*)(base + off[j]), (flip[j] >> ab) & 1u);
+            sm[j][k] = cneg_if(*(const C*)(base + off[j]), (flip[j] >> k) & 1u);
         }
       }
 #pragma unroll
-      for (int ab = 0; ab < B * B; ++ab) {
+      for (int k = 0; k < NS; ++k) {
         if constexpr (MIR) {
         } else if constexpr (MS == 2) {
-          const C2 v = *(const C2*)(sp + sym_offset(ab, m0, slane, E, SL));
-          sm[0][ab] = mk<C>(v.x, v.y);
-          sm[1][ab] = mk<C>(v.z, v.w);
+          const C2 v = *(const C2*)(sp + sym_offset(k, m0, slane, E, SL));
+          sm[0][k] = mk<C>(v.x, v.y);
+          sm[1][k] = mk<C>(v.z, v.w);
         } else {
-          sm[0][ab] = sp[sym_offset(ab, m0, slane, E, SL)];
+          sm[0][k] = sp[sym_offset(k, m0, slane, E, SL)];
         }
       }
 #pragma unroll
@@ -481,7 +499,10 @@ __global__ void __launch_bounds__((Geo<Real, L>::RBMAX * Geo<Real, L>::SL)) k_le
         for (int ar = 0; ar < B; ++ar) {
           C u = czero<C>();
 #pragma unroll
-          for (int c = 0; c < B; ++c) u = cadd(u, cmul(sm[j][ar * B + c], w[c][m0 + j]));
+          for (int c = 0; c < B; ++c) {
+            const C v = cmul(sm[j][BSy::idx(ar, c)], w[c][m0 + j]);
+            u = BSy::neg(ar, c) ? csub(u, v) : cadd(u, v);
+          }
           o[ar] = u;
         }
 #pragma unroll
@@ -561,8 +582,8 @@ struct AxisOps {
   int RBMAX;           // leaf: most right-hand sides per workgroup
   pass_fn strided[2];   // [0] FWD2, [1] INV2
   pass_fn contig[2];
-  pass_fn leaf[5][3];   // [B][NPAR], null where not built
-  pass_fn leaf_mirror[5];  // [B], NPAR = 2, mirrored symbol storage
+  pass_fn leaf[5][3][3];    // [B][NPAR][block symmetry], null where not built
+  pass_fn leaf_mirror[5][3];  // [B][block symmetry], NPAR = 2, mirrored symbol storage
 };
 
 constexpr int64_t kIdx32 = (int64_t)1 << 31;
@@ -595,7 +616,7 @@ template <typename Real, int L, int MODE> hipError_t launch_contig(const PassArg
   return hipGetLastError();
 }
 
-template <typename Real, int L, int B, int NPAR, bool MIR = false>
+template <typename Real, int L, int B, int NPAR, bool MIR = false, int BS = 0>
 hipError_t launch_leaf(const PassArgs& a, hipStream_t s) {
   using G = Geo<Real, L>;
   constexpr size_t row_bytes = (size_t)G::PL * G::LLP * sizeof(cx<Real>) * G::template leaf_rows<B, NPAR>();
@@ -613,7 +634,7 @@ hipError_t launch_leaf(const PassArgs& a, hipStream_t s) {
     b.fd_b = FastDiv::make((uint32_t)((a.ntiles + 7) / 8));
   }
   const size_t smem = (size_t)rb * row_bytes;
-  hipLaunchKernelGGL((k_leaf<Real, L, B, NPAR, MIR>), dim3((unsigned)blocks), dim3(rb * G::SL), smem, s, b);
+  hipLaunchKernelGGL((k_leaf<Real, L, B, NPAR, MIR, BS>), dim3((unsigned)blocks), dim3(rb * G::SL), smem, s, b);
   return hipGetLastError();
 }
 
@@ -623,12 +644,23 @@ template <typename Real, int L> const AxisOps* make_ops() {
       L, G::T, G::E, G::W, G::P, G::LT, G::LE, G::PL, G::NTL, G::RBMAX,
       {launch_strided<Real, L, 0>, launch_strided<Real, L, 1>},
       {launch_contig<Real, L, 0>, launch_contig<Real, L, 1>},
-      {{nullptr, nullptr, nullptr},
-       {nullptr, launch_leaf<Real, L, 1, 1>, launch_leaf<Real, L, 1, 2>},
-       {nullptr, nullptr, nullptr},
-       {nullptr, launch_leaf<Real, L, 3, 1>, launch_leaf<Real, L, 3, 2>},
-       {nullptr, nullptr, nullptr}},
-      {nullptr, launch_leaf<Real, L, 1, 2, true>, nullptr, launch_leaf<Real, L, 3, 2, true>, nullptr},
+      {{},
+       {{},
+        {launch_leaf<Real, L, 1, 1>, launch_leaf<Real, L, 1, 1>, launch_leaf<Real, L, 1, 1>},
+        {launch_leaf<Real, L, 1, 2>, launch_leaf<Real, L, 1, 2>, launch_leaf<Real, L, 1, 2>}},
+       {},
+       {{},
+        {launch_leaf<Real, L, 3, 1, false, 0>, launch_leaf<Real, L, 3, 1, false, 1>,
+         launch_leaf<Real, L, 3, 1, false, 2>},
+        {launch_leaf<Real, L, 3, 2, false, 0>, launch_leaf<Real, L, 3, 2, false, 1>,
+         launch_leaf<Real, L, 3, 2, false, 2>}},
+       {}},
+      {{},
+       {launch_leaf<Real, L, 1, 2, true>, launch_leaf<Real, L, 1, 2, true>, launch_leaf<Real, L, 1, 2, true>},
+       {},
+       {launch_leaf<Real, L, 3, 2, true, 0>, launch_leaf<Real, L, 3, 2, true, 1>,
+        launch_leaf<Real, L, 3, 2, true, 2>},
+       {}},
   };
   return &ops;
 }

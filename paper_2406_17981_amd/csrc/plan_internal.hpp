@@ -38,6 +38,11 @@ struct sfft_plan_s {
   int64_t sym_bs = 0;  // symbol entries per leaf branch prefix
   int64_t ntiles = 0;  // leaf tiles per component per rhs
   int64_t npen = 0;    // leaf pencils per component per rhs
+  // block symmetry of the coefficients (0 none, 1 symmetric, 2 antisymmetric)
+  // and the stored block components: comp_of[k] = a*b + c of stored component k
+  int bsym = 0;
+  int ns = 1;
+  int comp_of[9] = {0};
   // mirrored symbol storage (compressed = 1)
   int64_t mst[kMaxD] = {0};
   int64_t mcomp = 0;

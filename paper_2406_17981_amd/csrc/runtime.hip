@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -105,10 +106,11 @@ __global__ void k_embed_generator(const double2* __restrict__ coeffs, double2* _
 }
 
 // Parity de-interleave of one FP64 symbol component into the leaf layout of
-// the split plan: [Q][p][tile][a*B + c][m][lane] with Q the branch prefix
-// over levels 1..d-1 (level 1 most significant) and p the last level's bit.
+// the split plan: [Q][p][tile][k][m][lane] with Q the branch prefix over
+// levels 1..d-1 (level 1 most significant), p the last level's bit and k
+// the stored component (NS per block).
 template <typename C>
-__global__ void k_scatter_split(const double2* __restrict__ full, C* __restrict__ sym, int ab, int B, Dims dm,
+__global__ void k_scatter_split(const double2* __restrict__ full, C* __restrict__ sym, int ks, int NS, Dims dm,
                                 int T, int E, int NT, int P, int64_t ntiles, int64_t npen, double scale,
                                 int64_t total) {
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
@@ -121,7 +123,7 @@ __global__ void k_scatter_split(const double2* __restrict__ full, C* __restrict_
     const int64_t Q = pq >> 1;
     const int64_t pencil = tile * P + tid / T;
     const int64_t k = tid % T + (int64_t)T * m;
-    const int64_t dst = (pq * ntiles + tile) * B * B * E * NT + sfft::sym_offset(ab, m, tid, E, NT);
+    const int64_t dst = (pq * ntiles + tile) * NS * E * NT + sfft::sym_offset(ks, m, tid, E, NT);
     if (pencil >= npen) {
       sym[dst] = sfft::mk<C>(0, 0);
       continue;
@@ -141,10 +143,10 @@ __global__ void k_scatter_split(const double2* __restrict__ full, C* __restrict_
   }
 }
 
-// Full symbol of the embedding baseline in the leaf layout: [tile][a*B+c][m][lane]
+// Full symbol of the embedding baseline in the leaf layout: [tile][k][m][lane]
 // over pencils of the 2n-grid.
 template <typename C>
-__global__ void k_scatter_embed(const double2* __restrict__ full, C* __restrict__ sym, int ab, int B, int T,
+__global__ void k_scatter_embed(const double2* __restrict__ full, C* __restrict__ sym, int ks, int NS, int T,
                                 int E, int NT, int P, int64_t ntiles, int64_t npen, int64_t L,
                                 double scale, int64_t total) {
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
@@ -154,7 +156,7 @@ __global__ void k_scatter_embed(const double2* __restrict__ full, C* __restrict_
     const int64_t tile = idx / ((int64_t)NT * E);
     const int64_t pencil = tile * P + tid / T;
     const int64_t k = tid % T + (int64_t)T * m;
-    const int64_t dst = tile * B * B * E * NT + sfft::sym_offset(ab, m, tid, E, NT);
+    const int64_t dst = tile * NS * E * NT + sfft::sym_offset(ks, m, tid, E, NT);
     if (pencil >= npen) {
       sym[dst] = sfft::mk<C>(0, 0);
       continue;
@@ -168,7 +170,7 @@ __global__ void k_scatter_embed(const double2* __restrict__ full, C* __restrict_
 // s_l in [0, n_l] along every level, s_l < n_l/2+1 holding the even bin
 // 2 s_l of the 2n_l lattice and the rest the odd bins 2 (s_l - n_l/2 - 1) + 1.
 template <typename C>
-__global__ void k_scatter_mirror(const double2* __restrict__ full, C* __restrict__ sym, int ab, Dims dm,
+__global__ void k_scatter_mirror(const double2* __restrict__ full, C* __restrict__ sym, int ks, Dims dm,
                                  double scale, int64_t total) {
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
@@ -183,7 +185,7 @@ __global__ void k_scatter_mirror(const double2* __restrict__ full, C* __restrict
       fstride *= 2 * n;
     }
     const double2 v = full[fidx];
-    sym[(int64_t)ab * total + idx] = sfft::mk<C>((decltype(C::x))(v.x * scale), (decltype(C::x))(v.y * scale));
+    sym[(int64_t)ks * total + idx] = sfft::mk<C>((decltype(C::x))(v.x * scale), (decltype(C::x))(v.y * scale));
   }
 }
 
@@ -218,6 +220,31 @@ __global__ void k_project(const C* __restrict__ P, C* __restrict__ y, Dims dm, i
       sstride *= 2 * dm.n[l];
     }
     y[idx] = P[rem * sstride + src];
+  }
+}
+
+// Block symmetry of the coefficients, exactly: for every pair a < c, bit 0 of
+// flags[pair] is set if some offset has t[a,c] != t[c,a], bit 1 if some
+// offset has t[a,c] != -t[c,a]. One atomic per wavefront that saw a mismatch.
+__global__ void k_block_symmetry(const double2* __restrict__ coeffs, int B, int64_t ncoef, unsigned* flags) {
+  unsigned bits = 0;  // bit 2*pair + {0: not symmetric, 1: not antisymmetric}
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < ncoef;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    int pr = 0;
+    for (int a = 0; a < B; ++a)
+      for (int c = a + 1; c < B; ++c, ++pr) {
+        const double2 u = coeffs[(int64_t)(a * B + c) * ncoef + idx];
+        const double2 v = coeffs[(int64_t)(c * B + a) * ncoef + idx];
+        if (!(u.x == v.x && u.y == v.y)) bits |= 1u << (2 * pr);
+        if (!(u.x == -v.x && u.y == -v.y)) bits |= 2u << (2 * pr);
+      }
+  }
+  for (int off = 32; off > 0; off >>= 1) bits |= __shfl_xor(bits, off, 64);
+  if (bits && (threadIdx.x % 64) == 0) {
+    for (int pr = 0; pr < B * (B - 1) / 2; ++pr) {
+      const unsigned f = (bits >> (2 * pr)) & 3u;
+      if (f) atomicOr(&flags[pr], f);
+    }
   }
 }
 
@@ -345,11 +372,11 @@ sfft_status run_leaf(const sfft_plan_s* p, const void* in, void* out, int64_t in
     }
     a.mcomp = p->mcomp;
     a.odd_bits = p->odd_bits;
-    f = o->leaf_mirror[p->b];
+    f = o->leaf_mirror[p->b][p->bsym];
   } else {
     a.sym = (const char*)p->sym + (size_t)(q0 * p->sym_bs) * p->esz;
     a.sym_bs = p->sym_bs;
-    f = o->leaf[p->b][p->method == SFFT_SPLIT ? 2 : 1];
+    f = o->leaf[p->b][p->method == SFFT_SPLIT ? 2 : 1][p->bsym];
   }
   if (!f) return fail(SFFT_UNSUPPORTED, "no leaf kernel for this block size");
   ProfScope ps(p, SFFT_KIND_LEAF, st);
@@ -509,6 +536,35 @@ sfft_status make_table(int dtype, int64_t L, void** out, size_t* bytes, hipStrea
   return SFFT_OK;
 }
 
+// Exact block (anti)symmetry of the coefficient array (b, b, 2n_1-1, ...):
+// 1 if t[a,c] == t[c,a] at every offset for every pair, 2 if t[a,c] ==
+// -t[c,a] everywhere, else 0. SFFT_NO_BLOCK_SYMMETRY=1 reports 0.
+sfft_status detect_block_symmetry(const double2* coeffs, int b, int64_t ncoef, hipStream_t st, int* bsym) {
+  *bsym = 0;
+  const char* env = std::getenv("SFFT_NO_BLOCK_SYMMETRY");
+  if (b < 2 || (env && env[0] && env[0] != '0')) return SFFT_OK;
+  const int npair = b * (b - 1) / 2;
+  unsigned* flags = nullptr;
+  HIP_TRY(hipMalloc((void**)&flags, npair * sizeof(unsigned)), "symmetry flags allocation");
+  std::vector<unsigned> h(npair, 0);
+  hipError_t e = hipMemsetAsync(flags, 0, npair * sizeof(unsigned), st);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_block_symmetry, dim3(grid_for(ncoef)), dim3(256), 0, st, coeffs, b, ncoef, flags);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(h.data(), flags, npair * sizeof(unsigned), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(flags);
+  if (e != hipSuccess) return hip_fail(e, "block symmetry check");
+  bool sym = true, anti = true;
+  for (unsigned f : h) {
+    sym = sym && !(f & 1u);
+    anti = anti && !(f & 2u);
+  }
+  *bsym = sym ? 1 : (anti ? 2 : 0);
+  return SFFT_OK;
+}
+
 sfft_status build_symbols(sfft_plan_s* p, const double2* coeffs, hipStream_t st) {
   const int d = p->d;
   Dims dm;
@@ -534,7 +590,8 @@ sfft_status build_symbols(sfft_plan_s* p, const double2* coeffs, hipStream_t st)
   }
   const double scale = 1.0 / ((double)full);  // 2^-d / prod(n)
   const AxisOps* lo = p->ops[d - 1];
-  for (int ab = 0; ab < p->b * p->b && s == SFFT_OK; ++ab) {
+  for (int ks = 0; ks < p->ns && s == SFFT_OK; ++ks) {
+    const int ab = p->comp_of[ks];
     hipLaunchKernelGGL(k_embed_generator, dim3(grid_for(full)), dim3(256), 0, st, coeffs, tmp, ab, dm, full);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
@@ -546,27 +603,28 @@ sfft_status build_symbols(sfft_plan_s* p, const double2* coeffs, hipStream_t st)
       const int64_t total = p->mcomp;
       if (p->dtype == SFFT_C64)
         hipLaunchKernelGGL(k_scatter_mirror<float2>, dim3(grid_for(total)), dim3(256), 0, st, tmp, (float2*)p->sym,
-                           ab, dm, scale, total);
+                           ks, dm, scale, total);
       else
         hipLaunchKernelGGL(k_scatter_mirror<double2>, dim3(grid_for(total)), dim3(256), 0, st, tmp,
-                           (double2*)p->sym, ab, dm, scale, total);
+                           (double2*)p->sym, ks, dm, scale, total);
     } else if (p->method == SFFT_SPLIT) {
       const int64_t total = (int64_t(1) << d) * p->ntiles * lo->LE * lo->NTL;
       if (p->dtype == SFFT_C64)
         hipLaunchKernelGGL(k_scatter_split<float2>, dim3(grid_for(total)), dim3(256), 0, st, tmp, (float2*)p->sym,
-                           ab, p->b, dm, lo->LT, lo->LE, lo->NTL, lo->PL, p->ntiles, p->npen, scale, total);
+                           ks, p->ns, dm, lo->LT, lo->LE, lo->NTL, lo->PL, p->ntiles, p->npen, scale, total);
       else
         hipLaunchKernelGGL(k_scatter_split<double2>, dim3(grid_for(total)), dim3(256), 0, st, tmp,
-                           (double2*)p->sym, ab, p->b, dm, lo->LT, lo->LE, lo->NTL, lo->PL, p->ntiles, p->npen,
+                           (double2*)p->sym, ks, p->ns, dm, lo->LT, lo->LE, lo->NTL, lo->PL, p->ntiles, p->npen,
                            scale, total);
     } else {
       const int64_t total = p->ntiles * lo->LE * lo->NTL;
       if (p->dtype == SFFT_C64)
         hipLaunchKernelGGL(k_scatter_embed<float2>, dim3(grid_for(total)), dim3(256), 0, st, tmp, (float2*)p->sym,
-                           ab, p->b, lo->LT, lo->LE, lo->NTL, lo->PL, p->ntiles, p->npen, p->L[d - 1], scale, total);
+                           ks, p->ns, lo->LT, lo->LE, lo->NTL, lo->PL, p->ntiles, p->npen, p->L[d - 1], scale,
+                           total);
       else
         hipLaunchKernelGGL(k_scatter_embed<double2>, dim3(grid_for(total)), dim3(256), 0, st, tmp,
-                           (double2*)p->sym, ab, p->b, lo->LT, lo->LE, lo->NTL, lo->PL, p->ntiles, p->npen,
+                           (double2*)p->sym, ks, p->ns, lo->LT, lo->LE, lo->NTL, lo->PL, p->ntiles, p->npen,
                            p->L[d - 1], scale, total);
     }
     e = hipGetLastError();
@@ -740,6 +798,18 @@ sfft_status sfft_plan_create(sfft_plan* out, int d, const int64_t* n, int b, con
   for (int l = 0; l < d - 1; ++l) p->npen *= p->L[l];
   p->ntiles = (p->npen + lo->PL - 1) / lo->PL;
   const int npar = method == SFFT_SPLIT ? 2 : 1;
+  {
+    int64_t ncoef = 1;
+    for (int l = 0; l < d; ++l) ncoef *= 2 * n[l] - 1;
+    sfft_status sb = detect_block_symmetry((const double2*)coeffs, b, ncoef, st, &p->bsym);
+    if (sb != SFFT_OK) {
+      delete p;
+      return sb;
+    }
+    p->ns = 0;
+    for (int a = 0; a < b; ++a)
+      for (int c = p->bsym ? a : 0; c < b; ++c) p->comp_of[p->ns++] = a * b + c;
+  }
   if (mirror) {
     p->compressed = 1;
     p->mcomp = 1;
@@ -747,13 +817,13 @@ sfft_status sfft_plan_create(sfft_plan* out, int d, const int64_t* n, int b, con
       p->mst[l] = p->mcomp;
       p->mcomp *= n[l] + 1;
     }
-    for (int ab = 0; ab < b * b; ++ab)
+    for (int k = 0; k < p->ns; ++k)
       for (int l = 0; l < d; ++l)
-        if (parity[ab * d + l] == SFFT_PARITY_ODD) p->odd_bits |= uint64_t(1) << (ab * 6 + l);
+        if (parity[p->comp_of[k] * d + l] == SFFT_PARITY_ODD) p->odd_bits |= uint64_t(1) << (k * 6 + l);
     p->sym_bs = 0;
-    p->sym_bytes = (size_t)(b * b * p->mcomp) * p->esz;
+    p->sym_bytes = (size_t)(p->ns * p->mcomp) * p->esz;
   } else {
-    p->sym_bs = (int64_t)npar * p->ntiles * b * b * lo->LE * lo->NTL;
+    p->sym_bs = (int64_t)npar * p->ntiles * p->ns * lo->LE * lo->NTL;
     const int64_t nbranch = method == SFFT_SPLIT ? (int64_t(1) << (d - 1)) : 1;
     p->sym_bytes = (size_t)(nbranch * p->sym_bs) * p->esz;
   }
@@ -807,6 +877,7 @@ sfft_status sfft_plan_info(sfft_plan plan, sfft_info* info) {
   info->method = plan->method;
   info->schedule = plan->sched;
   info->compressed = plan->compressed;
+  info->block_symmetry = plan->bsym;
   info->max_nrhs = plan->max_nrhs;
   info->symbol_bytes = plan->sym_bytes;
   info->table_bytes = plan->table_bytes;

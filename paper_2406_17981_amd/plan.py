@@ -88,7 +88,8 @@ class Plan:
         return dict(d=inf.d, n=tuple(inf.n[:inf.d]), b=inf.b, dtype=inf.dtype, method=inf.method,
                     schedule=inf.schedule, compressed=inf.compressed, max_nrhs=inf.max_nrhs,
                     symbol_bytes=inf.symbol_bytes, table_bytes=inf.table_bytes,
-                    workspace_bytes=inf.workspace_bytes, vector_elems=inf.vector_elems)
+                    workspace_bytes=inf.workspace_bytes, vector_elems=inf.vector_elems,
+                    block_symmetry=inf.block_symmetry)
 
     def workspace_size(self, nrhs: int) -> int:
         out = C.c_size_t()

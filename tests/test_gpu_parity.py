@@ -178,7 +178,9 @@ def test_mirrored_symbols_green(sf, grid, dtype):
         got = _run(sf, coeffs, x, dtype, "split", sched, parity=par, info=info)
         assert info["compressed"] == 1
         esz = 8 if dtype == "c64" else 16
-        assert info["symbol_bytes"] == 9 * math.prod(v + 1 for v in grid) * esz
+        # Green blocks are symmetric: 6 stored components of 9
+        assert info["block_symmetry"] == 1
+        assert info["symbol_bytes"] == 6 * math.prod(v + 1 for v in grid) * esz
         assert wl.relative_l2(got, want) <= TOL[dtype], sched
 
 
@@ -214,7 +216,7 @@ def test_green_64_mirrored_full_size(sf, green64, dtype):
     got = _run(sf, coeffs, x, dtype, "split", parity=wl.green_parity(3), info=info)
     err = wl.relative_l2(got, want)
     _say(f"green64 mirrored {dtype} rel_l2={err:.3e} symbol_bytes={info['symbol_bytes']}")
-    assert info["symbol_bytes"] == 9 * 65 ** 3 * (8 if dtype == "c64" else 16)
+    assert info["symbol_bytes"] == 6 * 65 ** 3 * (8 if dtype == "c64" else 16)
     assert err <= TOL[dtype]
 
 
@@ -314,3 +316,62 @@ def test_empty_batch_is_a_no_op(sf):
     assert wl.relative_l2(got, oracle.embed_matvec(coeffs, x)) <= TOL["c64"]
     assert N.lib.sfft_apply(plan.handle, None, None, -1, None, 0, None) != 0
     plan.close()
+
+
+# ---------------------------------------------------------------------------
+# Block symmetry of the coefficients (detected exactly at plan creation)
+# ---------------------------------------------------------------------------
+def _plan_info_and_product(sf, coeffs, x, dtype, parity=None):
+    info = {}
+    got = _run(sf, coeffs, x, dtype, "split", parity=parity, info=info)
+    return info, got
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_block_symmetry_detection_and_products(sf, dtype, monkeypatch):
+    grid = (6, 10, 12)
+    x = wl.vectors(51, grid, 3, 2)
+    green = wl.green_coeffs(grid, 0.8)
+    skew = wl.skew_coeffs(grid, 1.1)
+    iid = wl.iid_coeffs(52, grid, 3)
+    # symmetric except one offset of one pair: not symmetric
+    near = green.copy()
+    near[0, 1, 3, 4, 5] += 1e-9
+    # pair (0, 1) symmetric, pairs with 2 antisymmetric: neither pattern
+    mixed = iid.copy()
+    mixed[1, 0] = mixed[0, 1]
+    mixed[2, 0] = -mixed[0, 2]
+    mixed[2, 1] = -mixed[1, 2]
+    cases = [("iid", iid, 0, 9), ("green", green, 1, 6), ("skew", skew, 2, 6), ("near", near, 0, 9),
+             ("mixed", mixed, 0, 9)]
+    general = None  # symbol bytes with all 9 components stored (tiles padded as the leaf needs)
+    for name, coeffs, bs, ns in cases:
+        info, got = _plan_info_and_product(sf, coeffs, x, dtype)
+        general = general or info["symbol_bytes"]
+        assert info["block_symmetry"] == bs, name
+        assert info["symbol_bytes"] * 9 == general * ns, name
+        assert wl.relative_l2(got, oracle.embed_matvec(coeffs, x)) <= TOL[dtype], name
+    # the embedding baseline stores the same components
+    info_g, info_s = {}, {}
+    _run(sf, iid, x, dtype, "embed", info=info_g)
+    got = _run(sf, green, x, dtype, "embed", info=info_s)
+    assert info_s["block_symmetry"] == 1 and info_s["symbol_bytes"] * 9 == info_g["symbol_bytes"] * 6
+    assert wl.relative_l2(got, oracle.embed_matvec(green, x)) <= TOL[dtype]
+    # switching the detection off stores all 9 and gives the same product
+    monkeypatch.setenv("SFFT_NO_BLOCK_SYMMETRY", "1")
+    info, got_off = _plan_info_and_product(sf, green, x, dtype)
+    assert info["block_symmetry"] == 0 and info["symbol_bytes"] == general
+    monkeypatch.delenv("SFFT_NO_BLOCK_SYMMETRY")
+    _, got_on = _plan_info_and_product(sf, green, x, dtype)
+    assert wl.relative_l2(got_on, got_off) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_block_symmetry_with_mirrored_storage(sf, dtype):
+    grid = (8, 6, 10)
+    x = wl.vectors(53, grid, 3, 1)
+    for coeffs, par, bs in ((wl.green_coeffs(grid, 0.9), wl.green_parity(3), 1),
+                            (wl.skew_coeffs(grid, 1.2), wl.skew_parity(3), 2)):
+        info, got = _plan_info_and_product(sf, coeffs, x, dtype, parity=par)
+        assert info["compressed"] == 1 and info["block_symmetry"] == bs
+        assert wl.relative_l2(got, oracle.embed_matvec(coeffs, x)) <= TOL[dtype]
