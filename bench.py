@@ -129,7 +129,7 @@ def pmc_summarize(fetch_dir, write_dir, out_path):
         agg = per_kernel(load(d, counter))
         copy = [v for k, v in agg.items() if "copyBuffer" in k or "copy" in k.lower() and "sfft" not in k]
         copy_kib = max(copy[0]) if copy else None
-        leaf = [v for k, v in agg.items() if k.startswith("void sfft::k_leaf<float, 64, 3, 2, false>")]
+        leaf = [v for k, v in agg.items() if k.startswith("void sfft::k_leaf<float, 64, 3, 2, false, 1>")]
         leaf_kib = sorted(leaf[0])[len(leaf[0]) // 2] if leaf else None
         scale = COPY_PROBE_BYTES / (copy_kib * 1024.0) if copy_kib else None
         out[key] = dict(copy_kib=copy_kib, leaf_kib_median=leaf_kib, scale=scale,
@@ -137,7 +137,7 @@ def pmc_summarize(fetch_dir, write_dir, out_path):
     total = None
     if out["fetch"]["leaf_bytes"] is not None and out["write"]["leaf_bytes"] is not None:
         total = out["fetch"]["leaf_bytes"] + out["write"]["leaf_bytes"]
-    rec = dict(kernel="sfft::k_leaf<float, 64, 3, 2, false>", kernel_source_hash=kernel_source_hash(),
+    rec = dict(kernel="sfft::k_leaf<float, 64, 3, 2, false, 1>", kernel_source_hash=kernel_source_hash(),
                bytes_per_launch=total, detail=out,
                command="rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) -- python3 bench.py --pmc-probe")
     with open(out_path, "w") as f:
@@ -556,7 +556,7 @@ def main():
     nbr = 2 ** (d - 1)  # leaf launch: every branch prefix of levels 1..d-1
     leaf_alg_bytes = 2 * nbr * vbytes + info["symbol_bytes"]
     achieved = leaf_alg_bytes / leaf_avg_s / 1e9
-    leaf_kernel = "sfft::k_leaf<float, 64, 3, 2, false>"
+    leaf_kernel = f"sfft::k_leaf<float, 64, 3, 2, false, {info['block_symmetry']}>"
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(leaf_kernel),
                     kernel=leaf_kernel, avg_launch_us=round(leaf_avg_s * 1e6, 2),
