@@ -192,7 +192,7 @@ def bench_large(args):
             if leaf is not None and leaf[1] > 0:
                 # every launch of an apply together reads and writes each of the
                 # 2^(d-1) level-(d-1) branch vectors once and reads the stored symbols once
-                per_apply = leaf[1] / args.steps
+                per_apply = leaf[1] / len(range(0, args.steps, PROFILE_EVERY))
                 alg = (2 ** (len(n) - 1) * 2 * (vb // 2) + info["symbol_bytes"]) / per_apply
                 avg_s = leaf[0] / leaf[1] * 1e-3
                 out[f"{kname}_{label}"]["leaf"] = dict(
@@ -329,25 +329,33 @@ def bench_serve(args):
                       "budget_gb": args.budget_gb}), flush=True)
 
 
+PROFILE_EVERY = 10  # leaf launches bracketed by HIP events: every 10th apply of the timed region
+
+
 def time_plan(plan, x, y, ws, steps, warmup, profile_leaf=False):
+    """Mean wall time per apply (ms) over `steps` applies after `warmup`; with
+    profile_leaf, the leaf launches of every PROFILE_EVERY-th timed apply are
+    bracketed by HIP events on the apply stream (an event pair delays the
+    launches around it, so bracketing them all would slow the region it
+    measures), returning (total leaf ms, launches) as well."""
     import torch
     for _ in range(warmup):
         plan.apply(x, y, ws)
     torch.cuda.synchronize()
     if profile_leaf:
-        plan.profile(("leaf",))
         plan.profile_read("leaf", reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for i in range(steps):
+        sample = profile_leaf and i % PROFILE_EVERY == 0
+        if sample:
+            plan.profile(("leaf",))
         plan.apply(x, y, ws)
+        if sample:
+            plan.profile(())
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    leaf = None
-    if profile_leaf:
-        ms, cnt = plan.profile_read("leaf", reset=True)
-        plan.profile(())
-        leaf = (ms, cnt)
+    leaf = plan.profile_read("leaf", reset=True) if profile_leaf else None
     return (t1 - t0) * 1e3 / steps, leaf
 
 
