@@ -581,6 +581,14 @@ def main():
     copy_gbs = stream_copy_gbs()
     roofline["stream_copy_gbs"] = round(copy_gbs, 1)
     roofline["frac_of_stream_copy"] = round(achieved / copy_gbs, 4)
+    # the whole product: every level's pass moves its branch vectors once,
+    # (2^(d+2) - 6) V over the d-1 forward passes, the leaf and the d-1
+    # inverse passes, plus the stored symbols once
+    path_bytes = (2 ** (d + 2) - 6) * vbytes + info["symbol_bytes"]
+    path_gbs = path_bytes / (ms * 1e-3) / 1e9
+    roofline["whole_matvec"] = dict(bytes_per_matvec=int(path_bytes), achieved=round(path_gbs, 1),
+                                    frac=round(path_gbs / HBM_PEAK_GBS, 4),
+                                    frac_of_stream_copy=round(path_gbs / copy_gbs, 4))
 
     cpu = None
     rel = {}
