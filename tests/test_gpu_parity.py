@@ -56,6 +56,7 @@ SMALL = [
     # (grid, b) -- several tiles per pass and ragged last tiles
     ((24,), 1), ((40,), 3), ((10, 12), 1), ((16, 40), 3), ((6, 10, 12), 1), ((5, 12, 40), 3),
     ((8, 6, 10), 3), ((4, 3, 2, 5), 1), ((2, 3, 4, 2, 2), 1), ((16, 16, 16), 3),
+    ((2, 3, 2, 2, 4, 2), 1), ((2, 2, 3, 2, 2, 5), 3),  # d = 6, the most levels a plan takes
 ]
 
 
