@@ -451,8 +451,29 @@ __global__ void __launch_bounds__((Geo<Real, L>::RBMAX * Geo<Real, L>::SL)) k_le
     }
   }
 
+  // symbols requested ahead: parity 0, entries 0..3, before the forward
+  // transforms; parity 1, entries 0 and 1, before parity 0's product
+  constexpr int MSP = (E % 2 == 0) ? 2 : 1;
+  constexpr int NPF = (MSP == 2 && E >= 4) ? 2 : 1;
+  C2 pf[NPF][NS];
+  C2 pf1[NS];
+  auto sym_base = [&](int p) {
+    return (const C*)a.sym + q * a.sym_bs + ((int64_t)p * a.ntiles + tile) * (NS * E * SL);
+  };
+  if constexpr (!MIR && MSP == 2) {
+#pragma unroll
+    for (int j = 0; j < NPF; ++j)
+#pragma unroll
+      for (int k = 0; k < NS; ++k) pf[j][k] = *(const C2*)(sym_base(0) + sym_offset(k, 2 * j, slane, E, SL));
+  }
   // mulBrn for one child p: w[.][m] <- S_p[., .](m) w[.][m]
   auto block_product = [&](C (&w)[B][E], int p) {
+    if constexpr (!MIR && MSP == 2 && NPAR == 2) {  // the embedding baseline has one child
+      if (p == 0) {
+#pragma unroll
+        for (int k = 0; k < NS; ++k) pf1[k] = *(const C2*)(sym_base(1) + sym_offset(k, 0, slane, E, SL));
+      }
+    }
     const C* sp = (const C*)a.sym + q * a.sym_bs + ((int64_t)p * a.ntiles + tile) * (NS * E * SL);
     constexpr int MS = (E % 2 == 0) ? 2 : 1;  // entries per symbol load
 #pragma unroll
@@ -485,7 +506,8 @@ __global__ void __launch_bounds__((Geo<Real, L>::RBMAX * Geo<Real, L>::SL)) k_le
       for (int k = 0; k < NS; ++k) {
         if constexpr (MIR) {
         } else if constexpr (MS == 2) {
-          const C2 v = *(const C2*)(sp + sym_offset(k, m0, slane, E, SL));
+          const C2 v = (p == 0 && m0 < 2 * NPF) ? pf[m0 / 2][k]
+                       : (p == 1 && m0 == 0) ? pf1[k] : *(const C2*)(sp + sym_offset(k, m0, slane, E, SL));
           sm[0][k] = mk<C>(v.x, v.y);
           sm[1][k] = mk<C>(v.z, v.w);
         } else {
