@@ -466,6 +466,28 @@ __global__ void __launch_bounds__((Geo<Real, L>::RBMAX * Geo<Real, L>::SL)) k_le
 #pragma unroll
       for (int k = 0; k < NS; ++k) pf[j][k] = *(const C2*)(sym_base(0) + sym_offset(k, 2 * j, slane, E, SL));
   }
+  // mirrored storage: the stored entries of group (p, m0) of every component,
+  // with their sign flips (bit k of flip[j])
+  auto mir_group = [&](int p, int m0, C (&dst)[MSP][NS], uint32_t (&flip)[MSP]) {
+    uint32_t off[MSP];
+#pragma unroll
+    for (int j = 0; j < MSP; ++j) {
+      const int k = t + T * (m0 + j);
+      const bool mir = 2 * k + p > L;
+      off[j] = ((uint32_t)mbase + (uint32_t)(p * (L / 2 + 1) + (mir ? (p ? L - 1 - k : L - k) : k))) *
+               (uint32_t)sizeof(C);
+      flip[j] = osign ^ (mir ? lodd : 0u);
+    }
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      const char* base = (const char*)a.sym + k * a.mcomp * (int64_t)sizeof(C);
+#pragma unroll
+      for (int j = 0; j < MSP; ++j) dst[j][k] = *(const C*)(base + off[j]);
+    }
+  };
+  C mpf[MSP][NS];
+  uint32_t mpf_flip[MSP];
+  if constexpr (MIR) mir_group(0, 0, mpf, mpf_flip);
   // mulBrn for one child p: w[.][m] <- S_p[., .](m) w[.][m]
   auto block_product = [&](C (&w)[B][E], int p) {
     if constexpr (!MIR && MSP == 2 && NPAR == 2) {  // the embedding baseline has one child
@@ -480,27 +502,22 @@ __global__ void __launch_bounds__((Geo<Real, L>::RBMAX * Geo<Real, L>::SL)) k_le
     for (int m0 = 0; m0 < E; m0 += MS) {
       C sm[MS][NS];
       if constexpr (MIR) {
-        // stored index along the last level and the sign flips, shared by all
-        // block components
-        // 32-bit byte offsets from a lane-uniform base per component (plan
-        // creation keeps one stored component below 4 GiB)
-        uint32_t off[MS];
-        uint32_t flip[MS];
+        C raw[MSP][NS];
+        uint32_t flip[MSP];
+        if (p == 0 && m0 == 0) {
 #pragma unroll
-        for (int j = 0; j < MS; ++j) {
-          const int k = t + T * (m0 + j);
-          const bool mir = 2 * k + p > L;
-          off[j] = ((uint32_t)mbase + (uint32_t)(p * (L / 2 + 1) + (mir ? (p ? L - 1 - k : L - k) : k))) *
-                   (uint32_t)sizeof(C);
-          flip[j] = osign ^ (mir ? lodd : 0u);
+          for (int j = 0; j < MSP; ++j) {
+            flip[j] = mpf_flip[j];
+#pragma unroll
+            for (int k = 0; k < NS; ++k) raw[j][k] = mpf[j][k];
+          }
+        } else {
+          mir_group(p, m0, raw, flip);
         }
 #pragma unroll
-        for (int k = 0; k < NS; ++k) {
-          const char* base = (const char*)a.sym + k * a.mcomp * (int64_t)sizeof(C);
+        for (int k = 0; k < NS; ++k)
 #pragma unroll
-          for (int j = 0; j < MS; ++j)
-            sm[j][k] = cneg_if(*(const C*)(base + off[j]), (flip[j] >> k) & 1u);
-        }
+          for (int j = 0; j < MS; ++j) sm[j][k] = cneg_if(raw[j][k], (flip[j] >> k) & 1u);
       }
 #pragma unroll
       for (int k = 0; k < NS; ++k) {
