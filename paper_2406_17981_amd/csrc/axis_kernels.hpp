@@ -83,7 +83,21 @@ struct PassArgs {
   // filled by the launchers: block and column decoding without 64-bit division
   FastDiv fd_a, fd_b;  // strided: tiles per branch, inner; leaf: rhs groups, tile groups of 8
   int idx32;           // every decoded index fits in 32 bits
+  // XCD-contiguous block order of the strided and contiguous passes (set by
+  // their launchers): workgroups are dispatched round-robin over the 8 XCDs,
+  // so block b runs work item (b % 8) * (grid / 8) + b / 8 and each XCD
+  // sweeps one contiguous range of tiles; items >= nblk (the grid is rounded
+  // up to a multiple of 8) exit at once
+  int xcd;
+  uint32_t nblk;
 };
+
+// Work item of this workgroup under the launch's block order.
+__device__ __forceinline__ uint32_t work_item(const PassArgs& a) {
+  uint32_t bx = blockIdx.x;
+  if (a.xcd) bx = (bx & 7u) * (gridDim.x >> 3) + (bx >> 3);
+  return bx;
+}
 
 // Launch geometry per length.
 template <typename Real, int L> struct Geo {
@@ -161,18 +175,20 @@ __global__ void __launch_bounds__(256) k_strided(PassArgs a) {
   const int tid = threadIdx.x;
   const int c = tid % W, t = tid / W;
   const int64_t cols = a.outer * a.inner;
+  const uint32_t bx = work_item(a);
+  if (a.xcd && bx >= a.nblk) return;  // whole workgroup exits together
   int64_t q, col, o, i;
   if (a.idx32) {
-    const uint32_t bq = a.fd_a.div(blockIdx.x);
+    const uint32_t bq = a.fd_a.div(bx);
     q = bq;
-    col = (int64_t)(blockIdx.x - bq * a.fd_a.d) * W + c;
+    col = (int64_t)(bx - bq * a.fd_a.d) * W + c;
     const uint32_t oc = a.fd_b.div((uint32_t)col);
     o = oc;
     i = (uint32_t)col - oc * a.fd_b.d;
   } else {
     const int64_t ntile = (cols + W - 1) / W;
-    q = blockIdx.x / ntile;
-    col = (blockIdx.x % ntile) * W + c;
+    q = bx / ntile;
+    col = (bx % ntile) * W + c;
     o = col / a.inner;
     i = col - o * a.inner;
   }
@@ -231,7 +247,7 @@ __global__ void __launch_bounds__(256) k_strided(PassArgs a) {
     if (a.in1) {
       fft_pencil<+1, Sh>(w, lp, W, t, lt);
 #pragma unroll
-      for (int m = 0; m < E; ++m) h[m] = cadd(h[m], a.use_phase ? cmulc(w[m], ph[m]) : w[m]);
+      for (int m = 0; m < E; ++m) h[m] = a.use_phase ? cfmac(w[m], ph[m], h[m]) : cadd(h[m], w[m]);
     }
     if (act) {
       C* out = (C*)a.out + q * a.out_bs + base;
@@ -283,15 +299,17 @@ __global__ void __launch_bounds__(256) k_contig(PassArgs a) {
   __shared__ C lds[P * LP];
   const int tid = threadIdx.x;
   const int g = tid / T, t = tid % T;
+  const uint32_t bx = work_item(a);
+  if (a.xcd && bx >= a.nblk) return;  // whole workgroup exits together
   int64_t q, p0;
   if (a.idx32) {
-    const uint32_t bq = a.fd_a.div(blockIdx.x);
+    const uint32_t bq = a.fd_a.div(bx);
     q = bq;
-    p0 = (int64_t)(blockIdx.x - bq * a.fd_a.d) * P;
+    p0 = (int64_t)(bx - bq * a.fd_a.d) * P;
   } else {
     const int64_t ntile = (a.outer + P - 1) / P;
-    q = blockIdx.x / ntile;
-    p0 = (blockIdx.x % ntile) * P;
+    q = bx / ntile;
+    p0 = (bx % ntile) * P;
   }
   const int nh = (int)((a.outer - p0) < P ? (a.outer - p0) : P);
   const C* tw = (const C*)a.tw;
@@ -333,7 +351,7 @@ __global__ void __launch_bounds__(256) k_contig(PassArgs a) {
       __syncthreads();
       fft_pencil<+1, Sh, G::WS>(w, lp, 1, t, lt);
 #pragma unroll
-      for (int m = 0; m < E; ++m) h[m] = cadd(h[m], a.use_phase ? cmulc(w[m], ph[m]) : w[m]);
+      for (int m = 0; m < E; ++m) h[m] = a.use_phase ? cfmac(w[m], ph[m], h[m]) : cadd(h[m], w[m]);
     }
     store_home<C, L, T, E, P, NT>((C*)a.out + q * a.out_bs + p0 * L, lds, h, g, t, nh, tid);
   }
@@ -536,11 +554,13 @@ __global__ void __launch_bounds__((Geo<Real, L>::RBMAX * Geo<Real, L>::SL)) k_le
         C o[B];
 #pragma unroll
         for (int ar = 0; ar < B; ++ar) {
-          C u = czero<C>();
+          // first term a product, the others fused multiply-adds
+          C u = cmul(sm[j][BSy::idx(ar, 0)], w[0][m0 + j]);
+          if (BSy::neg(ar, 0)) u = mk<C>(-u.x, -u.y);
 #pragma unroll
-          for (int c = 0; c < B; ++c) {
-            const C v = cmul(sm[j][BSy::idx(ar, c)], w[c][m0 + j]);
-            u = BSy::neg(ar, c) ? csub(u, v) : cadd(u, v);
+          for (int c = 1; c < B; ++c) {
+            const C sv = sm[j][BSy::idx(ar, c)];
+            u = BSy::neg(ar, c) ? cfms(sv, w[c][m0 + j], u) : cfma(sv, w[c][m0 + j], u);
           }
           o[ar] = u;
         }
@@ -593,7 +613,7 @@ __global__ void __launch_bounds__((Geo<Real, L>::RBMAX * Geo<Real, L>::SL)) k_le
 #pragma unroll
     for (int c = 0; c < B; ++c)
 #pragma unroll
-      for (int m = 0; m < E; ++m) x[c][m] = cadd(h[c][m], cmulc(h[B + c][m], phase(m)));
+      for (int m = 0; m < E; ++m) x[c][m] = cfmac(h[B + c][m], phase(m), h[c][m]);
   } else {
 #pragma unroll
     for (int c = 0; c < B; ++c)
@@ -639,7 +659,10 @@ template <typename Real, int L, int MODE> hipError_t launch_strided(const PassAr
     b.fd_a = FastDiv::make((uint32_t)ntile);
     b.fd_b = FastDiv::make((uint32_t)a.inner);
   }
-  hipLaunchKernelGGL((k_strided<Real, L, MODE>), dim3((unsigned)blocks), dim3(G::NT), 0, s, b);
+  b.xcd = blocks < kIdx32;
+  b.nblk = (uint32_t)blocks;
+  const int64_t grid = b.xcd ? (blocks + 7) / 8 * 8 : blocks;
+  hipLaunchKernelGGL((k_strided<Real, L, MODE>), dim3((unsigned)grid), dim3(G::NT), 0, s, b);
   return hipGetLastError();
 }
 
@@ -651,7 +674,10 @@ template <typename Real, int L, int MODE> hipError_t launch_contig(const PassArg
   PassArgs b = a;
   b.idx32 = blocks < kIdx32;
   if (b.idx32) b.fd_a = FastDiv::make((uint32_t)ntile);
-  hipLaunchKernelGGL((k_contig<Real, L, MODE>), dim3((unsigned)blocks), dim3(G::NT), 0, s, b);
+  b.xcd = blocks < kIdx32;
+  b.nblk = (uint32_t)blocks;
+  const int64_t grid = b.xcd ? (blocks + 7) / 8 * 8 : blocks;
+  hipLaunchKernelGGL((k_contig<Real, L, MODE>), dim3((unsigned)grid), dim3(G::NT), 0, s, b);
   return hipGetLastError();
 }
 
@@ -668,6 +694,7 @@ hipError_t launch_leaf(const PassArgs& a, hipStream_t s) {
   const int64_t blocks = a.nq * ((a.ntiles + 7) / 8) * nrg * 8;
   if (blocks <= 0) return hipSuccess;
   b.idx32 = blocks < kIdx32;
+  b.xcd = 0;
   if (b.idx32) {
     b.fd_a = FastDiv::make((uint32_t)nrg);
     b.fd_b = FastDiv::make((uint32_t)((a.ntiles + 7) / 8));

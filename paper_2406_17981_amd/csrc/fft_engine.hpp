@@ -40,6 +40,19 @@ template <typename C> __device__ __forceinline__ C cmulc(C a, C b) {
   return mk<C>(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
 }
 template <typename C> __device__ __forceinline__ C cscale(C a, decltype(C::x) s) { return mk<C>(a.x * s, a.y * s); }
+// fused multiply-add, one rounding
+__device__ __forceinline__ float fmar(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmar(double a, double b, double c) { return __builtin_fma(a, b, c); }
+// u + a * b, u - a * b and u + a * conj(b) as four fused multiply-adds each
+template <typename C> __device__ __forceinline__ C cfma(C a, C b, C u) {
+  return mk<C>(fmar(-a.y, b.y, fmar(a.x, b.x, u.x)), fmar(a.y, b.x, fmar(a.x, b.y, u.y)));
+}
+template <typename C> __device__ __forceinline__ C cfms(C a, C b, C u) {
+  return mk<C>(fmar(a.y, b.y, fmar(-a.x, b.x, u.x)), fmar(-a.y, b.x, fmar(-a.x, b.y, u.y)));
+}
+template <typename C> __device__ __forceinline__ C cfmac(C a, C b, C u) {
+  return mk<C>(fmar(a.y, b.y, fmar(a.x, b.x, u.x)), fmar(-a.x, b.y, fmar(a.y, b.x, u.y)));
+}
 template <typename C> __device__ __forceinline__ C czero() { return mk<C>(0, 0); }
 // -a when s is 1, a when s is 0 (sign bits flipped, no compare or select)
 __device__ __forceinline__ float2 cneg_if(float2 a, uint32_t s) {
@@ -162,6 +175,87 @@ template <int DIR, typename C> __device__ __forceinline__ void dft16(C* v) {
     dft4<DIR>(z);
 #pragma unroll
     for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = z[k2];
+  }
+}
+
+// Radix-4 DFT whose first layer is done: a0, a1 = e0 +- e2 and b0, b1 =
+// e1 +- e3 of the inputs e0..e3.
+template <int DIR, typename C> __device__ __forceinline__ void dft4_tail(C* v, C a0, C a1, C b0, C b1) {
+  const C t3 = mul_di<DIR>(b1);
+  v[0] = cadd(a0, b0);
+  v[2] = csub(a0, b0);
+  v[1] = cadd(a1, t3);
+  v[3] = csub(a1, t3);
+}
+
+// Twiddled butterfly of a stage after the first: entries r >= 1 are scaled by
+// w[r-1] (conjugated for the inverse) and the radix-R DFT follows. For R = 2,
+// 4, 8, 16 the DFT's first layer pairs entries r and r + R/2; each pair is
+// formed as y0 = a + w b with fused multiply-adds and y1 = 2a - y0, so the
+// product w b of the pair's upper entry is never rounded on its own (the
+// multiply-add butterfly of Linzer and Feig).
+template <int R, int DIR, typename C> __device__ __forceinline__ void tw_dft(C* v, const C* w) {
+  using Rl = decltype(C::x);
+  constexpr int H = R / 2;
+  C y0[H], y1[H];
+#pragma unroll
+  for (int r = 0; r < H; ++r) {
+    C a = v[r];
+    if (r > 0) a = (DIR > 0) ? cmulc(a, w[r - 1]) : cmul(a, w[r - 1]);
+    const C b = v[r + H];
+    const C s = (DIR > 0) ? cfmac(b, w[r + H - 1], a) : cfma(b, w[r + H - 1], a);
+    y0[r] = s;
+    y1[r] = mk<C>(fmar((Rl)2, a.x, -s.x), fmar((Rl)2, a.y, -s.y));
+  }
+  if constexpr (R == 2) {
+    v[0] = y0[0];
+    v[1] = y1[0];
+  } else if constexpr (R == 4) {
+    dft4_tail<DIR>(v, y0[0], y1[0], y0[1], y1[1]);
+  } else if constexpr (R == 8) {
+    // as dft8: e = DFT4 of the even entries, o = DFT4 of the odd ones
+    const Rl h = (Rl)0.70710678118654752440084436210485;  // sqrt(1/2)
+    C e[4], o[4];
+    dft4_tail<DIR>(e, y0[0], y1[0], y0[2], y1[2]);
+    dft4_tail<DIR>(o, y0[1], y1[1], y0[3], y1[3]);
+    o[1] = cscale(cadd(o[1], mul_di<DIR>(o[1])), h);
+    o[2] = mul_di<DIR>(o[2]);
+    o[3] = cscale(csub(mul_di<DIR>(o[3]), o[3]), h);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      v[k] = cadd(e[k], o[k]);
+      v[k + 4] = csub(e[k], o[k]);
+    }
+  } else {
+    static_assert(R == 16, "twiddled butterfly for radix 2, 4, 8, 16");
+    // as dft16: n = 4 n1 + n2; the DFT4 over n1 of group n2 pairs entries
+    // n2, n2 + 8 and n2 + 4, n2 + 12
+    const Rl h = (Rl)0.70710678118654752440084436210485;
+    const Rl c8 = (Rl)0.92387953251128675612818318939679;
+    const Rl s8 = (Rl)0.38268343236508977172845998403040;
+    C y[4][4];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) dft4_tail<DIR>(y[n2], y0[n2], y1[n2], y0[n2 + 4], y1[n2 + 4]);
+    const Rl D = (Rl)DIR;
+    const C w1 = mk<C>(c8, D * s8);
+    const C w2 = mk<C>(h, D * h);
+    const C w3 = mk<C>(s8, D * c8);
+    y[1][1] = cmul(y[1][1], w1);
+    y[1][2] = cmul(y[1][2], w2);
+    y[1][3] = cmul(y[1][3], w3);
+    y[2][1] = cmul(y[2][1], w2);
+    y[2][2] = mul_di<DIR>(y[2][2]);
+    y[2][3] = cmul(y[2][3], mk<C>(-h, D * h));
+    y[3][1] = cmul(y[3][1], w3);
+    y[3][2] = cmul(y[3][2], mk<C>(-h, D * h));
+    y[3][3] = cmul(y[3][3], mk<C>(-c8, -D * s8));
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+      C z[4] = {y[0][k1], y[1][k1], y[2][k1], y[3][k1]};
+      dft4<DIR>(z);
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = z[k2];
+    }
   }
 }
 
@@ -331,14 +425,21 @@ __device__ __forceinline__ void fft_stage(C (&home)[Sh::E], C* lds, int kst, int
         if constexpr (FIRST_REG) v[u][r] = home[u + r * (NB / T)];
         else v[u][r] = lds[(j + r * NB) * kst];
       }
-      if constexpr (s > 0) {
+      if constexpr (s > 0 && (R == 2 || R == 4 || R == 8 || R == 16)) {
+        C w[R - 1];
 #pragma unroll
-        for (int r = 1; r < R; ++r) {
-          const C w = lt.w[LaneTw<C, Sh>::off(s) + u * (R - 1) + r - 1];
-          v[u][r] = (DIR > 0) ? cmulc(v[u][r], w) : cmul(v[u][r], w);
+        for (int r = 1; r < R; ++r) w[r - 1] = lt.w[LaneTw<C, Sh>::off(s) + u * (R - 1) + r - 1];
+        tw_dft<R, DIR>(v[u], w);
+      } else {
+        if constexpr (s > 0) {
+#pragma unroll
+          for (int r = 1; r < R; ++r) {
+            const C w = lt.w[LaneTw<C, Sh>::off(s) + u * (R - 1) + r - 1];
+            v[u][r] = (DIR > 0) ? cmulc(v[u][r], w) : cmul(v[u][r], w);
+          }
         }
+        dft<R, DIR>(v[u]);
       }
-      dft<R, DIR>(v[u]);
     }
   }
 
@@ -414,14 +515,21 @@ __device__ __forceinline__ void fft_stage_multi(C (&home)[NP][Sh::E], C* lds, in
           if constexpr (FIRST_REG) v[p][u][r] = home[p][u + r * (NB / T)];
           else v[p][u][r] = lds[p * pstride + (j + r * NB) * kst];
         }
-        if constexpr (s > 0) {
+        if constexpr (s > 0 && (R == 2 || R == 4 || R == 8 || R == 16)) {
+          C w[R - 1];
 #pragma unroll
-          for (int r = 1; r < R; ++r) {
-            const C w = lt.w[LaneTw<C, Sh>::off(s) + u * (R - 1) + r - 1];
-            v[p][u][r] = (DIR > 0) ? cmulc(v[p][u][r], w) : cmul(v[p][u][r], w);
+          for (int r = 1; r < R; ++r) w[r - 1] = lt.w[LaneTw<C, Sh>::off(s) + u * (R - 1) + r - 1];
+          tw_dft<R, DIR>(v[p][u], w);
+        } else {
+          if constexpr (s > 0) {
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+              const C w = lt.w[LaneTw<C, Sh>::off(s) + u * (R - 1) + r - 1];
+              v[p][u][r] = (DIR > 0) ? cmulc(v[p][u][r], w) : cmul(v[p][u][r], w);
+            }
           }
+          dft<R, DIR>(v[p][u]);
         }
-        dft<R, DIR>(v[p][u]);
       }
     }
 
