@@ -83,20 +83,32 @@ struct PassArgs {
   // filled by the launchers: block and column decoding without 64-bit division
   FastDiv fd_a, fd_b;  // strided: tiles per branch, inner; leaf: rhs groups, tile groups of 8
   int idx32;           // every decoded index fits in 32 bits
-  // XCD-contiguous block order of the strided and contiguous passes (set by
-  // their launchers): workgroups are dispatched round-robin over the 8 XCDs,
-  // so block b runs work item (b % 8) * (grid / 8) + b / 8 and each XCD
-  // sweeps one contiguous range of tiles; items >= nblk (the grid is rounded
-  // up to a multiple of 8) exit at once
-  int xcd;
-  uint32_t nblk;
+  // block order of the strided and contiguous passes (set by their
+  // launchers): workgroup b runs work item (b % 8) * xm1 + (b / 8) * xm2.
+  // (1, 8) keeps the dispatch order; (grid / 8, 1) gives each XCD one
+  // contiguous range of tiles, since workgroups are dispatched round-robin
+  // over the 8 XCDs. Items >= nblk (the grid rounded up to a multiple of 8)
+  // store nothing. Branch-free, so the work item needs no second round of
+  // argument loads.
+  uint32_t xm1, xm2, nblk;
 };
 
-// Work item of this workgroup under the launch's block order.
 __device__ __forceinline__ uint32_t work_item(const PassArgs& a) {
-  uint32_t bx = blockIdx.x;
-  if (a.xcd) bx = (bx & 7u) * (gridDim.x >> 3) + (bx >> 3);
-  return bx;
+  return (blockIdx.x & 7u) * a.xm1 + (blockIdx.x >> 3) * a.xm2;
+}
+
+// Fills the block order fields for a pass of `blocks` workgroups; returns the grid.
+inline int64_t set_block_order(PassArgs& b, int64_t blocks, bool xcd) {
+  b.nblk = (uint32_t)blocks;
+  if (xcd) {
+    const int64_t grid = (blocks + 7) / 8 * 8;
+    b.xm1 = (uint32_t)(grid / 8);
+    b.xm2 = 1;
+    return grid;
+  }
+  b.xm1 = 1;
+  b.xm2 = 8;
+  return blocks;
 }
 
 // Launch geometry per length.
@@ -132,6 +144,11 @@ template <typename Real, int L> struct Geo {
   // single exchange the pencils go one after another through one row, which
   // keeps LDS per workgroup (and so occupancy) low
   template <int B, int NPAR> static constexpr int leaf_rows() { return LSh::S >= 3 ? NPAR * B : 1; }
+  // Leaves of length 128 and more run many wavefronts per SIMD and are bound
+  // by instruction throughput: they use the multiply-add butterflies, block
+  // product and merge (fewer VALU instructions, longer dependence chains);
+  // shorter leaves, bound by latency, keep independent products and adds
+  static constexpr bool LFMA = L >= 128;
 };
 
 // Stored block components. BS = 0: all B*B components, index a*B + c.
@@ -175,8 +192,11 @@ __global__ void __launch_bounds__(256) k_strided(PassArgs a) {
   const int tid = threadIdx.x;
   const int c = tid % W, t = tid / W;
   const int64_t cols = a.outer * a.inner;
-  const uint32_t bx = work_item(a);
-  if (a.xcd && bx >= a.nblk) return;  // whole workgroup exits together
+  // an item past the end (grid rounded up to 8) works on tile 0 and stores
+  // nothing; no early exit, which would hold back the other argument loads
+  const uint32_t wi = work_item(a);
+  const bool live = wi < a.nblk;
+  const uint32_t bx = live ? wi : 0u;
   int64_t q, col, o, i;
   if (a.idx32) {
     const uint32_t bq = a.fd_a.div(bx);
@@ -192,7 +212,7 @@ __global__ void __launch_bounds__(256) k_strided(PassArgs a) {
     o = col / a.inner;
     i = col - o * a.inner;
   }
-  const bool act = col < cols;
+  const bool act = live && col < cols;
   if (!act) o = i = 0;
   const int64_t base = o * L * a.inner + i;
   const int64_t st = a.inner;
@@ -247,7 +267,7 @@ __global__ void __launch_bounds__(256) k_strided(PassArgs a) {
     if (a.in1) {
       fft_pencil<+1, Sh>(w, lp, W, t, lt);
 #pragma unroll
-      for (int m = 0; m < E; ++m) h[m] = a.use_phase ? cfmac(w[m], ph[m], h[m]) : cadd(h[m], w[m]);
+      for (int m = 0; m < E; ++m) h[m] = cadd(h[m], a.use_phase ? cmulc(w[m], ph[m]) : w[m]);
     }
     if (act) {
       C* out = (C*)a.out + q * a.out_bs + base;
@@ -299,8 +319,9 @@ __global__ void __launch_bounds__(256) k_contig(PassArgs a) {
   __shared__ C lds[P * LP];
   const int tid = threadIdx.x;
   const int g = tid / T, t = tid % T;
-  const uint32_t bx = work_item(a);
-  if (a.xcd && bx >= a.nblk) return;  // whole workgroup exits together
+  const uint32_t wi = work_item(a);
+  const bool live = wi < a.nblk;  // past the end: tile 0, nothing loaded or stored
+  const uint32_t bx = live ? wi : 0u;
   int64_t q, p0;
   if (a.idx32) {
     const uint32_t bq = a.fd_a.div(bx);
@@ -311,7 +332,7 @@ __global__ void __launch_bounds__(256) k_contig(PassArgs a) {
     q = bx / ntile;
     p0 = (bx % ntile) * P;
   }
-  const int nh = (int)((a.outer - p0) < P ? (a.outer - p0) : P);
+  const int nh = live ? (int)((a.outer - p0) < P ? (a.outer - p0) : P) : 0;
   const C* tw = (const C*)a.tw;
   C* lp = lds + g * LP;
   LaneTw<C, Sh> lt;
@@ -351,7 +372,7 @@ __global__ void __launch_bounds__(256) k_contig(PassArgs a) {
       __syncthreads();
       fft_pencil<+1, Sh, G::WS>(w, lp, 1, t, lt);
 #pragma unroll
-      for (int m = 0; m < E; ++m) h[m] = a.use_phase ? cfmac(w[m], ph[m], h[m]) : cadd(h[m], w[m]);
+      for (int m = 0; m < E; ++m) h[m] = cadd(h[m], a.use_phase ? cmulc(w[m], ph[m]) : w[m]);
     }
     store_home<C, L, T, E, P, NT>((C*)a.out + q * a.out_bs + p0 * L, lds, h, g, t, nh, tid);
   }
@@ -554,13 +575,23 @@ __global__ void __launch_bounds__((Geo<Real, L>::RBMAX * Geo<Real, L>::SL)) k_le
         C o[B];
 #pragma unroll
         for (int ar = 0; ar < B; ++ar) {
-          // first term a product, the others fused multiply-adds
-          C u = cmul(sm[j][BSy::idx(ar, 0)], w[0][m0 + j]);
-          if (BSy::neg(ar, 0)) u = mk<C>(-u.x, -u.y);
+          C u;
+          if constexpr (G::LFMA) {
+            // first term a product, the others fused multiply-adds
+            u = cmul(sm[j][BSy::idx(ar, 0)], w[0][m0 + j]);
+            if (BSy::neg(ar, 0)) u = mk<C>(-u.x, -u.y);
 #pragma unroll
-          for (int c = 1; c < B; ++c) {
-            const C sv = sm[j][BSy::idx(ar, c)];
-            u = BSy::neg(ar, c) ? cfms(sv, w[c][m0 + j], u) : cfma(sv, w[c][m0 + j], u);
+            for (int c = 1; c < B; ++c) {
+              const C sv = sm[j][BSy::idx(ar, c)];
+              u = BSy::neg(ar, c) ? cfms(sv, w[c][m0 + j], u) : cfma(sv, w[c][m0 + j], u);
+            }
+          } else {
+            u = czero<C>();
+#pragma unroll
+            for (int c = 0; c < B; ++c) {
+              const C v = cmul(sm[j][BSy::idx(ar, c)], w[c][m0 + j]);
+              u = BSy::neg(ar, c) ? csub(u, v) : cadd(u, v);
+            }
           }
           o[ar] = u;
         }
@@ -595,25 +626,26 @@ __global__ void __launch_bounds__((Geo<Real, L>::RBMAX * Geo<Real, L>::SL)) k_le
       for (int m = 0; m < E; ++m) h[c][m] = x[c][m];
   }
   if constexpr (NROW == NP) {
-    fft_pencils<-1, Sh, G::LWS, NP>(h, lp, LP, 1, t, lt);
+    fft_pencils<-1, Sh, G::LWS, NP, G::LFMA>(h, lp, LP, 1, t, lt);
   } else {
 #pragma unroll
-    for (int c = 0; c < NP; ++c) fft_pencil<-1, Sh, G::LWS>(h[c], lp, 1, t, lt);
+    for (int c = 0; c < NP; ++c) fft_pencil<-1, Sh, G::LWS, G::LFMA>(h[c], lp, 1, t, lt);
   }
   block_product(*reinterpret_cast<C(*)[B][E]>(&h[0]), 0);
   if constexpr (NPAR == 2) block_product(*reinterpret_cast<C(*)[B][E]>(&h[B]), 1);
   if constexpr (NROW == NP) {
-    fft_pencils<+1, Sh, G::LWS, NP>(h, lp, LP, 1, t, lt);
+    fft_pencils<+1, Sh, G::LWS, NP, G::LFMA>(h, lp, LP, 1, t, lt);
   } else {
 #pragma unroll
-    for (int c = 0; c < NP; ++c) fft_pencil<+1, Sh, G::LWS>(h[c], lp, 1, t, lt);
+    for (int c = 0; c < NP; ++c) fft_pencil<+1, Sh, G::LWS, G::LFMA>(h[c], lp, 1, t, lt);
   }
   if constexpr (NPAR == 2) {
     // merge: even + conj(Phi) odd
 #pragma unroll
     for (int c = 0; c < B; ++c)
 #pragma unroll
-      for (int m = 0; m < E; ++m) x[c][m] = cfmac(h[B + c][m], phase(m), h[c][m]);
+      for (int m = 0; m < E; ++m)
+        x[c][m] = G::LFMA ? cfmac(h[B + c][m], phase(m), h[c][m]) : cadd(h[c][m], cmulc(h[B + c][m], phase(m)));
   } else {
 #pragma unroll
     for (int c = 0; c < B; ++c)
@@ -646,6 +678,9 @@ struct AxisOps {
 };
 
 constexpr int64_t kIdx32 = (int64_t)1 << 31;
+// passes of at least this many workgroups (many per CU) use the
+// XCD-contiguous block order; it helped the large grids only
+constexpr int64_t kXcdOrderFrom = 8192;
 
 template <typename Real, int L, int MODE> hipError_t launch_strided(const PassArgs& a, hipStream_t s) {
   using G = Geo<Real, L>;
@@ -653,15 +688,14 @@ template <typename Real, int L, int MODE> hipError_t launch_strided(const PassAr
   const int64_t ntile = (cols + G::W - 1) / G::W;
   const int64_t blocks = a.nq * ntile;
   if (blocks <= 0) return hipSuccess;
+  if (blocks >= kIdx32) return hipErrorInvalidConfiguration;  // beyond the 1-D grid
   PassArgs b = a;
   b.idx32 = blocks < kIdx32 && ntile * G::W < kIdx32;
   if (b.idx32) {
     b.fd_a = FastDiv::make((uint32_t)ntile);
     b.fd_b = FastDiv::make((uint32_t)a.inner);
   }
-  b.xcd = blocks < kIdx32;
-  b.nblk = (uint32_t)blocks;
-  const int64_t grid = b.xcd ? (blocks + 7) / 8 * 8 : blocks;
+  const int64_t grid = set_block_order(b, blocks, blocks >= kXcdOrderFrom);
   hipLaunchKernelGGL((k_strided<Real, L, MODE>), dim3((unsigned)grid), dim3(G::NT), 0, s, b);
   return hipGetLastError();
 }
@@ -671,12 +705,11 @@ template <typename Real, int L, int MODE> hipError_t launch_contig(const PassArg
   const int64_t ntile = (a.outer + G::P - 1) / G::P;
   const int64_t blocks = a.nq * ntile;
   if (blocks <= 0) return hipSuccess;
+  if (blocks >= kIdx32) return hipErrorInvalidConfiguration;  // beyond the 1-D grid
   PassArgs b = a;
   b.idx32 = blocks < kIdx32;
   if (b.idx32) b.fd_a = FastDiv::make((uint32_t)ntile);
-  b.xcd = blocks < kIdx32;
-  b.nblk = (uint32_t)blocks;
-  const int64_t grid = b.xcd ? (blocks + 7) / 8 * 8 : blocks;
+  const int64_t grid = set_block_order(b, blocks, blocks >= kXcdOrderFrom);
   hipLaunchKernelGGL((k_contig<Real, L, MODE>), dim3((unsigned)grid), dim3(G::NT), 0, s, b);
   return hipGetLastError();
 }
@@ -694,7 +727,6 @@ hipError_t launch_leaf(const PassArgs& a, hipStream_t s) {
   const int64_t blocks = a.nq * ((a.ntiles + 7) / 8) * nrg * 8;
   if (blocks <= 0) return hipSuccess;
   b.idx32 = blocks < kIdx32;
-  b.xcd = 0;
   if (b.idx32) {
     b.fd_a = FastDiv::make((uint32_t)nrg);
     b.fd_b = FastDiv::make((uint32_t)((a.ntiles + 7) / 8));

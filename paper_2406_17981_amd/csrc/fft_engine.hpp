@@ -193,7 +193,9 @@ template <int DIR, typename C> __device__ __forceinline__ void dft4_tail(C* v, C
 // 4, 8, 16 the DFT's first layer pairs entries r and r + R/2; each pair is
 // formed as y0 = a + w b with fused multiply-adds and y1 = 2a - y0, so the
 // product w b of the pair's upper entry is never rounded on its own (the
-// multiply-add butterfly of Linzer and Feig).
+// multiply-add butterfly of Linzer and Feig). It issues fewer instructions
+// but chains more of them, so it pays in kernels with enough wavefronts to
+// hide VALU latency and is selected per kernel (template flag FMA).
 template <int R, int DIR, typename C> __device__ __forceinline__ void tw_dft(C* v, const C* w) {
   using Rl = decltype(C::x);
   constexpr int H = R / 2;
@@ -398,7 +400,7 @@ template <typename C, typename Sh> struct LaneTw {
 // One stage (and, recursively, the following ones) of a pencil transform.
 // lds: this pencil's LDS row, element k at lds[k * kst]. All lanes of the
 // workgroup (WS = false) or of the wavefront (WS = true) call this together.
-template <typename C, typename Sh, int DIR, int s, bool WS>
+template <typename C, typename Sh, int DIR, int s, bool WS, bool FMA>
 __device__ __forceinline__ void fft_stage(C (&home)[Sh::E], C* lds, int kst, int t, const LaneTw<C, Sh>& lt) {
   constexpr int L = Sh::L, T = Sh::T, S = Sh::S;
   constexpr int R = Sh::rad(s);
@@ -425,7 +427,7 @@ __device__ __forceinline__ void fft_stage(C (&home)[Sh::E], C* lds, int kst, int
         if constexpr (FIRST_REG) v[u][r] = home[u + r * (NB / T)];
         else v[u][r] = lds[(j + r * NB) * kst];
       }
-      if constexpr (s > 0 && (R == 2 || R == 4 || R == 8 || R == 16)) {
+      if constexpr (FMA && s > 0 && (R == 2 || R == 4 || R == 8 || R == 16)) {
         C w[R - 1];
 #pragma unroll
         for (int r = 1; r < R; ++r) w[r - 1] = lt.w[LaneTw<C, Sh>::off(s) + u * (R - 1) + r - 1];
@@ -468,22 +470,22 @@ __device__ __forceinline__ void fft_stage(C (&home)[Sh::E], C* lds, int kst, int
       xsync<WS>();
     }
   }
-  if constexpr (s + 1 < S) fft_stage<C, Sh, DIR, s + 1, WS>(home, lds, kst, t, lt);
+  if constexpr (s + 1 < S) fft_stage<C, Sh, DIR, s + 1, WS, FMA>(home, lds, kst, t, lt);
 }
 
 // Unnormalised DFT of one pencil (DIR = -1 forward, +1 inverse).
-template <int DIR, typename Sh, bool WS = false, typename C>
+template <int DIR, typename Sh, bool WS = false, bool FMA = false, typename C>
 __device__ __forceinline__ void fft_pencil(C (&home)[Sh::E], C* lds, int kst, int t, const LaneTw<C, Sh>& lt) {
   static_assert(shape_ok<Sh>(), "bad radix plan");
   static_assert(!WS || (64 % Sh::T) == 0, "wave sync needs whole pencils per wavefront");
-  fft_stage<C, Sh, DIR, 0, WS>(home, lds, kst, t, lt);
+  fft_stage<C, Sh, DIR, 0, WS, FMA>(home, lds, kst, t, lt);
 }
 
 // NP pencils of one lane advanced stage by stage together: pencil p's LDS row
 // is lds + p * pstride. Every exchange fences once for all NP pencils, and the
 // NP independent butterfly chains give the scheduler work to overlap with
 // LDS and memory latency.
-template <typename C, typename Sh, int DIR, int s, bool WS, int NP>
+template <typename C, typename Sh, int DIR, int s, bool WS, int NP, bool FMA>
 __device__ __forceinline__ void fft_stage_multi(C (&home)[NP][Sh::E], C* lds, int pstride, int kst, int t,
                                                 const LaneTw<C, Sh>& lt) {
   constexpr int L = Sh::L, T = Sh::T, S = Sh::S;
@@ -515,7 +517,7 @@ __device__ __forceinline__ void fft_stage_multi(C (&home)[NP][Sh::E], C* lds, in
           if constexpr (FIRST_REG) v[p][u][r] = home[p][u + r * (NB / T)];
           else v[p][u][r] = lds[p * pstride + (j + r * NB) * kst];
         }
-        if constexpr (s > 0 && (R == 2 || R == 4 || R == 8 || R == 16)) {
+        if constexpr (FMA && s > 0 && (R == 2 || R == 4 || R == 8 || R == 16)) {
           C w[R - 1];
 #pragma unroll
           for (int r = 1; r < R; ++r) w[r - 1] = lt.w[LaneTw<C, Sh>::off(s) + u * (R - 1) + r - 1];
@@ -564,16 +566,16 @@ __device__ __forceinline__ void fft_stage_multi(C (&home)[NP][Sh::E], C* lds, in
       xsync<WS>();
     }
   }
-  if constexpr (s + 1 < S) fft_stage_multi<C, Sh, DIR, s + 1, WS, NP>(home, lds, pstride, kst, t, lt);
+  if constexpr (s + 1 < S) fft_stage_multi<C, Sh, DIR, s + 1, WS, NP, FMA>(home, lds, pstride, kst, t, lt);
 }
 
 // Unnormalised DFTs of NP pencils of the same lane (DIR = -1 forward, +1 inverse).
-template <int DIR, typename Sh, bool WS, int NP, typename C>
+template <int DIR, typename Sh, bool WS, int NP, bool FMA = false, typename C>
 __device__ __forceinline__ void fft_pencils(C (&home)[NP][Sh::E], C* lds, int pstride, int kst, int t,
                                             const LaneTw<C, Sh>& lt) {
   static_assert(shape_ok<Sh>(), "bad radix plan");
   static_assert(!WS || (64 % Sh::T) == 0, "wave sync needs whole pencils per wavefront");
-  fft_stage_multi<C, Sh, DIR, 0, WS, NP>(home, lds, pstride, kst, t, lt);
+  fft_stage_multi<C, Sh, DIR, 0, WS, NP, FMA>(home, lds, pstride, kst, t, lt);
 }
 
 }  // namespace sfft
