@@ -62,17 +62,20 @@ def measured_traffic(kernel: str):
 
 
 def stream_copy_gbs(nbytes=1 << 30, reps=20):
-    """Device-to-device copy bandwidth (read + write bytes per second) of a plain
-    copy of nbytes: the practical HBM ceiling on this machine."""
+    """Device-to-device copy bandwidth (read + write bytes per second) of a
+    streaming copy of nbytes: the practical HBM ceiling on this machine. The copy
+    is torch's elementwise kernel (b = a + 0), one short contiguous run per
+    thread over the whole grid, which moves about a quarter more than
+    Tensor.copy_'s blit kernel (hipMemcpy)."""
     import torch
     a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
     b = torch.empty_like(a)
     for _ in range(3):
-        b.copy_(a)
+        torch.add(a, 0.0, out=b)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
-        b.copy_(a)
+        torch.add(a, 0.0, out=b)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / reps
     del a, b
