@@ -207,6 +207,69 @@ __global__ void k_pad(const C* __restrict__ x, C* __restrict__ P, Dims dm, int64
   }
 }
 
+// One-shot pad and project of the embedding baseline (one or two entries per
+// thread, indices decoded by multiply-high division), used while every index
+// fits in 32 bits: per level the grid size and dividers by n and 2n.
+struct PadGeo {
+  int d;
+  uint32_t n[kMaxD];
+  sfft::FastDiv fn[kMaxD], f2n[kMaxD];
+};
+
+PadGeo pad_geo(const Dims& dm) {
+  PadGeo g;
+  std::memset(&g, 0, sizeof(g));
+  g.d = dm.d;
+  for (int l = 0; l < dm.d; ++l) {
+    g.n[l] = (uint32_t)dm.n[l];
+    g.fn[l] = sfft::FastDiv::make((uint32_t)dm.n[l]);
+    g.f2n[l] = sfft::FastDiv::make((uint32_t)(2 * dm.n[l]));
+  }
+  return g;
+}
+
+// x (nv, n...) -> P (nv, 2n...): thread i writes padded entries 2i and 2i + 1,
+// which share a row (the padded last length is even); the first n entries
+// along every level come from x, the rest are zero
+template <typename C>
+__global__ void __launch_bounds__(256) k_pad2(const C* __restrict__ x, C* __restrict__ P, PadGeo g, uint32_t npairs) {
+  const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+  if (i >= npairs) return;
+  uint32_t rem = 2 * i, src = 0, sstride = 1, mlast = 0;
+  bool inside = true;
+  for (int l = g.d - 1; l >= 0; --l) {
+    const uint32_t q = g.f2n[l].div(rem);
+    const uint32_t m = rem - q * (2 * g.n[l]);
+    if (l == g.d - 1) mlast = m;
+    else inside = inside && m < g.n[l];
+    src += m * sstride;
+    sstride *= g.n[l];
+    rem = q;
+  }
+  const uint32_t s0 = rem * sstride + src;  // rem is the vector index
+  const uint32_t nl = g.n[g.d - 1];
+  C a = sfft::mk<C>(0, 0), b = a;
+  if (inside && mlast < nl) a = x[s0];
+  if (inside && mlast + 1 < nl) b = x[s0 + 1];
+  P[2 * (size_t)i] = a;
+  P[2 * (size_t)i + 1] = b;
+}
+
+// y (nv, n...) <- the first n entries along every level of P (nv, 2n...)
+template <typename C>
+__global__ void __launch_bounds__(256) k_project2(const C* __restrict__ P, C* __restrict__ y, PadGeo g, uint32_t total) {
+  const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+  if (i >= total) return;
+  uint32_t rem = i, src = 0, sstride = 1;
+  for (int l = g.d - 1; l >= 0; --l) {
+    const uint32_t q = g.fn[l].div(rem);
+    src += (rem - q * g.n[l]) * sstride;
+    sstride *= 2 * g.n[l];
+    rem = q;
+  }
+  y[i] = P[rem * sstride + src];
+}
+
 // zero-padded (nv, 2n...) -> y (nv, n...): keep the first n along every level
 template <typename C>
 __global__ void k_project(const C* __restrict__ P, C* __restrict__ y, Dims dm, int64_t total) {
@@ -462,9 +525,17 @@ sfft_status embed_apply(const sfft_plan_s* p, const void* x, void* y, int64_t nr
   dm.d = d;
   for (int l = 0; l < d; ++l) dm.n[l] = p->n[l];
   const int64_t big = nv * p->s * (int64_t(1) << d);
+  const bool idx32 = big < (int64_t(1) << 32);
+  const PadGeo pg = pad_geo(dm);
   {
     ProfScope ps(p, SFFT_KIND_COPY, st);
-    if (p->dtype == SFFT_C64)
+    const uint32_t npairs = (uint32_t)(big / 2);
+    const dim3 g2((npairs + 255) / 256);
+    if (idx32 && p->dtype == SFFT_C64)
+      hipLaunchKernelGGL(k_pad2<float2>, g2, dim3(256), 0, st, (const float2*)x, (float2*)ws, pg, npairs);
+    else if (idx32)
+      hipLaunchKernelGGL(k_pad2<double2>, g2, dim3(256), 0, st, (const double2*)x, (double2*)ws, pg, npairs);
+    else if (p->dtype == SFFT_C64)
       hipLaunchKernelGGL(k_pad<float2>, dim3(grid_for(big)), dim3(256), 0, st, (const float2*)x, (float2*)ws, dm,
                          big);
     else
@@ -490,7 +561,14 @@ sfft_status embed_apply(const sfft_plan_s* p, const void* x, void* y, int64_t nr
   const int64_t small = nv * p->s;
   {
     ProfScope ps(p, SFFT_KIND_COPY, st);
-    if (p->dtype == SFFT_C64)
+    const dim3 g1((unsigned)((small + 255) / 256));
+    if (idx32 && p->dtype == SFFT_C64)
+      hipLaunchKernelGGL(k_project2<float2>, g1, dim3(256), 0, st, (const float2*)ws, (float2*)y, pg,
+                         (uint32_t)small);
+    else if (idx32)
+      hipLaunchKernelGGL(k_project2<double2>, g1, dim3(256), 0, st, (const double2*)ws, (double2*)y, pg,
+                         (uint32_t)small);
+    else if (p->dtype == SFFT_C64)
       hipLaunchKernelGGL(k_project<float2>, dim3(grid_for(small)), dim3(256), 0, st, (const float2*)ws, (float2*)y,
                          dm, small);
     else

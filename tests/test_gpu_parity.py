@@ -140,6 +140,33 @@ def test_multi_rhs_and_depth_schedule(sf):
             assert wl.relative_l2(got, want) <= TOL[dtype]
 
 
+@pytest.mark.parametrize("grid,nrhs", [((64, 64, 64), 16), ((64, 24, 10), 401)])
+def test_large_launch_matches_single_rhs_applies(sf, grid, nrhs):
+    """b=3, complex64, breadth-first, many right-hand sides: 64^3 with 16 of them
+    runs level-2 passes of 12288 workgroups, 64 x 24 x 10 with 401 passes of 9023
+    and 24060 (not multiples of 8: the grids are rounded up and 1 and 4 work items
+    are past the end); all use the XCD-contiguous block order, and the leaf takes several
+    right-hand sides per symbol fetch. Neither changes any entry's arithmetic, so
+    every right-hand side must equal its own single-RHS apply (dispatch order, one
+    right-hand side per leaf lane group) bit for bit: a tile skipped or done twice
+    would not. The first right-hand side is also checked against the FP64 oracle."""
+    coeffs = wl.green_coeffs(grid, 0.7) if grid == (64, 64, 64) else wl.iid_coeffs(41, grid, 3)
+    x = wl.vectors(42, grid, 3, nrhs)
+    _say(f"block order n={grid} nrhs={nrhs}")
+    plan = sf.Plan(grid, 3, torch.from_numpy(coeffs).cuda(), dtype="c64", max_nrhs=nrhs, schedule="breadth")
+    xd = torch.from_numpy(x.astype(np.complex64)).cuda()
+    ws = plan.alloc_workspace(nrhs)
+    y = plan.apply(xd, workspace=ws)
+    for r in range(nrhs):
+        y1 = plan.apply(xd[r:r + 1].contiguous(), workspace=ws)
+        assert torch.equal(y[r:r + 1], y1), r
+    torch.cuda.synchronize()
+    got = y[:1].cpu().numpy().astype(np.complex128)
+    plan.close()
+    want = oracle.embed_matvec(coeffs, x[:1])
+    assert wl.relative_l2(got, want) <= TOL["c64"]
+
+
 def test_apply_rejects_bad_arguments(sf):
     grid, b = (8, 8), 1
     plan = sf.Plan(grid, b, torch.from_numpy(wl.iid_coeffs(1, grid, b)).cuda(), dtype="c64")
