@@ -326,6 +326,7 @@ def bench_serve(args):
         out[name] = {k: (round(v, 5) if isinstance(v, float) else v) for k, v in summ.items()}
         log(f"[serve {name}] p50 {summ['p50_s']:.3f} s p99 {summ['p99_s']:.3f} s, "
             f"{summ['matvecs_per_s']:.0f} matvecs/s")
+        ex.close()
         del ex, srv
         torch.cuda.empty_cache()
     print(json.dumps({"workload": "serve-poisson200-green-b3-arnoldi30", "results": out,

@@ -111,11 +111,32 @@ typedef struct {
  *   max_nrhs  largest nrhs a later apply may use (sizes sfft_plan_info only).
  *   schedule  sfft_schedule.
  *   stream    hipStream_t for the generation kernels.
- * The plan owns its device memory and is immutable after creation; one plan
- * may be applied concurrently on several streams with distinct workspaces. */
+ * The plan owns its device memory and changes only through sfft_plan_update;
+ * one plan may be applied concurrently on several streams with distinct
+ * workspaces. */
 sfft_status sfft_plan_create(sfft_plan* out, int d, const int64_t* n, int b, const void* coeffs,
                              int dtype, int method, const int32_t* parity, int64_t max_nrhs,
                              int schedule, void* stream);
+
+/* Regenerates the plan's symbols (Section II: the FFT of the embedded
+ * generator, split by parity per level) from new coefficients in place, so a
+ * plan and its memory serve another Toeplitz matrix of the same shape: sizes,
+ * buffers, workspace needs and batched-apply graphs that hold the plan stay
+ * valid, and nothing is allocated beyond the generation scratch (ordered on
+ * `stream`).
+ *   coeffs  device, complex128, the layout of sfft_plan_create; its block
+ *           symmetry (every pair t[a,c] = t[c,a], or every pair
+ *           t[a,c] = -t[c,a], or neither) must equal the plan's
+ *           (sfft_info.block_symmetry), else SFFT_INVALID_ARG and the plan is
+ *           unchanged. A mirrored plan trusts the parity it was created with.
+ *   stream  hipStream_t for the generation kernels, synchronised before
+ *           return. Every earlier use of the plan (applies on any stream) must
+ *           be ordered before the work on `stream`: the symbols are
+ *           overwritten in place.
+ * Errors: SFFT_INVALID_ARG (null plan or coeffs, other block symmetry),
+ * SFFT_OUT_OF_MEMORY / SFFT_HIP_ERROR (generation scratch or kernels; the
+ * symbols are then undefined until a successful update). */
+sfft_status sfft_plan_update(sfft_plan plan, const void* coeffs, void* stream);
 
 /* Device bytes of workspace sfft_apply needs for nrhs >= 0 right-hand sides
  * (0 for nrhs = 0). */

@@ -26,7 +26,7 @@ EXPORTS = [
     "sfft_plan_create", "sfft_workspace_size", "sfft_apply", "sfft_workspace_size_multi",
     "sfft_apply_multi", "sfft_plan_info", "sfft_plan_destroy", "sfft_status_string",
     "sfft_last_error", "sfft_length_supported", "sfft_profile_enable", "sfft_profile_read",
-    "sfft_plan_autotune", "sfft_arnoldi_scratch_size", "sfft_arnoldi_step_multi",
+    "sfft_plan_autotune", "sfft_arnoldi_scratch_size", "sfft_arnoldi_step_multi", "sfft_plan_update",
 ]
 KIND_FORWARD, KIND_LEAF, KIND_INVERSE, KIND_COPY = range(4)
 
@@ -68,6 +68,7 @@ def _load():
                                      vp]
     lib.sfft_plan_info.argtypes = [vp, C.POINTER(SfftInfo)]
     lib.sfft_plan_destroy.argtypes = [vp]
+    lib.sfft_plan_update.argtypes = [vp, vp, vp]
     lib.sfft_status_string.argtypes = [C.c_int]
     lib.sfft_status_string.restype = C.c_char_p
     lib.sfft_last_error.argtypes = []

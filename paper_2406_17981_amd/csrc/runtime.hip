@@ -289,25 +289,41 @@ __global__ void k_project(const C* __restrict__ P, C* __restrict__ y, Dims dm, i
 // Block symmetry of the coefficients, exactly: for every pair a < c, bit 0 of
 // flags[pair] is set if some offset has t[a,c] != t[c,a], bit 1 if some
 // offset has t[a,c] != -t[c,a]. One atomic per wavefront that saw a mismatch.
-__global__ void k_block_symmetry(const double2* __restrict__ coeffs, int B, int64_t ncoef, unsigned* flags) {
+// Every wavefront that finds a mismatch would otherwise hit the same few flag
+// words (the symmetric Green blocks make every one of them "not
+// antisymmetric"), so the workgroup first combines its bits in LDS and skips
+// the atomic when the flag already holds them.
+template <int B>
+__global__ void __launch_bounds__(256) k_block_symmetry(const double2* __restrict__ coeffs, int64_t ncoef,
+                                                        unsigned* flags) {
+  constexpr int NPR = B * (B - 1) / 2;
+  __shared__ unsigned wg_bits;
+  if (threadIdx.x == 0) wg_bits = 0;
+  __syncthreads();
   unsigned bits = 0;  // bit 2*pair + {0: not symmetric, 1: not antisymmetric}
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < ncoef;
        idx += (int64_t)gridDim.x * blockDim.x) {
+    double2 u[NPR], v[NPR];
     int pr = 0;
+#pragma unroll
     for (int a = 0; a < B; ++a)
+#pragma unroll
       for (int c = a + 1; c < B; ++c, ++pr) {
-        const double2 u = coeffs[(int64_t)(a * B + c) * ncoef + idx];
-        const double2 v = coeffs[(int64_t)(c * B + a) * ncoef + idx];
-        if (!(u.x == v.x && u.y == v.y)) bits |= 1u << (2 * pr);
-        if (!(u.x == -v.x && u.y == -v.y)) bits |= 2u << (2 * pr);
+        u[pr] = coeffs[(int64_t)(a * B + c) * ncoef + idx];
+        v[pr] = coeffs[(int64_t)(c * B + a) * ncoef + idx];
       }
+#pragma unroll
+    for (int q = 0; q < NPR; ++q) {
+      if (!(u[q].x == v[q].x && u[q].y == v[q].y)) bits |= 1u << (2 * q);
+      if (!(u[q].x == -v[q].x && u[q].y == -v[q].y)) bits |= 2u << (2 * q);
+    }
   }
   for (int off = 32; off > 0; off >>= 1) bits |= __shfl_xor(bits, off, 64);
-  if (bits && (threadIdx.x % 64) == 0) {
-    for (int pr = 0; pr < B * (B - 1) / 2; ++pr) {
-      const unsigned f = (bits >> (2 * pr)) & 3u;
-      if (f) atomicOr(&flags[pr], f);
-    }
+  if (bits && (threadIdx.x % 64) == 0) atomicOr(&wg_bits, bits);
+  __syncthreads();
+  if (threadIdx.x < NPR) {
+    const unsigned f = (wg_bits >> (2 * threadIdx.x)) & 3u;
+    if (f && (__atomic_load_n(&flags[threadIdx.x], __ATOMIC_RELAXED) & f) != f) atomicOr(&flags[threadIdx.x], f);
   }
 }
 
@@ -601,10 +617,31 @@ sfft_status fft64_inplace(const Dims& dm, double2* a, void* const* tw64, hipStre
   return SFFT_OK;
 }
 
-sfft_status make_table(int dtype, int64_t L, void** out, size_t* bytes, hipStream_t st) {
+// Transient device buffers of plan creation, allocated and freed in order on
+// its stream (hipFree would wait for all work on the device, including other
+// streams' applies); plain hipMalloc / hipFree where the device has no
+// stream-ordered pools.
+bool pools_supported() {
+  static const bool ok = [] {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    return hipDeviceGetAttribute(&v, hipDeviceAttributeMemoryPoolsSupported, dev) == hipSuccess && v != 0;
+  }();
+  return ok;
+}
+hipError_t tmp_alloc(void** p, size_t n, hipStream_t st) {
+  return pools_supported() ? hipMallocAsync(p, n, st) : hipMalloc(p, n);
+}
+void tmp_free(void* p, hipStream_t st) {
+  if (!p) return;
+  if (pools_supported()) (void)hipFreeAsync(p, st);
+  else (void)hipFree(p);
+}
+
+sfft_status make_table(int dtype, int64_t L, void** out, size_t* bytes, hipStream_t st, bool transient = false) {
   const size_t esz = dtype == SFFT_C64 ? 8 : 16;
   const size_t nb = (size_t)(2 * L) * esz;
-  HIP_TRY(hipMalloc(out, nb), "twiddle table allocation");
+  HIP_TRY(transient ? tmp_alloc(out, nb, st) : hipMalloc(out, nb), "twiddle table allocation");
   if (dtype == SFFT_C64)
     hipLaunchKernelGGL(k_twiddle<float2>, dim3(grid_for(2 * L)), dim3(256), 0, st, (float2*)*out, (int)L);
   else
@@ -623,16 +660,19 @@ sfft_status detect_block_symmetry(const double2* coeffs, int b, int64_t ncoef, h
   if (b < 2 || (env && env[0] && env[0] != '0')) return SFFT_OK;
   const int npair = b * (b - 1) / 2;
   unsigned* flags = nullptr;
-  HIP_TRY(hipMalloc((void**)&flags, npair * sizeof(unsigned)), "symmetry flags allocation");
+  HIP_TRY(tmp_alloc((void**)&flags, npair * sizeof(unsigned), st), "symmetry flags allocation");
   std::vector<unsigned> h(npair, 0);
   hipError_t e = hipMemsetAsync(flags, 0, npair * sizeof(unsigned), st);
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_block_symmetry, dim3(grid_for(ncoef)), dim3(256), 0, st, coeffs, b, ncoef, flags);
+    const dim3 g(grid_for(ncoef));
+    if (b == 2) hipLaunchKernelGGL(k_block_symmetry<2>, g, dim3(256), 0, st, coeffs, ncoef, flags);
+    else if (b == 3) hipLaunchKernelGGL(k_block_symmetry<3>, g, dim3(256), 0, st, coeffs, ncoef, flags);
+    else hipLaunchKernelGGL(k_block_symmetry<4>, g, dim3(256), 0, st, coeffs, ncoef, flags);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipMemcpyAsync(h.data(), flags, npair * sizeof(unsigned), hipMemcpyDeviceToHost, st);
+  tmp_free(flags, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
-  (void)hipFree(flags);
   if (e != hipSuccess) return hip_fail(e, "block symmetry check");
   bool sym = true, anti = true;
   for (unsigned f : h) {
@@ -656,14 +696,13 @@ sfft_status build_symbols(sfft_plan_s* p, const double2* coeffs, hipStream_t st)
   double2* tmp = nullptr;
   sfft_status s = SFFT_OK;
   auto cleanup = [&]() {
+    for (int l = 0; l < d; ++l) tmp_free(tw64[l], st);
+    tmp_free(tmp, st);
     (void)hipStreamSynchronize(st);
-    for (int l = 0; l < d; ++l)
-      if (tw64[l]) (void)hipFree(tw64[l]);
-    if (tmp) (void)hipFree(tmp);
   };
-  for (int l = 0; l < d && s == SFFT_OK; ++l) s = make_table(SFFT_C128, 2 * p->n[l], &tw64[l], nullptr, st);
+  for (int l = 0; l < d && s == SFFT_OK; ++l) s = make_table(SFFT_C128, 2 * p->n[l], &tw64[l], nullptr, st, true);
   if (s == SFFT_OK) {
-    hipError_t e = hipMalloc((void**)&tmp, (size_t)full * sizeof(double2));
+    hipError_t e = tmp_alloc((void**)&tmp, (size_t)full * sizeof(double2), st);
     if (e != hipSuccess) s = hip_fail(e, "FP64 symbol scratch allocation");
   }
   const double scale = 1.0 / ((double)full);  // 2^-d / prod(n)
@@ -919,6 +958,20 @@ sfft_status sfft_plan_create(sfft_plan* out, int d, const int64_t* n, int b, con
   }
   *out = p;
   return SFFT_OK;
+}
+
+sfft_status sfft_plan_update(sfft_plan plan, const void* coeffs, void* stream) {
+  if (!plan || !coeffs) return fail(SFFT_INVALID_ARG, "null argument");
+  hipStream_t st = (hipStream_t)stream;
+  int64_t ncoef = 1;
+  for (int l = 0; l < plan->d; ++l) ncoef *= 2 * plan->n[l] - 1;
+  int bsym = 0;
+  sfft_status s = detect_block_symmetry((const double2*)coeffs, plan->b, ncoef, st, &bsym);
+  if (s != SFFT_OK) return s;
+  if (bsym != plan->bsym)
+    return fail(SFFT_INVALID_ARG, "block symmetry " + std::to_string(bsym) + " differs from the plan's " +
+                                      std::to_string(plan->bsym));
+  return build_symbols(plan, (const double2*)coeffs, st);
 }
 
 sfft_status sfft_workspace_size(sfft_plan plan, int64_t nrhs, size_t* bytes) {

@@ -163,6 +163,19 @@ class Plan:
                 "sfft_profile_read")
         return float(ms.value), int(cnt.value)
 
+    def update(self, coeffs, stream=None) -> None:
+        """New coefficients of the same shape and block symmetry: the symbols
+        are regenerated in place (sfft_plan_update). Earlier applies of the
+        plan must be ordered before `stream`."""
+        if not isinstance(coeffs, torch.Tensor) or not coeffs.is_cuda:
+            coeffs = torch.as_tensor(coeffs, dtype=torch.complex128).to("cuda")
+        _require_device(coeffs, "coeffs", torch.complex128)
+        want = (self.b, self.b) + tuple(2 * v - 1 for v in self.n)
+        if tuple(coeffs.shape) != want:
+            raise ValueError(f"coeffs shape {tuple(coeffs.shape)} != {want}")
+        N.check(N.lib.sfft_plan_update(self.handle, C.c_void_p(coeffs.data_ptr()),
+                                       C.c_void_p(_stream_handle(stream))), "sfft_plan_update")
+
     def close(self):
         if getattr(self, "_h", None) is not None:
             N.lib.sfft_plan_destroy(self._h)

@@ -17,7 +17,13 @@ The server
   batching), and records arrival, admission and completion times;
 * finishes a request with the GMRES solve of T x = b on its chain: the small
   least-squares problem min ||beta e_1 - H y|| on the host and x = V y on the
-  device.
+  device. The host does not wait for the device between steps: a finished
+  chain's Hessenberg matrix is copied back asynchronously and the request
+  completes once that copy has landed, while later steps are already queued;
+* keeps the plans of finished requests for reuse: a new request on the same
+  grid takes one over and only regenerates its symbols (sfft_plan_update),
+  so admission allocates and frees no device memory; idle plans count
+  against the budget and are closed when an admission needs the room.
 
 Every kernel is deterministic and works on one request's buffers only, so a
 request's results are bitwise the same alone and in any mix.
@@ -89,11 +95,29 @@ class Executor:
         """One Arnoldi step for each slot."""
         raise NotImplementedError
 
+    def finish_start(self, slot: object) -> None:
+        """Starts fetching a finished chain's results without waiting."""
+
+    def finish_ready(self, slot: object) -> bool:
+        """True once finish(slot) would not wait for the device."""
+        return True
+
+    def finish_wait(self, slot: object) -> None:
+        """Blocks until finish_ready(slot)."""
+
     def finish(self, slot: object) -> dict:
         raise NotImplementedError
 
     def release(self, slot: object) -> None:
         raise NotImplementedError
+
+    def idle_bytes(self, req: Optional[Request] = None) -> int:
+        """Device bytes kept for reuse outside any request, less what admitting
+        `req` would take over (counted in its own bytes_needed)."""
+        return 0
+
+    def trim(self, req: Optional[Request] = None) -> None:
+        """Frees the memory idle_bytes(req) counts."""
 
 
 @dataclass
@@ -120,11 +144,15 @@ class Server:
         self.batch_sizes: List[int] = []
         self.time_in = dict(admit=0.0, step=0.0, finish=0.0)  # host seconds per phase
 
-    def _try_admit(self, req: Request, now: float, active: List[_Slot]) -> bool:
+    def _try_admit(self, req: Request, now: float, active: List[_Slot], draining: int = 0) -> bool:
         resident, transient = self.ex.bytes_needed(req)
         if resident + transient > self.budget:
             raise ValueError(f"request {req.rid} needs {resident + transient} bytes, budget {self.budget}")
-        if len(active) >= self.max_active or self.reserved + resident + transient > self.budget:
+        if len(active) + draining >= self.max_active:
+            return False
+        if self.reserved + resident + transient + self.ex.idle_bytes(req) > self.budget and self.ex.idle_bytes(req):
+            self.ex.trim(req)
+        if self.reserved + resident + transient + self.ex.idle_bytes(req) > self.budget:
             return False
         self.reserved += resident + transient
         self.peak_reserved = max(self.peak_reserved, self.reserved)
@@ -136,22 +164,41 @@ class Server:
         active.append(_Slot(req, handle, resident))
         return True
 
+    def _complete(self, s: _Slot, t0: float, finished: List[Request]) -> None:
+        t = self.clock()
+        s.req.result = self.ex.finish(s.handle)
+        s.req.done = self.clock() - t0
+        self.ex.release(s.handle)
+        self.time_in["finish"] += self.clock() - t
+        self.reserved -= s.reserved
+        finished.append(s.req)
+
     def run(self, requests: Sequence[Request]) -> List[Request]:
         pending = sorted(requests, key=lambda r: r.arrival)
         queue: List[Request] = []
         active: List[_Slot] = []
+        draining: List[_Slot] = []   # chains done, results on their way back
         finished: List[Request] = []
         t0 = self.clock()
         i = 0
-        while i < len(pending) or queue or active:
+        while i < len(pending) or queue or active or draining:
+            still = []
+            for s in draining:
+                if self.ex.finish_ready(s.handle):
+                    self._complete(s, t0, finished)
+                else:
+                    still.append(s)
+            draining = still
             now = self.clock() - t0
             while i < len(pending) and pending[i].arrival <= now:
                 queue.append(pending[i])
                 i += 1
-            while queue and self._try_admit(queue[0], self.clock() - t0, active):
+            while queue and self._try_admit(queue[0], self.clock() - t0, active, len(draining)):
                 queue.pop(0)
             if not active:
-                if i < len(pending):
+                if draining:
+                    self.ex.finish_wait(draining[0].handle)
+                elif i < len(pending):
                     self.sleep(max(0.0, pending[i].arrival - (self.clock() - t0)))
                 continue
             t = self.clock()
@@ -163,13 +210,8 @@ class Server:
             for s in active:
                 s.done_steps += 1
                 if s.done_steps >= s.req.steps:
-                    t = self.clock()
-                    s.req.result = self.ex.finish(s.handle)
-                    s.req.done = self.clock() - t0
-                    self.ex.release(s.handle)
-                    self.time_in["finish"] += self.clock() - t
-                    self.reserved -= s.reserved
-                    finished.append(s.req)
+                    self.ex.finish_start(s.handle)
+                    draining.append(s)
                 else:
                     still.append(s)
             active = still
@@ -200,7 +242,7 @@ class GpuExecutor(Executor):
     `mirrored` (symbols stored mirrored)."""
 
     def __init__(self, coeff_fn, parity_fn=None, dtype: str = "c64", nstreams: int = 4, mirrored: bool = True,
-                 schedule: str = "depth", keep_basis: bool = False):
+                 schedule: str = "depth", keep_basis: bool = False, max_ahead: int = 2):
         import torch
         from . import _native as N
         from .plan import Plan
@@ -223,6 +265,13 @@ class GpuExecutor(Executor):
         # its completion wait does not drain the other requests' queued steps
         self.admit_stream = torch.cuda.Stream()
         self._scratch = None
+        # plans of finished requests by grid, each with the event after its
+        # last use, and their device bytes
+        self._idle = {}
+        self._idle_total = 0
+        # server steps queued on the device beyond the one being issued
+        self.max_ahead = max_ahead
+        self._inflight = []
 
     def bytes_needed(self, req: Request) -> tuple:
         n, d, b = req.n, len(req.n), 3
@@ -234,14 +283,46 @@ class GpuExecutor(Executor):
         transient = 9 * math.prod(2 * v - 1 for v in n) * 16 + math.prod(2 * v for v in n) * 16
         return resident, transient
 
+    @staticmethod
+    def _plan_bytes(plan) -> int:
+        info = plan.info()
+        return int(info["symbol_bytes"] + info["table_bytes"])
+
+    def idle_bytes(self, req: Optional[Request] = None) -> int:
+        total = self._idle_total
+        if req is not None and self._idle.get(tuple(req.n)):
+            total -= self._idle[tuple(req.n)][-1][2]
+        return total
+
+    def trim(self, req: Optional[Request] = None) -> None:
+        keep = tuple(req.n) if req is not None else None
+        for key, lst in list(self._idle.items()):
+            stay = lst[-1:] if key == keep else []
+            for plan, ev, nb in lst[:len(lst) - len(stay)]:
+                ev.synchronize()
+                plan.close()
+                self._idle_total -= nb
+            self._idle[key] = stay
+
+    def close(self) -> None:
+        self.trim()
+
     def admit(self, req: Request) -> dict:
         torch = self.torch
         n, b = req.n, 3
+        reuse = self._idle.get(tuple(n))
         with torch.cuda.stream(self.admit_stream):
             coeffs = self.coeff_fn(n, req.k)
-            par = self.parity_fn(len(n)) if self.mirrored else None
-            plan = self.Plan(n, b, coeffs, dtype=self.dtype, parity=par, max_nrhs=1, schedule=self.schedule,
-                             stream=self.admit_stream)
+            if reuse:
+                # the plan's last applies finish before its symbols change
+                plan, ev, nb = reuse.pop()
+                self._idle_total -= nb
+                self.admit_stream.wait_event(ev)
+                plan.update(coeffs, stream=self.admit_stream)
+            else:
+                par = self.parity_fn(len(n)) if self.mirrored else None
+                plan = self.Plan(n, b, coeffs, dtype=self.dtype, parity=par, max_nrhs=1, schedule=self.schedule,
+                                 stream=self.admit_stream)
             del coeffs
         vlen = b * math.prod(n)
         basis = torch.empty((req.steps + 1, vlen), dtype=self.tdt, device="cuda")
@@ -279,6 +360,15 @@ class GpuExecutor(Executor):
         N.check(N.lib.sfft_arnoldi_step_multi(len(jobs), arr, code, C.c_void_p(self._scratch.data_ptr()),
                                               self._scratch.numel(), C.c_void_p(st)), "sfft_arnoldi_step_multi")
 
+    def _throttle(self) -> None:
+        # at most max_ahead server steps queued behind the one being issued, so
+        # a newly admitted request does not wait behind a long queue
+        ev = self.torch.cuda.Event()
+        ev.record(self.main)
+        self._inflight.append(ev)
+        while len(self._inflight) > self.max_ahead:
+            self._inflight.pop(0).synchronize()
+
     def step(self, slots) -> None:
         torch = self.torch
         ev = torch.cuda.Event()
@@ -295,6 +385,23 @@ class GpuExecutor(Executor):
             jobs.append(dict(V=s["basis"], m=j + 1, w=s["w"], vout=s["basis"][j + 1], hcol=s["Hc"][j]))
             s["j"] = j + 1
         self._arnoldi(jobs)
+        self._throttle()
+
+    def finish_start(self, slot) -> None:
+        torch = self.torch
+        host = torch.empty(slot["Hc"].shape, dtype=torch.complex128, pin_memory=True)
+        with torch.cuda.stream(self.main):
+            host.copy_(slot["Hc"], non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(self.main)
+        slot["fin"] = (ev, host)
+
+    def finish_ready(self, slot) -> bool:
+        return slot["fin"][0].query() if "fin" in slot else True
+
+    def finish_wait(self, slot) -> None:
+        if "fin" in slot:
+            slot["fin"][0].synchronize()
 
     def finish(self, slot) -> dict:
         """GMRES on the finished chain: y = argmin ||beta e_1 - H y|| (a small
@@ -302,10 +409,15 @@ class GpuExecutor(Executor):
         y, the residual estimate ||beta e_1 - H y|| / beta and, when kept, the
         basis and x."""
         torch = self.torch
-        torch.cuda.current_stream().synchronize()
         req = slot["req"]
         m = req.steps
-        Hc = slot["Hc"].cpu().numpy()
+        if "fin" in slot:
+            ev, host = slot["fin"]
+            ev.synchronize()
+            Hc = host.numpy()
+        else:
+            self.main.synchronize()
+            Hc = slot["Hc"].cpu().numpy()
         H = Hc[:m].T.copy()                      # (m+1, m) upper Hessenberg
         beta = float(Hc[m, 0].real)              # ||b||
         rhs = np.zeros(m + 1, dtype=np.complex128)
@@ -321,7 +433,19 @@ class GpuExecutor(Executor):
         return out
 
     def release(self, slot) -> None:
-        slot["plan"].close()
+        # keep the plan for the next request on this grid with an event after
+        # its last use: the one behind the finished chain's copy (every stream
+        # of the request joined the main stream before it), not one at the
+        # current end of the main stream, which may hold later steps
+        if "fin" in slot:
+            ev = slot["fin"][0]
+        else:
+            ev = self.torch.cuda.Event()
+            ev.record(self.main)
+        plan = slot["plan"]
+        nb = self._plan_bytes(plan)
+        self._idle.setdefault(tuple(slot["req"].n), []).append((plan, ev, nb))
+        self._idle_total += nb
         slot.clear()
 
 
@@ -335,3 +459,4 @@ class SingleRequestExecutor(GpuExecutor):
             j = s["j"]
             self._arnoldi([dict(V=s["basis"], m=j + 1, w=s["w"], vout=s["basis"][j + 1], hcol=s["Hc"][j])])
             s["j"] = j + 1
+        self._throttle()

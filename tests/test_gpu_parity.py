@@ -403,3 +403,37 @@ def test_block_symmetry_with_mirrored_storage(sf, dtype):
         info, got = _plan_info_and_product(sf, coeffs, x, dtype, parity=par)
         assert info["compressed"] == 1 and info["block_symmetry"] == bs
         assert wl.relative_l2(got, oracle.embed_matvec(coeffs, x)) <= TOL[dtype]
+
+
+# ---------------------------------------------------------------------------
+# Plan update (new coefficients of the same shape and block symmetry)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("mirrored", [False, True])
+def test_plan_update_equals_a_fresh_plan(sf, dtype, mirrored):
+    """A plan made for the Green kernel at k=0.7 and updated to k=1.1 gives bit
+    for bit what a plan made at k=1.1 gives (the same symbol generation into the
+    same layout), and matches the FP64 oracle. Coefficients without the plan's
+    block symmetry (i.i.d. blocks) are refused, and the plan keeps its symbols."""
+    grid = (16, 12, 10)
+    ca, cb = wl.green_coeffs(grid, 0.7), wl.green_coeffs(grid, 1.1)
+    par = wl.green_parity(3) if mirrored else None
+    x = wl.vectors(55, grid, 3, 2)
+    xd = torch.from_numpy(x.astype(NP[dtype])).cuda()
+    _say(f"plan update n={grid} dtype={dtype} mirrored={mirrored}")
+    plan = sf.Plan(grid, 3, torch.from_numpy(ca).cuda(), dtype=dtype, parity=par, max_nrhs=2)
+    fresh = sf.Plan(grid, 3, torch.from_numpy(cb).cuda(), dtype=dtype, parity=par, max_nrhs=2)
+    ya = plan.apply(xd)
+    plan.update(torch.from_numpy(cb).cuda())
+    yb = plan.apply(xd)
+    assert torch.equal(yb, fresh.apply(xd))
+    assert not torch.equal(ya, yb)
+    want = oracle.embed_matvec(cb, x)
+    assert wl.relative_l2(yb.cpu().numpy().astype(np.complex128), want) <= TOL[dtype]
+    with pytest.raises(sf.SfftError):
+        plan.update(torch.from_numpy(wl.iid_coeffs(3, grid, 3)).cuda())
+    assert torch.equal(plan.apply(xd), yb)
+    assert plan.info()["block_symmetry"] == 1
+    torch.cuda.synchronize()
+    plan.close()
+    fresh.close()

@@ -90,3 +90,33 @@ def test_gmres_solution_residual_matches_estimate(serve, dtype, mirrored, tol):
             est = np.linalg.norm(rhs - Hm @ y) / res["start_norm"]
             assert est <= prev + 1e-12, (rid, m)
             prev = est
+
+
+def test_reused_plans_give_the_results_of_fresh_ones(serve):
+    """With two slots, later requests on a grid that an earlier request used
+    take over its plan (symbols regenerated for their own k); every result is
+    bitwise the one the request gets alone on a fresh executor."""
+    R = serve.Request
+    reqs = [R(rid=0, arrival=0.0, n=(16, 16, 16), k=0.9, steps=6, seed=21),
+            R(rid=1, arrival=0.0, n=(32, 32), k=1.2, steps=6, seed=22),
+            R(rid=2, arrival=0.0, n=(16, 16, 16), k=1.4, steps=6, seed=23),
+            R(rid=3, arrival=0.0, n=(32, 32), k=0.6, steps=6, seed=24),
+            R(rid=4, arrival=0.0, n=(16, 16, 16), k=0.7, steps=6, seed=25)]
+    ex = serve.GpuExecutor(_coeff_fn, wl.green_parity, dtype="c64", mirrored=True, keep_basis=True)
+    creates = []
+    orig = ex.Plan
+
+    def counting_plan(*a, **kw):
+        creates.append(a[0])
+        return orig(*a, **kw)
+
+    ex.Plan = counting_plan
+    srv = serve.Server(ex, budget_bytes=8 << 30, max_active=2)
+    mixed = {r.rid: r for r in srv.run(reqs)}
+    ex.close()
+    assert len(creates) < len(reqs)          # some admissions reused a plan
+    for r in reqs:
+        alone = _run(serve, [R(rid=r.rid, arrival=0.0, n=r.n, k=r.k, steps=r.steps, seed=r.seed)],
+                     max_active=1)[r.rid]
+        assert np.array_equal(alone.result["H"], mixed[r.rid].result["H"]), r.rid
+        assert np.array_equal(alone.result["basis"], mixed[r.rid].result["basis"]), r.rid
