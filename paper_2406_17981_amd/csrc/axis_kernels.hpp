@@ -121,6 +121,11 @@ template <typename Real, int L> struct Geo {
   static constexpr int P = NT / T;                     // contiguous tile (pencils)
   static constexpr int LP = L + 1;                     // padded LDS row
   static constexpr bool WS = (64 % T) == 0;    // contiguous pass: pencil inside one wavefront
+  // Passes of length 128 and more are bound by occupancy (about 170-200
+  // VGPRs): they form the split phase Phi[t + T m] = Phi[t] Phi[T m] from one
+  // per-lane value and lane-uniform table entries when needed. Shorter passes
+  // are bound by latency: they load their E phases up front.
+  static constexpr bool PH_ARRAY = L < 128;
   // Leaf kernel: its own radix plan (FP64 lanes hold fewer entries). A tile
   // is PL pencils (SL = PL * LT lanes, one symbol block); a workgroup takes
   // one tile for RB right-hand sides (RB chosen per launch, <= RBMAX).
@@ -220,9 +225,18 @@ __global__ void __launch_bounds__(256) k_strided(PassArgs a) {
   C* lp = lds + c;
   LaneTw<C, Sh> lt;
   lt.load(t, tw);
-  C ph[E];  // split phases Phi[k] of this lane's entries
+  // split phases Phi[t + T m] of this lane's entries (Geo::PH_ARRAY)
+  C ph[G::PH_ARRAY ? E : 1];
+  if constexpr (G::PH_ARRAY) {
 #pragma unroll
-  for (int m = 0; m < E; ++m) ph[m] = tw[t + T * m];
+    for (int m = 0; m < E; ++m) ph[m] = tw[t + T * m];
+  } else {
+    ph[0] = tw[t];
+  }
+  auto phase = [&](int m) -> C {
+    if constexpr (G::PH_ARRAY) return ph[m];
+    else return m == 0 ? ph[0] : cmul(ph[0], tw[T * m]);
+  };
   // loads are unconditional: an inactive column reads column 0 (base is 0
   // there), transforms it in its own LDS column and stores nothing, so no
   // load waits inside a branch
@@ -245,7 +259,7 @@ __global__ void __launch_bounds__(256) k_strided(PassArgs a) {
     if (a.out1) {
       C w[E];
 #pragma unroll
-      for (int m = 0; m < E; ++m) w[m] = a.use_phase ? cmul(h[m], ph[m]) : h[m];
+      for (int m = 0; m < E; ++m) w[m] = a.use_phase ? cmul(h[m], phase(m)) : h[m];
       fft_pencil<-1, Sh>(w, lp, W, t, lt);
       if (act) {
         C* out = (C*)a.out1 + q * a.out_bs + base;
@@ -267,7 +281,7 @@ __global__ void __launch_bounds__(256) k_strided(PassArgs a) {
     if (a.in1) {
       fft_pencil<+1, Sh>(w, lp, W, t, lt);
 #pragma unroll
-      for (int m = 0; m < E; ++m) h[m] = cadd(h[m], a.use_phase ? cmulc(w[m], ph[m]) : w[m]);
+      for (int m = 0; m < E; ++m) h[m] = cadd(h[m], a.use_phase ? cmulc(w[m], phase(m)) : w[m]);
     }
     if (act) {
       C* out = (C*)a.out + q * a.out_bs + base;
@@ -337,9 +351,18 @@ __global__ void __launch_bounds__(256) k_contig(PassArgs a) {
   C* lp = lds + g * LP;
   LaneTw<C, Sh> lt;
   lt.load(t, tw);
-  C ph[E];
+  // split phases Phi[t + T m] of this lane's entries (Geo::PH_ARRAY)
+  C ph[G::PH_ARRAY ? E : 1];
+  if constexpr (G::PH_ARRAY) {
 #pragma unroll
-  for (int m = 0; m < E; ++m) ph[m] = tw[t + T * m];
+    for (int m = 0; m < E; ++m) ph[m] = tw[t + T * m];
+  } else {
+    ph[0] = tw[t];
+  }
+  auto phase = [&](int m) -> C {
+    if constexpr (G::PH_ARRAY) return ph[m];
+    else return m == 0 ? ph[0] : cmul(ph[0], tw[T * m]);
+  };
   C h[E];
   tile_load<C, L, P, NT>(lds, (const C*)a.in + q * a.in_bs + p0 * L, nh, tid);
   __syncthreads();
@@ -357,7 +380,7 @@ __global__ void __launch_bounds__(256) k_contig(PassArgs a) {
     if (a.out1) {
       C w[E];
 #pragma unroll
-      for (int m = 0; m < E; ++m) w[m] = a.use_phase ? cmul(h[m], ph[m]) : h[m];
+      for (int m = 0; m < E; ++m) w[m] = a.use_phase ? cmul(h[m], phase(m)) : h[m];
       fft_pencil<-1, Sh, G::WS>(w, lp, 1, t, lt);
       store_home<C, L, T, E, P, NT>((C*)a.out1 + q * a.out_bs + p0 * L, lds, w, g, t, nh, tid);
     }
@@ -372,7 +395,7 @@ __global__ void __launch_bounds__(256) k_contig(PassArgs a) {
       __syncthreads();
       fft_pencil<+1, Sh, G::WS>(w, lp, 1, t, lt);
 #pragma unroll
-      for (int m = 0; m < E; ++m) h[m] = cadd(h[m], a.use_phase ? cmulc(w[m], ph[m]) : w[m]);
+      for (int m = 0; m < E; ++m) h[m] = cadd(h[m], a.use_phase ? cmulc(w[m], phase(m)) : w[m]);
     }
     store_home<C, L, T, E, P, NT>((C*)a.out + q * a.out_bs + p0 * L, lds, h, g, t, nh, tid);
   }
