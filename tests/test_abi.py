@@ -56,6 +56,8 @@ def test_argument_validation_without_a_device():
     assert N.lib.sfft_plan_create(ctypes.byref(h), 3, n7, 1, fake, 0, 0, None, 1, 0, None) == N.UNSUPPORTED
     assert b"7" in N.lib.sfft_last_error() or b"14" in N.lib.sfft_last_error()
     assert N.lib.sfft_apply(None, fake, fake, 1, None, 0, None) == N.INVALID_ARG
+    assert N.lib.sfft_plan_update(None, fake, None) == N.INVALID_ARG
+    assert b"null" in N.lib.sfft_last_error()
 
 
 def test_product_path_has_no_oracle_dependency():
