@@ -140,6 +140,24 @@ def test_multi_rhs_and_depth_schedule(sf):
             assert wl.relative_l2(got, want) <= TOL[dtype]
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("grid,b", [((256, 128, 4), 1), ((6, 4, 128), 3), ((8, 256), 3), ((128, 6, 10), 3)])
+def test_long_levels_match_oracle(sf, grid, b, dtype):
+    """Levels of length 128 and 256 in every position: strided passes of those
+    lengths form their split phases from one per-lane value, and leaves of
+    those lengths use the multiply-add butterflies, block product and merge
+    (the code paths shorter lengths do not take); every output against the
+    FP64 oracle, both schedules."""
+    coeffs = wl.green_coeffs(grid, 0.8) if b == 3 and len(grid) == 3 else wl.iid_coeffs(61, grid, b)
+    x = wl.vectors(62, grid, b, 2)
+    want = oracle.embed_matvec(coeffs, x)
+    for sched in ("breadth", "depth"):
+        got = _run(sf, coeffs, x, dtype, "split", sched)
+        err = wl.relative_l2(got, want)
+        _say(f"long levels {grid} b={b} {dtype} {sched} rel_l2={err:.3e}")
+        assert err <= TOL[dtype], (sched, err)
+
+
 @pytest.mark.parametrize("grid,nrhs", [((64, 64, 64), 16), ((64, 24, 10), 401)])
 def test_large_launch_matches_single_rhs_applies(sf, grid, nrhs):
     """b=3, complex64, breadth-first, many right-hand sides: 64^3 with 16 of them
