@@ -16,10 +16,12 @@
 //         out[a] = sum_p conj(Phi)^p .* iFFT_L( sum_c S_p[a, c] .* FFT_L(Phi^p .* in[c]) )
 //         with p over {0, 1} (split) or {0} (embedding baseline).
 //
-// Strided passes (inner > 1) give each lane of a wavefront one pencil so a
-// row k of a tile is one contiguous run in HBM; contiguous passes (inner = 1,
-// the innermost level) stage a tile of whole pencils through LDS so that
-// global loads and stores are linear.
+// Strided passes (inner > 1) take a tile of W consecutive pencils, T lanes
+// per pencil; the W lanes that hold row k of the tile read and write it as
+// one contiguous run in HBM. Contiguous passes (inner = 1, the innermost
+// level) stage a tile of whole pencils through LDS so that global loads and
+// stores are linear. Launches of many workgroups run their tiles in an
+// XCD-contiguous order (PassArgs::xm1, xm2).
 #pragma once
 
 #include <type_traits>
@@ -702,7 +704,8 @@ struct AxisOps {
 
 constexpr int64_t kIdx32 = (int64_t)1 << 31;
 // passes of at least this many workgroups (many per CU) use the
-// XCD-contiguous block order; it helped the large grids only
+// XCD-contiguous block order (1.4% on 256x256x128 passes); smaller launches
+// keep dispatch order (their start latency counts), except narrow tiles
 constexpr int64_t kXcdOrderFrom = 8192;
 
 template <typename Real, int L, int MODE> hipError_t launch_strided(const PassArgs& a, hipStream_t s) {
@@ -718,7 +721,12 @@ template <typename Real, int L, int MODE> hipError_t launch_strided(const PassAr
     b.fd_a = FastDiv::make((uint32_t)ntile);
     b.fd_b = FastDiv::make((uint32_t)a.inner);
   }
-  const int64_t grid = set_block_order(b, blocks, blocks >= kXcdOrderFrom);
+  // tiles narrower than a 128-byte line share lines with their neighbours:
+  // in dispatch order those neighbours run on different XCDs and each XCD
+  // fetches the line (a 1024-point pass moves 32-byte row segments); in
+  // XCD-contiguous order they share one L2 (-20% on a 1024^2 grid)
+  constexpr bool narrow = G::W * (int)sizeof(cx<Real>) < 128;
+  const int64_t grid = set_block_order(b, blocks, blocks >= kXcdOrderFrom || (narrow && blocks >= 16));
   hipLaunchKernelGGL((k_strided<Real, L, MODE>), dim3((unsigned)grid), dim3(G::NT), 0, s, b);
   return hipGetLastError();
 }
