@@ -86,10 +86,11 @@ def stream_copy_gbs(nbytes=1 << 30, reps=20):
 COPY_PROBE_BYTES = 1 << 30
 
 
-def pmc_probe():
+def pmc_probe(workload="green64"):
     """Run under rocprofv3 --pmc: a plain device copy of COPY_PROBE_BYTES (read
-    and written once each) next to ten headline matvecs, so the counters of the
-    leaf kernel can be scaled by those of a copy of known size."""
+    and written once each) next to twelve headline matvecs (or three depth-first
+    applies of the 256x256x128 workload), so the counters of the kernels can be
+    scaled by those of a copy of known size."""
     import torch
     import workloads as wl
     import paper_2406_17981_amd as sf
@@ -98,6 +99,22 @@ def pmc_probe():
     b.copy_(a)
     torch.cuda.synchronize()
     del a, b
+    if workload == "large":
+        import numpy as np
+        cfg = wl.LARGE_256
+        n, nrhs = cfg["n"], cfg["nrhs"]
+        cd = wl.green_coeffs_device(n, cfg["k"])
+        plan = sf.Plan(n, 3, cd, dtype="c64", max_nrhs=nrhs, schedule="depth")
+        del cd
+        torch.cuda.empty_cache()
+        x = torch.from_numpy(wl.vectors(cfg["seed_x"], n, 3, nrhs).astype(np.complex64)).cuda()
+        y = torch.empty_like(x)
+        ws = plan.alloc_workspace(nrhs)
+        for _ in range(3):
+            plan.apply(x, y, ws)
+        torch.cuda.synchronize()
+        log("pmc probe done")
+        return
     coeffs, x_host = wl.green_64(1)
     plan = sf.Plan(wl.GREEN_64["n"], 3, torch.from_numpy(coeffs).cuda(), dtype="c64", method="split")
     x = torch.from_numpy(x_host).to(torch.complex64).cuda()
@@ -143,6 +160,54 @@ def pmc_summarize(fetch_dir, write_dir, out_path):
     rec = dict(kernel="sfft::k_leaf<float, 64, 3, 2, false, 1>", kernel_source_hash=kernel_source_hash(),
                bytes_per_launch=total, detail=out,
                command="rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) -- python3 bench.py --pmc-probe")
+    with open(out_path, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec))
+
+
+# kernels of one depth-first 256x256x128 apply (8 right-hand sides) and their
+# algorithmic bytes per launch: a leaf reads and writes one branch vector
+# (1.61 GB each) and reads the quarter of the 3.22 GB of symbols its branch
+# needs; a pass moves three branch vectors
+LARGE_PMC_KERNELS = {
+    "sfft::k_leaf<float, 128, 3, 2, false, 1>": 2 * 1610612736 + 805306368,
+    "sfft::k_strided<float, 256, 0>": 3 * 1610612736,
+    "sfft::k_strided<float, 256, 1>": 3 * 1610612736,
+}
+
+
+def pmc_summarize_large(fetch_dir, write_dir, out_path):
+    """Per-dispatch FETCH_SIZE / WRITE_SIZE of the 256x256x128 kernels, scaled by
+    the copy probe's counters, against their algorithmic bytes."""
+    import csv
+    import glob
+
+    def load(d, counter):
+        rows = []
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            rows += [r for r in csv.DictReader(open(f)) if r.get("Counter_Name") == counter]
+        return rows
+
+    res = {}
+    scales = {}
+    for key, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
+        rows = load(d, counter)
+        copy = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
+        scales[key] = COPY_PROBE_BYTES / (max(copy) * 1024.0) if copy else None
+        for name in LARGE_PMC_KERNELS:
+            vals = sorted(float(r["Counter_Value"]) for r in rows if r["Kernel_Name"].startswith("void " + name))
+            if vals and scales[key]:
+                res.setdefault(name, {})[key] = vals[len(vals) // 2] * 1024.0 * scales[key]
+                res[name]["launches"] = len(vals)
+    out = {}
+    for name, alg in LARGE_PMC_KERNELS.items():
+        r = res.get(name, {})
+        if "fetch" in r and "write" in r:
+            out[name] = dict(fetch_bytes=r["fetch"], write_bytes=r["write"], measured_bytes=r["fetch"] + r["write"],
+                             algorithmic_bytes=alg, ratio=(r["fetch"] + r["write"]) / alg, launches=r["launches"])
+    rec = dict(workload="256x256x128, b=3, 8 right-hand sides, c64, split depth-first", scales=scales,
+               kernel_source_hash=kernel_source_hash(), kernels=out,
+               command="rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) -- python3 bench.py --workload large --pmc-probe")
     with open(out_path, "w") as f:
         json.dump(rec, f, indent=1)
     print(json.dumps(rec))
@@ -465,10 +530,10 @@ def main():
         args.warmup = warmup_default
 
     if args.pmc_summarize:
-        pmc_summarize(*args.pmc_summarize)
+        (pmc_summarize_large if args.workload == "large" else pmc_summarize)(*args.pmc_summarize)
         return
     if args.pmc_probe:
-        pmc_probe()
+        pmc_probe(args.workload)
         return
     if args.workload == "large":
         bench_large(args)
