@@ -46,6 +46,19 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def measured_traffic_large(kernel: str):
+    """HBM bytes per launch of a 256x256x128 kernel from the committed rocprofv3
+    PMC summary, or None when absent or taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "large_pmc_traffic.json")
+    try:
+        rec = json.load(open(path))
+    except Exception:
+        return None
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec.get("kernels", {}).get(kernel, {}).get("measured_bytes")
+
+
 def measured_traffic(kernel: str):
     """HBM bytes per launch from a committed rocprofv3 PMC summary, or None when
     absent or taken on kernel sources that have changed since."""
@@ -267,6 +280,9 @@ def bench_large(args):
                     avg_launch_us=round(avg_s * 1e6, 1), launches_per_apply=per_apply,
                     algorithmic_bytes_per_launch=int(alg), achieved_gbs=round(alg / avg_s / 1e9, 1),
                     frac=round(alg / avg_s / 1e9 / HBM_PEAK_GBS, 4))
+                if label == "split_depth" and kname == "green":
+                    out[f"{kname}_{label}"]["leaf"]["traffic"] = measured_traffic_large(
+                        "sfft::k_leaf<float, 128, 3, 2, false, 1>")
             log(f"[large {kname} {label}] {ms:.3f} ms per apply of {nrhs} RHS")
             if kname == "green" and label == "split_depth":
                 y_c64 = y.clone()
