@@ -149,8 +149,13 @@ template <typename Real, int L> struct Geo {
   // LDS rows per (pencil, rhs) lane group: plans with two or more exchanges
   // transform all NPAR*B pencils of a lane in lockstep (one row each); with a
   // single exchange the pencils go one after another through one row, which
-  // keeps LDS per workgroup (and so occupancy) low
-  template <int B, int NPAR> static constexpr int leaf_rows() { return LSh::S >= 3 ? NPAR * B : 1; }
+  // keeps LDS per workgroup (and so occupancy) low. So do leaves of length
+  // 1024 and more, whose six lockstep rows (48 KB per two-wavefront pencil at
+  // complex64) would leave about six wavefronts per CU (-11 to -13% on a
+  // 1024^2 grid with one row)
+  template <int B, int NPAR> static constexpr int leaf_rows() {
+    return (LSh::S >= 3 && L < 1024) ? NPAR * B : 1;
+  }
   // Leaves of length 128 and more run many wavefronts per SIMD and are bound
   // by instruction throughput: they use the multiply-add butterflies, block
   // product and merge (fewer VALU instructions, longer dependence chains);

@@ -141,13 +141,15 @@ def test_multi_rhs_and_depth_schedule(sf):
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-@pytest.mark.parametrize("grid,b", [((256, 128, 4), 1), ((6, 4, 128), 3), ((8, 256), 3), ((128, 6, 10), 3)])
+@pytest.mark.parametrize("grid,b", [((256, 128, 4), 1), ((6, 4, 128), 3), ((8, 256), 3), ((128, 6, 10), 3),
+                                    ((6, 1024), 3), ((1024, 10), 1)])
 def test_long_levels_match_oracle(sf, grid, b, dtype):
-    """Levels of length 128 and 256 in every position: strided passes of those
-    lengths form their split phases from one per-lane value, and leaves of
-    those lengths use the multiply-add butterflies, block product and merge
-    (the code paths shorter lengths do not take); every output against the
-    FP64 oracle, both schedules."""
+    """Levels of length 128 and more in every position: strided passes of those
+    lengths form their split phases from one per-lane value, leaves of those
+    lengths use the multiply-add butterflies, block product and merge, and
+    leaves of length 1024 transform their pencils one after another through
+    one LDS row (the code paths shorter lengths do not take); every output
+    against the FP64 oracle, both schedules."""
     coeffs = wl.green_coeffs(grid, 0.8) if b == 3 and len(grid) == 3 else wl.iid_coeffs(61, grid, b)
     x = wl.vectors(62, grid, b, 2)
     want = oracle.embed_matvec(coeffs, x)
