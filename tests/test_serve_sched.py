@@ -118,3 +118,95 @@ def test_poisson_stream_statistics():
     d2 = sum(1 for r in reqs if len(r.n) == 2)
     assert 0.45 < d2 / len(reqs) < 0.55
     assert all(0.5 <= r.k <= 1.5 for r in reqs)
+
+
+class PoolingExecutor(MockExecutor):
+    """Keeps released requests' memory as an idle pool per grid (as the GPU
+    executor keeps plans) and checks that admissions never exceed the budget
+    with the pool counted."""
+
+    def __init__(self, clock, server_ref, sizes, pool_bytes):
+        super().__init__(clock, server_ref, sizes)
+        self.pool_bytes = pool_bytes
+        self.idle = {}          # grid -> count of idle entries
+        self.trims = 0
+        self.reuses = 0
+
+    def idle_bytes(self, req=None):
+        total = sum(self.idle.values()) * self.pool_bytes
+        if req is not None and self.idle.get(req.n):
+            total -= self.pool_bytes
+        return total
+
+    def trim(self, req=None):
+        self.trims += 1
+        keep = req.n if req is not None else None
+        self.idle = {k: (1 if k == keep and v else 0) for k, v in self.idle.items()}
+
+    def admit(self, req):
+        srv = self.server_ref[0]
+        assert srv.reserved + self.idle_bytes(req) <= srv.budget
+        if self.idle.get(req.n):
+            self.idle[req.n] -= 1
+            self.reuses += 1
+        return super().admit(req)
+
+    def release(self, slot):
+        self.idle[slot.n] = self.idle.get(slot.n, 0) + 1
+
+
+def test_idle_pool_counts_against_the_budget_and_is_trimmed():
+    # each request holds 10 units while active (plus 5 during admission); a
+    # released one leaves 4 idle units behind for its grid; the budget fits two
+    # active requests and an admission, but not an idle entry of the other grid
+    # besides, so admitting on the other grid must trim
+    reqs = [Request(rid=i, arrival=0.0001 * i, n=(8, 8) if i % 2 else (4, 4, 4), k=1.0, steps=3)
+            for i in range(12)]
+    clock = FakeClock()
+    ref = [None]
+    ex = PoolingExecutor(clock, ref, {(8, 8): 10, (4, 4, 4): 10}, pool_bytes=4)
+    srv = Server(ex, 2 * 10 + 5 + 3, clock=clock, sleep=clock.sleep)
+    ref[0] = srv
+    done = srv.run(reqs)
+    assert sorted(r.rid for r in done) == list(range(12))
+    assert ex.reuses > 0            # later requests took over idle entries
+    assert ex.trims > 0             # and the pool was cut when room was needed
+    assert srv.peak_reserved <= srv.budget
+
+
+class DelayedExecutor(MockExecutor):
+    """Results become ready only after two more calls of finish_ready (as an
+    asynchronous copy that lands later); finish must not be called before."""
+
+    def __init__(self, clock, server_ref, sizes):
+        super().__init__(clock, server_ref, sizes)
+        self.pending = {}
+
+    def finish_start(self, slot):
+        self.pending[slot.rid] = 2
+
+    def finish_ready(self, slot):
+        self.pending[slot.rid] -= 1
+        return self.pending[slot.rid] <= 0
+
+    def finish_wait(self, slot):
+        self.pending[slot.rid] = 0
+
+    def finish(self, slot):
+        assert self.pending.pop(slot.rid) <= 0
+        return super().finish(slot)
+
+
+def test_asynchronous_completion_keeps_slots_and_memory_until_ready():
+    reqs = [Request(rid=i, arrival=0.0, n=(4, 4), k=1.0, steps=2 + i) for i in range(5)]
+    clock = FakeClock()
+    ref = [None]
+    ex = DelayedExecutor(clock, ref, {(4, 4): 10})
+    srv = Server(ex, 2 * 10 + 5, max_active=2, clock=clock, sleep=clock.sleep)
+    ref[0] = srv
+    done = srv.run(reqs)
+    assert sorted(r.rid for r in done) == list(range(5))
+    assert not ex.pending
+    assert max(srv.batch_sizes) <= 2 and srv.peak_reserved <= srv.budget
+    for r in done:
+        assert r.result["steps"] == r.steps
