@@ -155,22 +155,24 @@ class PoolingExecutor(MockExecutor):
         self.idle[slot.n] = self.idle.get(slot.n, 0) + 1
 
 
-def test_idle_pool_counts_against_the_budget_and_is_trimmed():
+@pytest.mark.parametrize("grids,reuse,trim", [([(4, 4, 4)], True, False),
+                                              ([(4, 4, 4), (8, 8), (2, 2, 2, 2)], False, True)])
+def test_idle_pool_counts_against_the_budget_and_is_trimmed(grids, reuse, trim):
     # each request holds 10 units while active (plus 5 during admission); a
     # released one leaves 4 idle units behind for its grid; the budget fits two
-    # active requests and an admission, but not an idle entry of the other grid
-    # besides, so admitting on the other grid must trim
-    reqs = [Request(rid=i, arrival=0.0001 * i, n=(8, 8) if i % 2 else (4, 4, 4), k=1.0, steps=3)
-            for i in range(12)]
+    # active requests and an admission, but not two idle entries of other grids
+    # besides: on one grid every later admission takes over an idle entry, with
+    # three grids in turn admissions must trim the others' entries
+    reqs = [Request(rid=i, arrival=0.0001 * i, n=grids[i % len(grids)], k=1.0, steps=3) for i in range(12)]
     clock = FakeClock()
     ref = [None]
-    ex = PoolingExecutor(clock, ref, {(8, 8): 10, (4, 4, 4): 10}, pool_bytes=4)
+    ex = PoolingExecutor(clock, ref, {g: 10 for g in grids}, pool_bytes=4)
     srv = Server(ex, 2 * 10 + 5 + 3, clock=clock, sleep=clock.sleep)
     ref[0] = srv
     done = srv.run(reqs)
     assert sorted(r.rid for r in done) == list(range(12))
-    assert ex.reuses > 0            # later requests took over idle entries
-    assert ex.trims > 0             # and the pool was cut when room was needed
+    assert (ex.reuses > 0) == reuse
+    assert (ex.trims > 0) == trim
     assert srv.peak_reserved <= srv.budget
 
 
