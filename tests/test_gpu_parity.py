@@ -142,14 +142,16 @@ def test_multi_rhs_and_depth_schedule(sf):
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("grid,b", [((256, 128, 4), 1), ((6, 4, 128), 3), ((8, 256), 3), ((128, 6, 10), 3),
-                                    ((6, 1024), 3), ((1024, 10), 1)])
+                                    ((6, 1024), 3), ((1024, 10), 1), ((512, 40), 3), ((1024, 40), 1)])
 def test_long_levels_match_oracle(sf, grid, b, dtype):
     """Levels of length 128 and more in every position: strided passes of those
     lengths form their split phases from one per-lane value, leaves of those
     lengths use the multiply-add butterflies, block product and merge, and
     leaves of length 1024 transform their pencils one after another through
-    one LDS row (the code paths shorter lengths do not take); every output
-    against the FP64 oracle, both schedules."""
+    one LDS row, and strided passes of length 512 and 1024, whose tiles are
+    narrower than a 128-byte line, run in XCD-contiguous order (512 x 40 and
+    1024 x 40: 45 and 20 tiles, grids rounded up to a multiple of 8); every
+    output against the FP64 oracle, both schedules."""
     coeffs = wl.green_coeffs(grid, 0.8) if b == 3 and len(grid) == 3 else wl.iid_coeffs(61, grid, b)
     x = wl.vectors(62, grid, b, 2)
     want = oracle.embed_matvec(coeffs, x)
