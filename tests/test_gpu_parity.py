@@ -431,8 +431,8 @@ def test_block_symmetry_with_mirrored_storage(sf, dtype):
 # Plan update (new coefficients of the same shape and block symmetry)
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-@pytest.mark.parametrize("mirrored", [False, True])
-def test_plan_update_equals_a_fresh_plan(sf, dtype, mirrored):
+@pytest.mark.parametrize("mirrored,method", [(False, "split"), (True, "split"), (False, "embed")])
+def test_plan_update_equals_a_fresh_plan(sf, dtype, mirrored, method):
     """A plan made for the Green kernel at k=0.7 and updated to k=1.1 gives bit
     for bit what a plan made at k=1.1 gives (the same symbol generation into the
     same layout), and matches the FP64 oracle. Coefficients without the plan's
@@ -442,9 +442,9 @@ def test_plan_update_equals_a_fresh_plan(sf, dtype, mirrored):
     par = wl.green_parity(3) if mirrored else None
     x = wl.vectors(55, grid, 3, 2)
     xd = torch.from_numpy(x.astype(NP[dtype])).cuda()
-    _say(f"plan update n={grid} dtype={dtype} mirrored={mirrored}")
-    plan = sf.Plan(grid, 3, torch.from_numpy(ca).cuda(), dtype=dtype, parity=par, max_nrhs=2)
-    fresh = sf.Plan(grid, 3, torch.from_numpy(cb).cuda(), dtype=dtype, parity=par, max_nrhs=2)
+    _say(f"plan update n={grid} dtype={dtype} mirrored={mirrored} method={method}")
+    plan = sf.Plan(grid, 3, torch.from_numpy(ca).cuda(), dtype=dtype, parity=par, max_nrhs=2, method=method)
+    fresh = sf.Plan(grid, 3, torch.from_numpy(cb).cuda(), dtype=dtype, parity=par, max_nrhs=2, method=method)
     ya = plan.apply(xd)
     plan.update(torch.from_numpy(cb).cuda())
     yb = plan.apply(xd)
