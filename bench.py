@@ -184,8 +184,8 @@ def pmc_summarize(fetch_dir, write_dir, out_path):
 # needs; a pass moves three branch vectors
 LARGE_PMC_KERNELS = {
     "sfft::k_leaf<float, 128, 3, 2, false, 1>": 2 * 1610612736 + 805306368,
-    "sfft::k_strided<float, 256, 0>": 3 * 1610612736,
-    "sfft::k_strided<float, 256, 1>": 3 * 1610612736,
+    "sfft::k_strided<float, 256, 0, 256>": 3 * 1610612736,
+    "sfft::k_strided<float, 256, 1, 256>": 3 * 1610612736,
 }
 
 

@@ -17,8 +17,9 @@
 //         with p over {0, 1} (split) or {0} (embedding baseline).
 //
 // Strided passes (inner > 1) take a tile of W consecutive pencils, T lanes
-// per pencil; the W lanes that hold row k of the tile read and write it as
-// one contiguous run in HBM. Contiguous passes (inner = 1, the innermost
+// per pencil (W = 256 / T, or 128 / T for launches of few workgroups); the W
+// lanes that hold row k of the tile read and write it as one contiguous run
+// in HBM. Contiguous passes (inner = 1, the innermost
 // level) stage a tile of whole pencils through LDS so that global loads and
 // stores are linear. Launches of many workgroups run their tiles in an
 // XCD-contiguous order (PassArgs::xm1, xm2).
@@ -119,7 +120,7 @@ template <typename Real, int L> struct Geo {
   static constexpr int T = Sh::T;
   static constexpr int E = Sh::E;
   static constexpr int NT = 256;                       // strided / contiguous passes
-  static constexpr int W = NT / T;                     // strided tile width (pencils)
+  static constexpr int W = NT / T;                     // strided tile width (pencils, full size)
   static constexpr int P = NT / T;                     // contiguous tile (pencils)
   static constexpr int LP = L + 1;                     // padded LDS row
   static constexpr bool WS = (64 % T) == 0;    // contiguous pass: pencil inside one wavefront
@@ -192,14 +193,14 @@ template <> struct PairOf<float2> { using type = float4; };
 template <> struct PairOf<double2> { using type = double4; };
 
 // ---------------------------------------------------------------------------
-// Strided axis: tile of L rows x W pencils, lane (c, t) = (tid % W, tid / W).
+// Strided axis: tile of L rows x W = NT / T pencils, lane (c, t) = (tid % W, tid / W).
 // ---------------------------------------------------------------------------
-template <typename Real, int L, int MODE>
-__global__ void __launch_bounds__(256) k_strided(PassArgs a) {
+template <typename Real, int L, int MODE, int NT>
+__global__ void __launch_bounds__(NT) k_strided(PassArgs a) {
   using C = cx<Real>;
   using G = Geo<Real, L>;
   using Sh = typename G::Sh;
-  constexpr int T = G::T, E = G::E, W = G::W;
+  constexpr int T = G::T, E = G::E, W = NT / T;
   __shared__ C lds[L * W];
   const int tid = threadIdx.x;
   const int c = tid % W, t = tid / W;
@@ -713,15 +714,15 @@ constexpr int64_t kIdx32 = (int64_t)1 << 31;
 // keep dispatch order (their start latency counts), except narrow tiles
 constexpr int64_t kXcdOrderFrom = 8192;
 
-template <typename Real, int L, int MODE> hipError_t launch_strided(const PassArgs& a, hipStream_t s) {
-  using G = Geo<Real, L>;
+template <typename Real, int L, int MODE, int NT> hipError_t launch_strided_nt(const PassArgs& a, hipStream_t s) {
+  constexpr int W = NT / Geo<Real, L>::T;
   const int64_t cols = a.outer * a.inner;
-  const int64_t ntile = (cols + G::W - 1) / G::W;
+  const int64_t ntile = (cols + W - 1) / W;
   const int64_t blocks = a.nq * ntile;
   if (blocks <= 0) return hipSuccess;
   if (blocks >= kIdx32) return hipErrorInvalidConfiguration;  // beyond the 1-D grid
   PassArgs b = a;
-  b.idx32 = blocks < kIdx32 && ntile * G::W < kIdx32;
+  b.idx32 = blocks < kIdx32 && ntile * W < kIdx32;
   if (b.idx32) {
     b.fd_a = FastDiv::make((uint32_t)ntile);
     b.fd_b = FastDiv::make((uint32_t)a.inner);
@@ -730,10 +731,26 @@ template <typename Real, int L, int MODE> hipError_t launch_strided(const PassAr
   // in dispatch order those neighbours run on different XCDs and each XCD
   // fetches the line (a 1024-point pass moves 32-byte row segments); in
   // XCD-contiguous order they share one L2 (-20% on a 1024^2 grid)
-  constexpr bool narrow = G::W * (int)sizeof(cx<Real>) < 128;
+  constexpr bool narrow = W * (int)sizeof(cx<Real>) < 128;
   const int64_t grid = set_block_order(b, blocks, blocks >= kXcdOrderFrom || (narrow && blocks >= 16));
-  hipLaunchKernelGGL((k_strided<Real, L, MODE>), dim3((unsigned)grid), dim3(G::NT), 0, s, b);
+  hipLaunchKernelGGL((k_strided<Real, L, MODE, NT>), dim3((unsigned)grid), dim3(NT), 0, s, b);
   return hipGetLastError();
+}
+
+// Launches of few workgroups use half-size ones (tiles still whole 128-byte
+// lines) when the lengths allow: 384 workgroups of four wavefronts leave half
+// of the CUs with twice the work of the others, 768 of two spread evenly.
+constexpr int64_t kHalfTilesBelow = 2048;
+
+template <typename Real, int L, int MODE> hipError_t launch_strided(const PassArgs& a, hipStream_t s) {
+  using G = Geo<Real, L>;
+  constexpr bool half_ok = (G::W / 2) * (int)sizeof(cx<Real>) >= 128;
+  if constexpr (half_ok) {
+    const int64_t cols = a.outer * a.inner;
+    const int64_t blocks = a.nq * ((cols + G::W - 1) / G::W);
+    if (blocks < kHalfTilesBelow) return launch_strided_nt<Real, L, MODE, G::NT / 2>(a, s);
+  }
+  return launch_strided_nt<Real, L, MODE, G::NT>(a, s);
 }
 
 template <typename Real, int L, int MODE> hipError_t launch_contig(const PassArgs& a, hipStream_t s) {
