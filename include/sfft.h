@@ -174,10 +174,13 @@ sfft_status sfft_plan_info(sfft_plan plan, sfft_info* info);
 /* One step of independent Arnoldi processes (Krylov chains of matvecs, the
  * iterative-solver setting of the paper's introduction). For every job the
  * new vector w (typically T v_{m-1}) is orthogonalised against the basis
- * v_0..v_{m-1} by classical Gram-Schmidt applied twice, then normalised:
- *     hcol[i] = <v_i, w> (both passes summed), hcol[m] = ||w||, vout = w/||w||.
+ * v_0..v_{m-1} (assumed orthonormal) by classical Gram-Schmidt, with a second
+ * pass when the first leaves less than half of ||w||^2 (the Kahan-Parlett
+ * "twice is enough" test), then normalised:
+ *     hcol[i] = <v_i, w> (passes summed), hcol[m] = ||w||, vout = w/||w||.
  * m = 0 only normalises (the start vector). Reductions accumulate in FP64 in
- * a fixed order, so results are bitwise independent of the other jobs.
+ * a fixed order and the test uses only the job's own sums, so results are
+ * bitwise independent of the other jobs.
  * All pointers are device pointers; vectors are of `dtype` (one dtype per
  * call); hcol is complex128. scratch: sfft_arnoldi_scratch_size bytes. */
 typedef struct {

@@ -3,11 +3,15 @@
 //
 // One call advances any number of independent Arnoldi processes by one step:
 // each job's new vector w = T v_j is orthogonalised against its basis
-// v_0..v_{m-1} by classical Gram-Schmidt applied twice (CGS2), normalised,
-// and written as v_m; the projections and the norm form column j of the
-// Hessenberg matrix. All reductions accumulate in FP64 in a fixed order
-// (per-block partial sums, then one ordered pass), so a job's results do not
-// depend on which other jobs share the call.
+// v_0..v_{m-1} by classical Gram-Schmidt, normalised, and written as v_m; the
+// projections and the norm form column j of the Hessenberg matrix. A second
+// Gram-Schmidt pass runs only for a job whose first pass removed more than
+// half of ||w||^2 (the Kahan-Parlett "twice is enough" test with
+// alpha = 1/sqrt(2)): otherwise one projection against an orthonormal basis
+// already leaves w orthogonal to working precision. All reductions
+// accumulate in FP64 in a fixed order (per-block partial sums, then one
+// ordered pass), and the test uses only the job's own sums, so a job's
+// results do not depend on which other jobs share the call.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -19,7 +23,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
-// Work per thread (measured on one MI355X; one CGS2 step of a 3 x 128^3
+// Work per thread (measured on one MI355X; one two-pass step of a 3 x 128^3
 // complex64 chain with 30 basis vectors): 4 entries and one basis vector per
 // sweep keep the streaming kernels small (about 70 VGPRs) and took 1.44 ms,
 // against 1.59 ms (2 vectors), 2.07 ms (4 vectors) and 3.31 ms (4 vectors of
@@ -28,6 +32,8 @@ constexpr int kPer = 4;                 // entries per thread of a chunk
 constexpr int kChunk = kBlock * kPer;   // entries per partial-sum block
 constexpr int kGroup = 1;               // basis vectors per sweep over a chunk
 constexpr int kMaxM = 64;               // basis vectors per job
+// second pass when ||w_1||^2 < kReorth2 ||w||^2 (w_1: w after one pass)
+constexpr double kReorth2 = 0.5;
 constexpr int kJobsPerLaunch = 24;
 
 struct Job {
@@ -38,8 +44,8 @@ struct Job {
   void* vout;
   int64_t n;
   double2* hcol;     // m+1 entries
-  double2* part;     // partial sums: nchunk x (m or 1)
-  double2* h;        // this pass's projections (m)
+  double2* part;     // partial sums: nchunk x (m + 1), column m for norms
+  double2* h;        // m + 2: this pass's projections, ||w||^2, ||w_1||^2
   int64_t chunk0;    // first block of this job in the launch
   int64_t nchunk;
 };
@@ -56,6 +62,9 @@ __device__ __forceinline__ int find_job(const JobTable& t, int64_t blk) {
 }
 
 template <typename C> __device__ __forceinline__ double2 to_d(C a) { return make_double2((double)a.x, (double)a.y); }
+
+// The job takes the second Gram-Schmidt pass (set once the first is done).
+__device__ __forceinline__ bool reorth(const Job& J) { return J.h[J.m + 1].x < kReorth2 * J.h[J.m].x; }
 
 // Sum over the 64 lanes of a wavefront by a fixed butterfly of shuffles, so
 // every lane gets the same, order-fixed result.
@@ -84,14 +93,17 @@ __device__ __forceinline__ double2 block_sum(double2 v, double2* red) {
   return s;
 }
 
-// partial[chunk][i] = sum_{k in chunk} conj(V_i[k]) w[k]. A sweep takes kGroup
-// basis vectors at once (their loads in flight together); each thread's sums
-// run over its entries in order, then wavefront butterflies and the wavefront
-// sums in order, so a partial depends only on its job's data.
+// partial[chunk][i] = sum_{k in chunk} conj(V_i[k]) w[k], and on the first
+// pass partial[chunk][m] = sum |w[k]|^2. A sweep takes kGroup basis vectors
+// at once (their loads in flight together); each thread's sums run over its
+// entries in order, then wavefront butterflies and the wavefront sums in
+// order, so a partial depends only on its job's data. On the second pass a
+// job that needs none exits (the whole block).
 template <typename C>
-__global__ void __launch_bounds__(kBlock) k_dots(JobTable t) {
+__global__ void __launch_bounds__(kBlock) k_dots(JobTable t, int pass) {
   const int jb = find_job(t, blockIdx.x);
   const Job& J = t.j[jb];
+  if (pass == 1 && !reorth(J)) return;
   const int64_t chunk = blockIdx.x - J.chunk0;
   const int64_t kb = chunk * kChunk + threadIdx.x;
   const C* V = (const C*)J.V;
@@ -132,43 +144,64 @@ __global__ void __launch_bounds__(kBlock) k_dots(JobTable t) {
         s.x += red[q][threadIdx.x].x;
         s.y += red[q][threadIdx.x].y;
       }
-      J.part[chunk * J.m + i0 + threadIdx.x] = s;
+      J.part[chunk * (J.m + 1) + i0 + threadIdx.x] = s;
     }
     __syncthreads();
+  }
+  if (pass == 0) {
+    double sq = 0.0;
+#pragma unroll
+    for (int s = 0; s < kPer; ++s) {
+      const double2 y = to_d(wv[s]);
+      sq += y.x * y.x + y.y * y.y;
+    }
+    const double2 v = wave_sum(make_double2(sq, 0.0));
+    if ((threadIdx.x & 63) == 0) red[wave][0] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double2 s = make_double2(0.0, 0.0);
+      for (int q = 0; q < kWaves; ++q) s.x += red[q][0].x;
+      J.part[chunk * (J.m + 1) + J.m] = s;
+    }
   }
 }
 
 // One block per (job, i): h[i] = sum over the job's chunks (each thread sums
 // the chunks c = tid, tid + kBlock, ... in order, then block_sum);
-// hcol[i] = h[i] (first pass) or += h[i]
-__global__ void __launch_bounds__(kBlock) k_dots_final(JobTable t, int accumulate) {
+// hcol[i] = h[i] (first pass) or += h[i] (second); on the first pass block
+// i = m sums the norm partials into h[m] = ||w||^2
+__global__ void __launch_bounds__(kBlock) k_dots_final(JobTable t, int pass) {
   const Job& J = t.j[blockIdx.x];
   const int64_t i = blockIdx.y;
-  if (i >= J.m) return;  // whole block
+  if (i > J.m || (pass == 1 && (i == J.m || !reorth(J)))) return;  // whole block
   __shared__ double2 red[kWaves];
   double2 v = make_double2(0.0, 0.0);
   for (int64_t c = threadIdx.x; c < J.nchunk; c += kBlock) {
-    v.x += J.part[c * J.m + i].x;
-    v.y += J.part[c * J.m + i].y;
+    v.x += J.part[c * (J.m + 1) + i].x;
+    v.y += J.part[c * (J.m + 1) + i].y;
   }
   const double2 s = block_sum(v, red);
   if (threadIdx.x == 0) {
     J.h[i] = s;
-    if (accumulate) {
-      J.hcol[i].x += s.x;
-      J.hcol[i].y += s.y;
-    } else {
-      J.hcol[i] = s;
+    if (i < J.m) {
+      if (pass == 1) {
+        J.hcol[i].x += s.x;
+        J.hcol[i].y += s.y;
+      } else {
+        J.hcol[i] = s;
+      }
     }
   }
 }
 
 // w[k] -= sum_i V_i[k] h[i]: a thread keeps its kPer entries in FP64 and
-// takes the basis vectors kGroup at a time (their loads in flight together)
+// takes the basis vectors kGroup at a time (their loads in flight together);
+// on the first pass partial[chunk][m] = sum |w_1[k]|^2 of the stored result
 template <typename C>
-__global__ void __launch_bounds__(kBlock) k_update(JobTable t) {
+__global__ void __launch_bounds__(kBlock) k_update(JobTable t, int pass) {
   const int jb = find_job(t, blockIdx.x);
   const Job& J = t.j[jb];
+  if (pass == 1 && !reorth(J)) return;
   const int64_t kb = (blockIdx.x - J.chunk0) * kChunk + threadIdx.x;
   const C* V = (const C*)J.V;
   C* w = (C*)J.w;
@@ -202,14 +235,33 @@ __global__ void __launch_bounds__(kBlock) k_update(JobTable t) {
       }
     }
   }
+  double sq = 0.0;
 #pragma unroll
   for (int s = 0; s < kPer; ++s) {
     const int64_t k = kb + (int64_t)s * kBlock;
-    if (k < J.n) {
-      w[k].x = (decltype(C::x))acc[s].x;
-      w[k].y = (decltype(C::x))acc[s].y;
-    }
+    C r;
+    r.x = (decltype(C::x))acc[s].x;
+    r.y = (decltype(C::x))acc[s].y;
+    if (k < J.n) w[k] = r;
+    const double2 y = to_d(r);  // 0 past the end
+    sq += y.x * y.x + y.y * y.y;
   }
+  if (pass == 0) {
+    __shared__ double2 red[kWaves];
+    const double2 tot = block_sum(make_double2(sq, 0.0), red);
+    if (threadIdx.x == 0) J.part[(blockIdx.x - J.chunk0) * (J.m + 1) + J.m] = tot;
+  }
+}
+
+// One block per job: h[m+1] = ||w_1||^2, the first pass's norm partials
+// summed in order
+__global__ void __launch_bounds__(kBlock) k_crit(JobTable t) {
+  const Job& J = t.j[blockIdx.x];
+  __shared__ double2 red[kWaves];
+  double2 v = make_double2(0.0, 0.0);
+  for (int64_t c = threadIdx.x; c < J.nchunk; c += kBlock) v.x += J.part[c * (J.m + 1) + J.m].x;
+  const double2 s = block_sum(v, red);
+  if (threadIdx.x == 0) J.h[J.m + 1] = s;
 }
 
 // partial[chunk] = sum_{k in chunk} |w[k]|^2
@@ -274,9 +326,9 @@ __global__ void __launch_bounds__(kBlock) k_scale(JobTable t) {
 int64_t nchunks(int64_t n) { return (n + kChunk - 1) / kChunk; }
 
 size_t job_scratch(const sfft_arnoldi_job& j) {
-  // partial sums (nchunk x max(m, 1)) + projections (max(m, 1)), in double2
-  const int64_t m = j.m > 0 ? j.m : 1;
-  return sfft_rt_align256((size_t)(nchunks(j.n) * m + m) * sizeof(double2));
+  // partial sums (nchunk x (m + 1)) + projections and the two squared norms
+  // (m + 2), in double2
+  return sfft_rt_align256((size_t)(nchunks(j.n) * (j.m + 1) + j.m + 2) * sizeof(double2));
 }
 
 template <typename C> hipError_t run(std::vector<JobTable>& tabs, hipStream_t st) {
@@ -287,11 +339,12 @@ template <typename C> hipError_t run(std::vector<JobTable>& tabs, hipStream_t st
       bool any = false;
       for (int k = 0; k < t.njobs; ++k) any |= t.j[k].m > 0;
       if (!any) continue;
-      hipLaunchKernelGGL(k_dots<C>, dim3((unsigned)blocks), dim3(kBlock), 0, st, t);
+      hipLaunchKernelGGL(k_dots<C>, dim3((unsigned)blocks), dim3(kBlock), 0, st, t, pass);
       int64_t mmax = 1;
       for (int k = 0; k < t.njobs; ++k) mmax = t.j[k].m > mmax ? t.j[k].m : mmax;
-      hipLaunchKernelGGL(k_dots_final, dim3(t.njobs, (unsigned)mmax), dim3(kBlock), 0, st, t, pass);
-      hipLaunchKernelGGL(k_update<C>, dim3((unsigned)blocks), dim3(kBlock), 0, st, t);
+      hipLaunchKernelGGL(k_dots_final, dim3(t.njobs, (unsigned)(mmax + 1)), dim3(kBlock), 0, st, t, pass);
+      hipLaunchKernelGGL(k_update<C>, dim3((unsigned)blocks), dim3(kBlock), 0, st, t, pass);
+      if (pass == 0) hipLaunchKernelGGL(k_crit, dim3(t.njobs), dim3(kBlock), 0, st, t);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
   }
@@ -348,9 +401,8 @@ sfft_status sfft_arnoldi_step_multi(int njobs, const sfft_arnoldi_job* jobs, int
     J.hcol = (double2*)q.hcol;
     J.nchunk = nchunks(q.n);
     J.chunk0 = t.njobs == 0 ? 0 : t.j[t.njobs - 1].chunk0 + t.j[t.njobs - 1].nchunk;
-    const int64_t m = q.m > 0 ? q.m : 1;
     J.part = (double2*)sp;
-    J.h = J.part + J.nchunk * m;
+    J.h = J.part + J.nchunk * (q.m + 1);
     sp += job_scratch(q);
     ++t.njobs;
   }
