@@ -69,3 +69,34 @@ def test_product_path_has_no_oracle_dependency():
                 txt = open(os.path.join(dirpath, f)).read()
                 assert not re.search(r"^\s*(import|from)\s+oracle", txt, re.M), f
                 assert "oracle/" not in txt, f
+
+
+def test_arnoldi_scratch_and_validation_without_a_device():
+    """Scratch sizes and argument checks of the batched Arnoldi step are host
+    logic: per job, one FP64 complex partial per 1024-entry chunk and basis
+    vector plus one for the norms, and m + 2 more, rounded up to 256 bytes."""
+    from paper_2406_17981_amd import _native as N
+    b = ctypes.c_size_t(123)
+    assert N.lib.sfft_arnoldi_scratch_size(0, None, ctypes.byref(b)) == N.OK and b.value == 0
+    jobs = (N.ArnoldiJob * 2)()
+    for j, (n, m) in zip(jobs, ((5000, 7), (3000, 0))):
+        j.V, j.ldv, j.m, j.n = 0x1000, n, m, n
+        j.w, j.vout, j.hcol = 0x2000, 0x3000, 0x4000
+    assert N.lib.sfft_arnoldi_scratch_size(2, jobs, ctypes.byref(b)) == N.OK
+
+    def per_job(n, m):
+        raw = (-(-n // 1024) * (m + 1) + m + 2) * 16
+        return -(-raw // 256) * 256
+    assert b.value == per_job(5000, 7) + per_job(3000, 0)
+    need = b.value
+    fake = ctypes.c_void_p(0x5000)
+    assert N.lib.sfft_arnoldi_step_multi(2, jobs, 9, fake, need, None) == N.INVALID_ARG       # dtype
+    assert N.lib.sfft_arnoldi_step_multi(2, jobs, N.C64, fake, need - 1, None) == N.INVALID_ARG
+    assert b"scratch" in N.lib.sfft_last_error()
+    jobs[0].m = 65                                                                              # > 64
+    assert N.lib.sfft_arnoldi_scratch_size(2, jobs, ctypes.byref(b)) == N.OK
+    assert N.lib.sfft_arnoldi_step_multi(2, jobs, N.C64, fake, b.value, None) == N.INVALID_ARG
+    jobs[0].m, jobs[0].ldv = 7, 4999                                                            # ldv < n
+    assert N.lib.sfft_arnoldi_step_multi(2, jobs, N.C64, fake, need, None) == N.INVALID_ARG
+    assert b"Arnoldi job" in N.lib.sfft_last_error()
+    assert N.lib.sfft_arnoldi_step_multi(0, None, N.C64, None, 0, None) == N.OK               # empty step
