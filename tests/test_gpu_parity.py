@@ -168,7 +168,10 @@ def test_large_launch_matches_single_rhs_applies(sf, grid, nrhs):
     runs level-2 passes of 12288 workgroups, 64 x 24 x 10 with 401 passes of 9023
     and 24060 (not multiples of 8: the grids are rounded up and 1 and 4 work items
     are past the end); all use the XCD-contiguous block order, and the leaf takes several
-    right-hand sides per symbol fetch. Neither changes any entry's arithmetic, so
+    right-hand sides per symbol fetch; the single-RHS applies' passes are small
+    launches of 128-lane workgroups (16-pencil tiles at length 64) where the
+    many-RHS passes take 256 lanes (32 pencils). None of this changes any entry's
+    arithmetic, so
     every right-hand side must equal its own single-RHS apply (dispatch order, one
     right-hand side per leaf lane group) bit for bit: a tile skipped or done twice
     would not. The first right-hand side is also checked against the FP64 oracle."""
