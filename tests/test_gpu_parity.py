@@ -434,18 +434,22 @@ def test_block_symmetry_with_mirrored_storage(sf, dtype):
 # Plan update (new coefficients of the same shape and block symmetry)
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-@pytest.mark.parametrize("mirrored,method", [(False, "split"), (True, "split"), (False, "embed")])
-def test_plan_update_equals_a_fresh_plan(sf, dtype, mirrored, method):
-    """A plan made for the Green kernel at k=0.7 and updated to k=1.1 gives bit
-    for bit what a plan made at k=1.1 gives (the same symbol generation into the
-    same layout), and matches the FP64 oracle. Coefficients without the plan's
-    block symmetry (i.i.d. blocks) are refused, and the plan keeps its symbols."""
+@pytest.mark.parametrize("kind,mirrored,method", [("green", False, "split"), ("green", True, "split"),
+                                                  ("green", False, "embed"), ("skew", False, "split"),
+                                                  ("skew", True, "split")])
+def test_plan_update_equals_a_fresh_plan(sf, dtype, kind, mirrored, method):
+    """A plan made for the Green (block-symmetric) or skew (block
+    antisymmetric) kernel at k=0.7 and updated to k=1.1 gives bit for bit what
+    a plan made at k=1.1 gives (the same symbol generation into the same
+    layout), and matches the FP64 oracle. Coefficients without the plan's block
+    symmetry (i.i.d. blocks) are refused, and the plan keeps its symbols."""
     grid = (16, 12, 10)
-    ca, cb = wl.green_coeffs(grid, 0.7), wl.green_coeffs(grid, 1.1)
-    par = wl.green_parity(3) if mirrored else None
+    make = wl.green_coeffs if kind == "green" else wl.skew_coeffs
+    ca, cb = make(grid, 0.7), make(grid, 1.1)
+    par = (wl.green_parity(3) if kind == "green" else wl.skew_parity(3)) if mirrored else None
     x = wl.vectors(55, grid, 3, 2)
     xd = torch.from_numpy(x.astype(NP[dtype])).cuda()
-    _say(f"plan update n={grid} dtype={dtype} mirrored={mirrored} method={method}")
+    _say(f"plan update n={grid} dtype={dtype} kind={kind} mirrored={mirrored} method={method}")
     plan = sf.Plan(grid, 3, torch.from_numpy(ca).cuda(), dtype=dtype, parity=par, max_nrhs=2, method=method)
     fresh = sf.Plan(grid, 3, torch.from_numpy(cb).cuda(), dtype=dtype, parity=par, max_nrhs=2, method=method)
     ya = plan.apply(xd)
@@ -458,7 +462,7 @@ def test_plan_update_equals_a_fresh_plan(sf, dtype, mirrored, method):
     with pytest.raises(sf.SfftError):
         plan.update(torch.from_numpy(wl.iid_coeffs(3, grid, 3)).cuda())
     assert torch.equal(plan.apply(xd), yb)
-    assert plan.info()["block_symmetry"] == 1
+    assert plan.info()["block_symmetry"] == (1 if kind == "green" else 2)
     torch.cuda.synchronize()
     plan.close()
     fresh.close()
