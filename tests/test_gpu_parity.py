@@ -321,6 +321,31 @@ def test_large_green_and_skew_full_size(sf, large_points):
         del coeffs
 
 
+@pytest.mark.parametrize("mirrored", [False, True])
+def test_serving_grid_1024_squared(sf, mirrored):
+    """The largest two-level grid of the serving stream: 1024 x 1024, 3x3 Green
+    blocks, complex64, depth-first as the server runs it. Length-1024 passes
+    have 4-pencil tiles (XCD-contiguous order), the length-1024 leaf runs its
+    pencils one after another through one LDS row, and the symbols come from
+    2048-point FP64 transforms; checked against direct sums at sampled output
+    points and the grid's corners."""
+    n = (1024, 1024)
+    coeffs = wl.green_coeffs(n, 0.9)
+    x = wl.vectors(61, n, 3, 1)
+    rng = np.random.default_rng(62)
+    pts = np.concatenate([np.stack([rng.integers(0, v, 12) for v in n], axis=1),
+                          np.array([[0, 0], [n[0] - 1, n[1] - 1], [0, n[1] - 1], [n[0] // 2, 0]])])
+    want = oracle.sampled_rows(coeffs, x, pts)
+    _say(f"serving grid n={n} mirrored={mirrored}")
+    plan = sf.Plan(n, 3, torch.from_numpy(coeffs).cuda(), dtype="c64",
+                   parity=wl.green_parity(2) if mirrored else None, max_nrhs=1, schedule="depth")
+    y = plan.apply(torch.from_numpy(x.astype(np.complex64)).cuda())
+    idx = torch.from_numpy(np.ravel_multi_index(pts.T, n)).cuda()
+    got = y.reshape(1, 3, -1)[:, :, idx].cpu().numpy().astype(np.complex128)
+    plan.close()
+    assert wl.relative_l2(got, want) <= TOL["c64"]
+
+
 # ---------------------------------------------------------------------------
 # Degenerate and empty inputs
 # ---------------------------------------------------------------------------
