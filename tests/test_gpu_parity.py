@@ -322,27 +322,31 @@ def test_large_green_and_skew_full_size(sf, large_points):
 
 
 @pytest.mark.parametrize("mirrored", [False, True])
-def test_serving_grid_1024_squared(sf, mirrored):
-    """The largest two-level grid of the serving stream: 1024 x 1024, 3x3 Green
-    blocks, complex64, depth-first as the server runs it. Length-1024 passes
-    have 4-pencil tiles (XCD-contiguous order), the length-1024 leaf runs its
-    pencils one after another through one LDS row, and the symbols come from
-    2048-point FP64 transforms; checked against direct sums at sampled output
-    points and the grid's corners."""
-    n = (1024, 1024)
+@pytest.mark.parametrize("n", [(1024, 1024), (128, 128, 128)])
+def test_largest_serving_grids(sf, n, mirrored):
+    """The largest grids of the serving stream, 1024 x 1024 and 128^3, 3x3 Green
+    blocks, complex64, depth-first as the server runs them. At 1024^2 the
+    length-1024 passes have 4-pencil tiles (XCD-contiguous order), the
+    length-1024 leaf runs its pencils one after another through one LDS row,
+    and the symbols come from 2048-point FP64 transforms; at 128^3 every level
+    has length 128. Checked against direct sums at sampled output points and
+    the grid's corners."""
+    d = len(n)
     coeffs = wl.green_coeffs(n, 0.9)
     x = wl.vectors(61, n, 3, 1)
     rng = np.random.default_rng(62)
-    pts = np.concatenate([np.stack([rng.integers(0, v, 12) for v in n], axis=1),
-                          np.array([[0, 0], [n[0] - 1, n[1] - 1], [0, n[1] - 1], [n[0] // 2, 0]])])
+    corners = np.array([[0] * d, [v - 1 for v in n], [0] * (d - 1) + [n[-1] - 1], [n[0] // 2] + [0] * (d - 1)])
+    pts = np.concatenate([np.stack([rng.integers(0, v, 12) for v in n], axis=1), corners])
     want = oracle.sampled_rows(coeffs, x, pts)
     _say(f"serving grid n={n} mirrored={mirrored}")
     plan = sf.Plan(n, 3, torch.from_numpy(coeffs).cuda(), dtype="c64",
-                   parity=wl.green_parity(2) if mirrored else None, max_nrhs=1, schedule="depth")
+                   parity=wl.green_parity(d) if mirrored else None, max_nrhs=1, schedule="depth")
     y = plan.apply(torch.from_numpy(x.astype(np.complex64)).cuda())
     idx = torch.from_numpy(np.ravel_multi_index(pts.T, n)).cuda()
     got = y.reshape(1, 3, -1)[:, :, idx].cpu().numpy().astype(np.complex128)
     plan.close()
+    del y
+    torch.cuda.empty_cache()
     assert wl.relative_l2(got, want) <= TOL["c64"]
 
 
