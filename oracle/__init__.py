@@ -14,8 +14,13 @@ Algorithm for Block Toeplitz Matrix-Vector Multiplication") by eye:
 * ``embedded_generator`` / ``embed_matvec``: the standard multilevel circulant
   embedding of the introduction (pad every level to 2n, FFT, diagonal
   multiply, inverse FFT, keep the first n along every level).
-* ``split_alg1``: Algorithm 1 (recursive branch driver) with operation and
-  live-vector counters (Section II.C).
+* ``split_branch_sum``: the split identity of Section II.A on every level as a
+  non-recursive sum over the 2^d parity branches with their symbols T[bId].
+* ``lazy_order`` / ``lazy_costs``: the lazy (depth-first) evaluation order of
+  the branch tree, built from the branch indices, with its work units and
+  live vectors (Section II.C counts, the (d+1) peak).
+* ``embed_matvec_with_symbol``: the embedding product for a symbol transformed
+  beforehand; ``adjoint_coeffs``: the generator of T^H.
 * ``sampled_rows``: direct sums for a few output indices (large grids).
 * ``branch_symbols`` / ``compress_symbols`` / ``expand_symbols``: the per-branch
   Toeplitz data T[bId] and its symmetric storage (Section II.C).

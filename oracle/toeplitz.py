@@ -41,7 +41,8 @@ import scipy.fft
 
 __all__ = [
     "grid_of", "dense_operator", "dense_matvec", "embedded_generator", "embed_symbol",
-    "embed_matvec", "branch_symbols", "phase", "split_alg1", "SplitCounters",
+    "embed_matvec", "embed_matvec_with_symbol", "adjoint_coeffs", "branch_symbols", "phase",
+    "split_branch_sum", "split_branch_sum_with_symbol", "lazy_order", "lazy_costs",
     "sampled_rows", "compress_symbol", "expand_symbol", "c_embed", "c_split",
     "c_split_closed", "ratio_c", "ratio_c_asymptotic", "ratio_m", "ratio_m_sym",
     "mem_embed", "mem_split", "branch_index",
@@ -142,11 +143,17 @@ def embed_matvec(coeffs: np.ndarray, x: np.ndarray) -> np.ndarray:
     the b x b blocks of the embedded symbol, inverse transform, keep the first
     n entries along every level (the projection).
     """
-    n = grid_of(coeffs)
-    b = coeffs.shape[0]
+    return embed_matvec_with_symbol(embed_symbol(coeffs), x)
+
+
+def embed_matvec_with_symbol(C: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """embed_matvec for an embedded symbol C = embed_symbol(coeffs) computed
+    beforehand (shape (b, b, 2n_1, ..., 2n_d)), so repeated products with one
+    operator transform the generator once."""
+    b = C.shape[0]
+    n = tuple(v // 2 for v in C.shape[2:])
     x = _as_vectors(x, b, n)
     d = len(n)
-    C = embed_symbol(coeffs)
     xp = np.zeros(x.shape[:2] + tuple(2 * v for v in n), dtype=np.complex128)
     xp[(slice(None), slice(None)) + tuple(slice(0, v) for v in n)] = x
     axes = tuple(range(2, 2 + d))
@@ -154,6 +161,15 @@ def embed_matvec(coeffs: np.ndarray, x: np.ndarray) -> np.ndarray:
     Y = np.einsum("ac...,rc...->ra...", C, X)
     y = scipy.fft.ifftn(Y, axes=axes, workers=_WORKERS)
     return y[(slice(None), slice(None)) + tuple(slice(0, v) for v in n)].copy()
+
+
+def adjoint_coeffs(coeffs: np.ndarray) -> np.ndarray:
+    """Generator of the conjugate transpose: T^H[(a, i), (c, j)] = conj(T[(c, j), (a, i)])
+    = conj(t(j - i)[c, a]), so t^H(r)[a, c] = conj(t(-r)[c, a]). Reversing
+    every offset axis maps index r_l + n_l - 1 to -r_l + n_l - 1."""
+    d = coeffs.ndim - 2
+    flipped = coeffs[(slice(None), slice(None)) + (slice(None, None, -1),) * d]
+    return np.conj(np.swapaxes(flipped, 0, 1)).copy()
 
 
 # ---------------------------------------------------------------------------
@@ -191,99 +207,128 @@ def phase(nl: int) -> np.ndarray:
     return np.exp(-1j * np.pi * np.arange(nl) / nl)
 
 
-class SplitCounters:
-    """Operation and live-vector counts of one Algorithm 1 run (Section II.C units).
-
-    fft: sum over FFT calls of (entries transformed) * log2(n_l);
-    phase: entries multiplied in sptBrn and mrgBrn;
-    mult: scalar products in mulBrn (b^2 per grid point per vector);
-    live / peak: vectors of s*b*nrhs entries alive now / at most.
-    """
-
-    def __init__(self):
-        self.fft = 0.0
-        self.phase = 0
-        self.mult = 0
-        self.fft_calls: Dict[int, int] = {}
-        self.live = 0
-        self.peak = 0
-
-    def alloc(self):
-        self.live += 1
-        self.peak = max(self.peak, self.live)
-
-    def free(self):
-        self.live -= 1
-
-    @property
-    def total(self):
-        return self.fft + self.phase + self.mult
-
-
 def _along(arr: np.ndarray, vec: np.ndarray, axis: int) -> np.ndarray:
     shape = [1] * arr.ndim
     shape[axis] = vec.shape[0]
     return arr * vec.reshape(shape)
 
 
-def split_alg1(coeffs: np.ndarray, x: np.ndarray, counters: SplitCounters | None = None
-               ) -> np.ndarray:
-    """y = T x by Algorithm 1 (lazy embedding, eager projection), recursively.
+def split_branch_sum(coeffs: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """y = T x as the sum over the 2^d parity branches, without recursion.
 
-    toe_mul_brn(level, p, v) follows the algorithm: a level > 0 transforms v
-    along its own axis; a level below d makes the phase-shifted child along the
-    next axis (sptBrn), evaluates the even branch (same p) and then the odd
-    branch (bit of the next level set: nxtId), and merges the two along the
-    next axis (mrgBrn); the last level multiplies by T[p] (mulBrn); a level > 0
-    finally inverse-transforms along its axis. The even branch is evaluated to
-    completion before the odd child is touched, so at most d + 1 vectors are
-    alive (Section II.C).
+    Section II.A applied to every level at once: the bins 2j + p of the
+    2n-point transform of the zero-padded vector are the n-point transform of
+    Phi^p x (Phi^p = prod over levels of Phi_l^(p_l)), and the first n entries
+    of the 2n-point inverse transform are half the sum over the two parities of
+    conj(Phi)^p times the n-point inverse transform of those bins. With the
+    parity sub-lattices T_p = T[bId] of the embedded symbol (Section II.C):
+
+        y = 2^-d  sum_p  conj(Phi^p) . iFFT_n( T_p . FFT_n( Phi^p . x ) )
+
+    where FFT_n is the unpadded d-dimensional transform and T_p . acts as the
+    b x b block product at every frequency. Every branch is evaluated on its
+    own; nothing is shared between branches.
     """
-    n = grid_of(coeffs)
-    b = coeffs.shape[0]
+    return split_branch_sum_with_symbol(embed_symbol(coeffs), x)
+
+
+def split_branch_sum_with_symbol(C: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """split_branch_sum for an embedded symbol C = embed_symbol(coeffs) computed
+    beforehand; branch q reads its parity sub-lattice T[bId] of C."""
+    b = C.shape[0]
+    n = tuple(v // 2 for v in C.shape[2:])
     d = len(n)
     x = _as_vectors(x, b, n)
-    nrhs = x.shape[0]
+    axes = tuple(range(2, 2 + d))
+    y = np.zeros_like(x)
+    for q in range(2 ** d):
+        p = [(q >> (d - 1 - l)) & 1 for l in range(d)]
+        Tq = C[(slice(None), slice(None)) + tuple(slice(pl, None, 2) for pl in p)]
+        v = x
+        for l in range(d):
+            if p[l]:
+                v = _along(v, phase(n[l]), 2 + l)
+        V = scipy.fft.fftn(v, axes=axes, workers=_WORKERS)
+        W = np.einsum("ac...,rc...->ra...", Tq, V)
+        w = scipy.fft.ifftn(W, axes=axes, workers=_WORKERS)
+        for l in range(d):
+            if p[l]:
+                w = _along(w, np.conj(phase(n[l])), 2 + l)
+        y += w
+    return y / 2 ** d
+
+
+def lazy_order(d: int):
+    """Events of the lazy (depth-first) evaluation of the d-level branch tree.
+
+    Section II: a node at depth k holds one vector; splitting it along level
+    k + 1 creates the phase-shifted odd child, the even subtree is finished
+    before the odd one is started, and the two results are merged along level
+    k + 1 before the node is left. Entering a node at depth l >= 1 transforms
+    its vector along level l and leaving it transforms back. The events are
+    built here from the leaves' binary branch indices in increasing order
+    (p_1 most significant, even before odd): between leaf q - 1 and leaf q the
+    trailing odd levels of q - 1 are closed (inverse transform, merge) and the
+    deepest even level of q - 1 is left and re-entered as its odd sibling.
+
+    Returns a list of tuples: ("split", l), ("fft", l), ("leaf", q),
+    ("ifft", l), ("merge", l) with levels l = 1..d.
+    """
+    ev = []
+    for l in range(1, d + 1):
+        ev += [("split", l), ("fft", l)]
+    for q in range(2 ** d):
+        if q > 0:
+            prev = q - 1
+            k = 0
+            while (prev >> k) & 1:
+                k += 1          # trailing odd levels d, d-1, ..., d-k+1 of leaf q-1
+            for l in range(d, d - k, -1):
+                ev += [("ifft", l), ("merge", l)]
+            top = d - k          # deepest even level of leaf q-1: becomes odd
+            ev += [("ifft", top), ("fft", top)]
+            for l in range(top + 1, d + 1):
+                ev += [("split", l), ("fft", l)]
+        ev.append(("leaf", q))
+    for l in range(d, 0, -1):
+        ev += [("ifft", l), ("merge", l)]
+    return ev
+
+
+def lazy_costs(n: Sequence[int], b: int = 1, nrhs: int = 1) -> Dict[str, object]:
+    """Work units and live vectors of the lazy evaluation (Section II.C units).
+
+    Walks lazy_order: an FFT or inverse FFT along level l costs
+    (entries of one vector) * log2(n_l), a split or merge costs one phase
+    multiply per entry, a leaf costs b^2 scalar products per grid point and
+    right-hand side. The input is one live vector, a split adds one, a merge
+    frees one. Returns fft, phase, mult, total, fft_calls / ifft_calls per
+    level, the leaves in visiting order, and the peak number of live vectors.
+    """
+    n = tuple(n)
+    d = len(n)
     s = math.prod(n)
-    units = b * nrhs  # scalar entries per grid point of one vector
-    T = branch_symbols(coeffs)
-    cnt = counters if counters is not None else SplitCounters()
-    phases = [phase(v) for v in n]
-
-    def axis_of(level):  # array axis of grid level l (1-based)
-        return 1 + level
-
-    def toe_mul_brn(level: int, p: Tuple[int, ...], v: np.ndarray) -> np.ndarray:
-        if level > 0:
-            v = scipy.fft.fft(v, axis=axis_of(level), workers=_WORKERS)
-            cnt.fft += units * s * math.log2(n[level - 1])
-            cnt.fft_calls[level] = cnt.fft_calls.get(level, 0) + 1
-        if level < d:
-            # sptBrn: a phase-shifted copy along the next level
-            child = _along(v, phases[level], axis_of(level + 1))
-            cnt.phase += units * s
-            cnt.alloc()
-            v = toe_mul_brn(level + 1, p + (0,), v)
-            child = toe_mul_brn(level + 1, p + (1,), child)
-            # mrgBrn: even and odd results recombined along the next level
-            v = 0.5 * (v + _along(child, np.conj(phases[level]), axis_of(level + 1)))
-            cnt.phase += units * s
-            cnt.free()
+    units = s * b * nrhs
+    out = dict(fft=0.0, phase=0, mult=0, fft_calls={}, ifft_calls={}, leaves=[], peak=1)
+    live = 1
+    for kind, arg in lazy_order(d):
+        if kind in ("fft", "ifft"):
+            out["fft"] += units * math.log2(n[arg - 1])
+            key = "fft_calls" if kind == "fft" else "ifft_calls"
+            out[key][arg] = out[key].get(arg, 0) + 1
+        elif kind == "split":
+            out["phase"] += units
+            live += 1
+            out["peak"] = max(out["peak"], live)
+        elif kind == "merge":
+            out["phase"] += units
+            live -= 1
         else:
-            # mulBrn: per-point b x b block product with T[bId]
-            blk = T[branch_index(p)]
-            v = np.einsum("ac...,rc...->ra...", blk, v)
-            cnt.mult += nrhs * b * b * s
-        if level > 0:
-            v = scipy.fft.ifft(v, axis=axis_of(level), workers=_WORKERS)
-            cnt.fft += units * s * math.log2(n[level - 1])
-            cnt.fft_calls[-level] = cnt.fft_calls.get(-level, 0) + 1
-        return v
-
-    cnt.alloc()  # the input vector
-    y = toe_mul_brn(0, (), x)
-    cnt.free()
-    return y
+            out["mult"] += nrhs * b * b * s
+            out["leaves"].append(arg)
+    out["live_at_end"] = live
+    out["total"] = out["fft"] + out["phase"] + out["mult"]
+    return out
 
 
 # ---------------------------------------------------------------------------
