@@ -1,18 +1,22 @@
 #!/usr/bin/env python3
 """Benchmark of the split-FFT multilevel block-Toeplitz matvec on one MI355X.
 
-Workload: d = 3 levels, 64 x 64 x 64 grid, 3 x 3 Green-function blocks
-t(r) = exp(i k |r|)/|r| (I - rhat rhat^T), k = 0.7, self term 2 I; one
-complex vector per matvec (seeded complex-normal). A step is one matvec
-y = T x through the whole hot path (forward split passes, fused leaf,
-inverse merge passes), inputs resident in HBM.
+Headline workload (the default): d = 3 levels, 256 x 256 x 128 grid, 3 x 3
+Green-function blocks t(r) = exp(i k |r|)/|r| (I - rhat rhat^T), k = 1.3,
+self term 2 I; 8 seeded complex-normal right-hand sides per apply, complex64
+data path with FP64-generated symbols and twiddles. A step is one apply of the
+whole hot path to the 8 right-hand sides (forward split passes, fused leaf,
+inverse merge passes) in Algorithm 1's depth-first order, inputs resident in
+HBM; value = matvecs/s = 8 / step time.
 
-Prints ONE JSON line: the headline is the complex64 split path; the FP64
-split path and the full circulant-embedding baseline (same GPU, same kernels)
-are reported beside it, with the dominant kernel's roofline and the FP64 CPU
-oracle's throughput on the host.
+Prints ONE JSON line: the split path's throughput, its apply latency
+percentiles (warm and after a 1 GiB cache scrub), the dominant kernel's
+roofline, breadth-first / mirrored-symbol / skew-kernel variants and the full
+circulant embedding on the same GPU with measured device memory, and the FP64
+CPU oracle timed on the host cores.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
+    python bench.py --workload green64|batch|serve   (the other configurations)
 """
 
 from __future__ import annotations
@@ -226,93 +230,224 @@ def pmc_summarize_large(fetch_dir, write_dir, out_path):
     print(json.dumps(rec))
 
 
+LARGE_LEAF = "sfft::k_leaf<float, 128, 3, 2, false, 1>"
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline_large(coeffs, x_host, budget_s):
+    """The FP64 oracle (circulant embedding, symbol transformed once before the
+    timed loop) on one right-hand side of the 256x256x128 workload, with
+    scipy.fft using all host cores and then one core."""
+    import oracle
+    cores = len(os.sched_getaffinity(0))
+    oracle.set_workers(cores)
+    t0 = time.perf_counter()
+    C = oracle.embed_symbol(coeffs)
+    t_sym = time.perf_counter() - t0
+    log(f"[cpu] embedded symbol in {t_sym:.1f} s ({cores} workers)")
+    runs, ref = {}, None
+    for workers, budget in ((cores, budget_s), (1, 0.0)):
+        oracle.set_workers(workers)
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            y = oracle.embed_matvec_with_symbol(C, x_host[:1])
+            reps += 1
+            if ref is None:
+                ref = y
+            if time.perf_counter() - t0 >= budget:
+                break
+        wall = time.perf_counter() - t0
+        runs[workers] = dict(matvecs_per_s=round(reps / wall, 5), reps=reps, wall_s=round(wall, 2))
+        log(f"[cpu] workers={workers}: {reps} matvecs in {wall:.1f} s")
+    oracle.set_workers(None)
+    del C
+    best = runs[cores]
+    return ref, dict(value=best["matvecs_per_s"], unit="matvecs/s", cores=cores, kind="oracle",
+                     sample=f"{best['reps']} FP64 matvecs (1 right-hand side each) of the same 256x256x128 "
+                            f"b=3 Green workload through oracle.embed_matvec_with_symbol, symbol transformed "
+                            f"once beforehand ({t_sym:.1f} s, not timed); scipy.fft workers={cores}",
+                     cpu_model=cpu_model(), per_workers={str(k): v for k, v in runs.items()})
+
+
 def bench_large(args):
-    """256 x 256 x 128 grid, 3x3 Green blocks (k=1.3) and the skew kernel, 8 RHS,
-    complex64: time per product and device memory of the split path (both
-    schedules, general and mirrored symbols) against the full embedding."""
+    """Headline: 256 x 256 x 128 grid, 3x3 Green blocks (k=1.3, self term 2I),
+    8 right-hand sides per apply, complex64 data path with FP64-generated
+    symbols and twiddles, split product in Algorithm 1's depth-first order.
+    Beside it: breadth-first, mirrored symbols, the skew-symmetric kernel and
+    the full circulant embedding on the same GPU, apply latency percentiles,
+    the dominant kernel's roofline and the FP64 CPU oracle."""
     import numpy as np
     import torch
     import workloads as wl
     import paper_2406_17981_amd as sf
+
+    if not torch.cuda.is_available():
+        log("no GPU visible")
+        sys.exit(1)
+    dev = torch.cuda.get_device_properties(0)
+    log(f"device: {dev.name}, {dev.multi_processor_count} CUs")
     cfg = wl.LARGE_256
-    n, nrhs = cfg["n"], cfg["nrhs"]
-    x_host = wl.vectors(cfg["seed_x"], n, 3, nrhs).astype(np.complex64)
-    x = torch.from_numpy(x_host).cuda()
+    n, nrhs, b = cfg["n"], cfg["nrhs"], 3
+    d = len(n)
+    log("generating coefficients and vectors on the host")
+    coeffs = wl.green_coeffs(n, cfg["k"])
+    x_host = wl.vectors(cfg["seed_x"], n, b, nrhs)
+    x = torch.from_numpy(x_host.astype(np.complex64)).cuda()
     y = torch.empty_like(x)
-    del x_host
-    out = {}
-    fp64_check = {}
+    vb = x.numel() * 8  # V: bytes of one set of 8 right-hand sides
+    golden = np.load(os.path.join(ROOT, "tests", "golden", "large_256_rows.npz"))
+    pts = golden["points"]
+    pidx = torch.from_numpy(np.ravel_multi_index(pts.T, n)).cuda()
+
+    def sampled_err(kname):
+        got = y.reshape(nrhs, b, -1)[:, :, pidx].cpu().numpy().astype(np.complex128)
+        return wl.relative_l2(got, golden[kname])
+
+    results, rel = {}, {}
+    headline = {}
     for kname in ("green", "skew"):
-        coeffs = wl.green_coeffs(n, cfg["k"]) if kname == "green" else wl.skew_coeffs(n, cfg["k"])
+        if kname == "skew":
+            del coeffs_d
+            torch.cuda.empty_cache()
+            ck = wl.skew_coeffs(n, cfg["k"])
+        else:
+            ck = coeffs
+        coeffs_d = torch.from_numpy(ck).cuda()
+        if kname == "skew":
+            del ck
         par = wl.green_parity(3) if kname == "green" else wl.skew_parity(3)
-        cd = torch.from_numpy(coeffs).cuda()
-        del coeffs
         cases = [("split_depth", "split", "depth", None), ("split_breadth", "split", "breadth", None),
                  ("split_depth_mirrored", "split", "depth", par), ("embed", "embed", "auto", None)]
         if kname == "skew":
-            cases = [cases[2], cases[3]]
+            cases = [cases[0], cases[2], cases[3]]
         for label, method, sched, parity in cases:
+            key = f"{kname}_{label}"
             torch.cuda.synchronize()
             free0 = torch.cuda.mem_get_info()[0]
-            plan = sf.Plan(n, 3, cd, dtype="c64", method=method, parity=parity, max_nrhs=nrhs,
+            plan = sf.Plan(n, b, coeffs_d, dtype="c64", method=method, parity=parity, max_nrhs=nrhs,
                            schedule=sched)
             ws = plan.alloc_workspace(nrhs)
             torch.cuda.synchronize()
             held = free0 - torch.cuda.mem_get_info()[0]
-            ms, leaf = time_plan(plan, x, y, ws, args.steps, args.warmup, profile_leaf=method == "split")
             info = plan.info()
-            vb = 2 * x.numel() * 8
-            out[f"{kname}_{label}"] = dict(ms_per_apply=round(ms, 4), matvecs_per_s=round(nrhs * 1e3 / ms, 1),
-                                           device_bytes=info["symbol_bytes"] + info["table_bytes"]
-                                           + info["workspace_bytes"] + vb,
-                                           symbol_bytes=info["symbol_bytes"],
-                                           workspace_bytes=info["workspace_bytes"],
-                                           measured_plan_and_workspace_bytes=int(held))
-            lat = apply_latencies(plan, x, y, ws, max(args.steps, 10))
-            out[f"{kname}_{label}"]["apply_ms_p10_p50_p90"] = [round(v / 1e3, 4) for v in lat]
-            if leaf is not None and leaf[1] > 0:
-                # every launch of an apply together reads and writes each of the
-                # 2^(d-1) level-(d-1) branch vectors once and reads the stored symbols once
-                per_apply = leaf[1] / len(range(0, args.steps, PROFILE_EVERY))
-                alg = (2 ** (len(n) - 1) * 2 * (vb // 2) + info["symbol_bytes"]) / per_apply
-                avg_s = leaf[0] / leaf[1] * 1e-3
-                out[f"{kname}_{label}"]["leaf"] = dict(
-                    avg_launch_us=round(avg_s * 1e6, 1), launches_per_apply=per_apply,
-                    algorithmic_bytes_per_launch=int(alg), achieved_gbs=round(alg / avg_s / 1e9, 1),
-                    frac=round(alg / avg_s / 1e9 / HBM_PEAK_GBS, 4))
-                if label == "split_depth" and kname == "green":
-                    out[f"{kname}_{label}"]["leaf"]["traffic"] = measured_traffic_large(
-                        "sfft::k_leaf<float, 128, 3, 2, false, 1>")
-            log(f"[large {kname} {label}] {ms:.3f} ms per apply of {nrhs} RHS")
-            if kname == "green" and label == "split_depth":
+            head = key == "green_split_depth"
+            log(f"[{key}] timing {args.steps} applies after {args.warmup}")
+            ms, leaf = time_plan(plan, x, y, ws, args.steps, args.warmup, profile_leaf=head)
+            rel[key] = float(f"{sampled_err(kname):.3e}")
+            r = dict(ms_per_apply=round(ms, 4), matvecs_per_s=round(nrhs * 1e3 / ms, 2),
+                     schedule=["auto", "breadth", "depth"][info["schedule"]],
+                     symbol_bytes=info["symbol_bytes"], workspace_bytes=info["workspace_bytes"],
+                     model_device_bytes=info["symbol_bytes"] + info["table_bytes"] + info["workspace_bytes"] + 2 * vb,
+                     measured_device_bytes=int(held) + 2 * vb)
+            if head or key in ("green_embed", "green_split_depth_mirrored"):
+                warm = apply_latencies(plan, x, y, ws, max(100, args.steps), pct=(50, 99))
+                cold = apply_latencies(plan, x, y, ws, 30, scrub_bytes=1 << 30, pct=(50, 99))
+                r["latency_ms"] = {"warm": {"p50": warm[0] / 1e3, "p99": warm[1] / 1e3},
+                                   "cold": {"p50": cold[0] / 1e3, "p99": cold[1] / 1e3}}
+            if head:
+                headline = dict(ms=ms, leaf=leaf, info=info)
                 y_c64 = y.clone()
+            results[key] = r
+            log(f"[{key}] {ms:.3f} ms per apply ({r['matvecs_per_s']:.0f} matvecs/s), "
+                f"sampled rel L2 {rel[key]:.2e}, device bytes {r['measured_device_bytes'] / 1e9:.2f} GB")
             plan.close()
             del ws
             torch.cuda.empty_cache()
         if kname == "green":
             # FP64 residual of the complex64 product: the same product through a
             # complex128 plan, compared on the device in FP64
-            plan = sf.Plan(n, 3, cd, dtype="c128", method="split", max_nrhs=nrhs, schedule="depth")
+            plan = sf.Plan(n, b, coeffs_d, dtype="c128", method="split", max_nrhs=nrhs, schedule="depth")
             x128 = x.to(torch.complex128)
             y128 = plan.apply(x128, workspace=plan.alloc_workspace(nrhs))
-            rel = (torch.linalg.vector_norm(y_c64.to(torch.complex128) - y128)
-                   / torch.linalg.vector_norm(y128)).item()
-            fp64_check = {"green_split_depth_rel_l2_c64_vs_c128": float(f"{rel:.3e}")}
-            log(f"[large green] rel L2 of the c64 product against the c128 product: {rel:.3e}")
+            fp64_rel = (torch.linalg.vector_norm(y_c64.to(torch.complex128) - y128)
+                        / torch.linalg.vector_norm(y128)).item()
+            log(f"[green] rel L2 of the c64 product against the c128 product: {fp64_rel:.3e}")
             plan.close()
-            del x128, y128, y_c64
+            del x128, y128
             torch.cuda.empty_cache()
-        del cd
-        torch.cuda.empty_cache()
-    g = out
-    line = {"workload": "green/skew-256x256x128-b3-8rhs-c64", "grid": list(n), "b": 3, "nrhs": nrhs,
-            "steps": args.steps, "warmup": args.warmup, "results": g, "fp64_residual": fp64_check,
-            "split_depth_vs_embed": {
-                "speedup": round(g["green_embed"]["ms_per_apply"] / g["green_split_depth"]["ms_per_apply"], 3),
-                "device_bytes_ratio_embed_over_split": round(g["green_embed"]["device_bytes"]
-                                                             / g["green_split_depth"]["device_bytes"], 3),
-                "device_bytes_ratio_embed_over_split_mirrored": round(
-                    g["green_embed"]["device_bytes"] / g["green_split_depth_mirrored"]["device_bytes"], 3)}}
+    del coeffs_d, x
+    torch.cuda.empty_cache()
+
+    ms = headline["ms"]
+    info = headline["info"]
+    leaf_ms, leaf_cnt = headline["leaf"]
+    sampled_applies = len(range(0, args.steps, PROFILE_EVERY))
+    per_apply = leaf_cnt / max(sampled_applies, 1)
+    leaf_avg_s = leaf_ms / max(leaf_cnt, 1) * 1e-3
+    S = info["symbol_bytes"]
+    b_alg = 2 * vb + S  # compulsory bytes of one apply: x read, y written, stored symbols read once
+    achieved = b_alg / (leaf_avg_s * per_apply) / 1e9
+    kernel_bytes = (2 * vb + S / per_apply)  # one leaf launch: its branch in and out, its quarter of the symbols
+    model_bytes = (2 ** (d + 2) - 6) * vb + S  # every level's pass moves its branch vectors once
+    copy_gbs = stream_copy_gbs()
+    roofline = dict(
+        bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+        frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic_large(LARGE_LEAF),
+        kernel=LARGE_LEAF, avg_launch_us=round(leaf_avg_s * 1e6, 1), launches_per_apply=per_apply,
+        algorithmic_bytes_per_apply=int(b_alg),
+        algorithmic_bytes_per_launch=int(b_alg / per_apply),
+        note="achieved = (2V + S) / (leaf launches per apply x mean leaf launch time); V = one set of 8 "
+             "right-hand sides, S = stored symbol bytes",
+        kernel_own=dict(bytes_per_launch=int(kernel_bytes), achieved=round(kernel_bytes / leaf_avg_s / 1e9, 1),
+                        frac=round(kernel_bytes / leaf_avg_s / 1e9 / HBM_PEAK_GBS, 4)),
+        whole_apply=dict(algorithmic_bytes=int(b_alg), achieved=round(b_alg / (ms * 1e-3) / 1e9, 1),
+                         frac=round(b_alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                         model_bytes=int(model_bytes), model_achieved=round(model_bytes / (ms * 1e-3) / 1e9, 1),
+                         model_frac=round(model_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)),
+        stream_copy_gbs=round(copy_gbs, 1))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"CPU oracle baseline (~{args.cpu_seconds:.0f} s with all cores, then one rep on one core)")
+        ref, cpu = cpu_baseline_large(coeffs, x_host, args.cpu_seconds)
+        rel["green_split_depth_full_rhs0_vs_cpu_oracle"] = float(
+            f"{wl.relative_l2(y_c64[:1].cpu().numpy().astype(np.complex128), ref):.3e}")
+        del ref
+    g = results
+    line = {
+        "metric": METRIC,
+        "value": g["green_split_depth"]["matvecs_per_s"],
+        "unit": "matvecs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": g["green_split_depth"]["ms_per_apply"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64",
+        "data": "synthetic",
+        "config": {"workload": "green-256x256x128-b3-k1.3-8rhs", "grid": list(n), "b": b, "nrhs": nrhs,
+                   "method": "split", "schedule": "depth",
+                   "kernel": "3x3 Green blocks exp(ik|r|)/|r| (I - rr^T), k=1.3, self 2I",
+                   "step": "one apply of 8 right-hand sides (8 matvecs)"},
+        "roofline": roofline,
+        "latency_ms": g["green_split_depth"].get("latency_ms"),
+        "cpu_baseline": cpu,
+        "variants": g,
+        "split_vs_embed": {
+            "speedup": round(g["green_embed"]["ms_per_apply"] / g["green_split_depth"]["ms_per_apply"], 3),
+            "device_bytes_ratio_embed_over_split": round(
+                g["green_embed"]["measured_device_bytes"] / g["green_split_depth"]["measured_device_bytes"], 3),
+            "device_bytes_ratio_embed_over_split_mirrored": round(
+                g["green_embed"]["measured_device_bytes"] / g["green_split_depth_mirrored"]["measured_device_bytes"],
+                3),
+            "skew_speedup_mirrored": round(g["skew_embed"]["ms_per_apply"]
+                                           / g["skew_split_depth_mirrored"]["ms_per_apply"], 3)},
+        "fp64_residual_c64_vs_c128": float(f"{fp64_rel:.3e}"),
+        "rel_l2_vs_fp64_oracle": rel,
+        "rel_l2_note": "sampled: all 8 right-hand sides at 128 grid points against stored FP64 oracle values "
+                       "(tests/golden/large_256_rows.npz)",
+    }
     print(json.dumps(line), flush=True)
 
 
@@ -444,10 +579,10 @@ def time_plan(plan, x, y, ws, steps, warmup, profile_leaf=False):
     return (t1 - t0) * 1e3 / steps, leaf
 
 
-def apply_latencies(plan, x, y, ws, reps, scrub_bytes=0):
+def apply_latencies(plan, x, y, ws, reps, scrub_bytes=0, pct=(10, 50, 90)):
     """Per-apply device time (HIP events around each apply on the current
     stream), optionally after a fill of scrub_bytes that evicts the
-    memory-side cache; returns (p10, p50, p90) in microseconds."""
+    memory-side cache; returns the percentiles pct in microseconds."""
     import numpy as np
     import torch
     scrub = torch.empty(max(scrub_bytes // 4, 1), dtype=torch.float32, device="cuda")
@@ -465,7 +600,7 @@ def apply_latencies(plan, x, y, ws, reps, scrub_bytes=0):
     us = np.array([a.elapsed_time(b) * 1e3 for a, b in ev])
     del scrub
     torch.cuda.empty_cache()
-    return tuple(round(float(v), 2) for v in np.percentile(us, [10, 50, 90]))
+    return tuple(round(float(v), 2) for v in np.percentile(us, list(pct)))
 
 
 def time_plan_cold(plan, x, y, ws, reps, scrub_bytes=1 << 30):
@@ -516,57 +651,10 @@ def cpu_baseline(coeffs, x, budget_s):
                             f"{wall:.1f} s wall")
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=None,
-                    help="timed applies (default 1000 for the headline workload, 10 large, 50 batch)")
-    ap.add_argument("--warmup", type=int, default=None,
-                    help="untimed applies first (default 2000 for the headline workload, whose "
-                         "applies are short and would otherwise run before the GPU clocks ramp up; "
-                         "2 large, 5 batch)")
-    ap.add_argument("--schedule", default="auto", choices=["auto", "breadth", "depth"])
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--variants", default="all", choices=["all", "headline"])
-    ap.add_argument("--pmc-probe", action="store_true", help="workload for rocprofv3 --pmc runs")
-    ap.add_argument("--requests", type=int, default=400, help="serve: requests in the stream")
-    ap.add_argument("--single-requests", type=int, default=None,
-                    help="serve: requests for the FP64 path (default: the same stream)")
-    ap.add_argument("--budget-gb", type=float, default=64.0, help="serve: HBM budget")
-    ap.add_argument("--workload", default="green64", choices=["green64", "large", "batch", "serve"],
-                    help="large: the 256x256x128 8-RHS configuration, split vs embed; "
-                         "batch: 8 uneven-grid problems, 64 RHS, one graph")
-    ap.add_argument("--pmc-summarize", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON"))
-    args = ap.parse_args()
-    steps_default, warmup_default = {"large": (10, 2), "batch": (50, 5)}.get(args.workload, (1000, 2000))
-    if args.steps is None:
-        args.steps = steps_default
-    if args.warmup is None:
-        args.warmup = warmup_default
-
-    if args.pmc_summarize:
-        (pmc_summarize_large if args.workload == "large" else pmc_summarize)(*args.pmc_summarize)
-        return
-    if args.pmc_probe:
-        pmc_probe(args.workload)
-        return
-    if args.workload == "large":
-        bench_large(args)
-        return
-    if args.workload == "batch":
-        bench_batch(args)
-        return
-    if args.workload == "serve":
-        bench_serve(args)
-        return
-
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU split of the branch tree is a design note, not a measured path.",
-              file=sys.stderr)
-        sys.exit(2)
-
+def bench_green64(args):
+    """64^3 grid, 3x3 Green blocks (k=0.7), one right-hand side per apply: the split
+    path in complex64 and complex128, mirrored symbols, all 9 components, and the
+    full embedding, with the leaf's roofline and the FP64 CPU oracle."""
     import numpy as np
     import torch
     import workloads as wl
@@ -719,6 +807,52 @@ def main():
     if emb is None:
         line.pop("speedup_vs_embed")
     print(json.dumps(line), flush=True)
+
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed applies (default 20 large, 1000 green64, 50 batch)")
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed applies first (default 5 large; 2000 green64, whose applies are "
+                         "short and would otherwise run before the GPU clocks ramp up; 5 batch)")
+    ap.add_argument("--schedule", default="auto", choices=["auto", "breadth", "depth"])
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--variants", default="all", choices=["all", "headline"])
+    ap.add_argument("--pmc-probe", action="store_true", help="workload for rocprofv3 --pmc runs")
+    ap.add_argument("--requests", type=int, default=400, help="serve: requests in the stream")
+    ap.add_argument("--single-requests", type=int, default=None,
+                    help="serve: requests for the FP64 path (default: the same stream)")
+    ap.add_argument("--budget-gb", type=float, default=64.0, help="serve: HBM budget")
+    ap.add_argument("--workload", default="large", choices=["large", "green64", "batch", "serve"],
+                    help="large (default, the headline): 256x256x128, b=3, 8 RHS, split vs embed; "
+                         "green64: the 64^3 one-RHS configuration; "
+                         "batch: 8 uneven-grid problems, 64 RHS, one graph; serve: the Poisson stream")
+    ap.add_argument("--pmc-summarize", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON"))
+    args = ap.parse_args()
+    steps_default, warmup_default = {"large": (20, 5), "batch": (50, 5), "green64": (1000, 2000)}.get(
+        args.workload, (1, 0))
+    if args.steps is None:
+        args.steps = steps_default
+    if args.warmup is None:
+        args.warmup = warmup_default
+
+    if args.pmc_summarize:
+        (pmc_summarize_large if args.workload == "large" else pmc_summarize)(*args.pmc_summarize)
+        return
+    if args.pmc_probe:
+        pmc_probe(args.workload)
+        return
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU split of the branch tree is a design note, not a measured path.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    {"large": bench_large, "green64": bench_green64, "batch": bench_batch, "serve": bench_serve}[args.workload](args)
 
 
 if __name__ == "__main__":

@@ -42,8 +42,9 @@ typedef struct sfft_plan_s* sfft_plan;
 
 typedef enum {
   SFFT_OK = 0,
-  SFFT_INVALID_ARG = 1,   /* null pointer, d < 1, n_l < 1, bad enum, x aliases y, short workspace */
-  SFFT_UNSUPPORTED = 2,   /* level size without built kernels, b not in {1, 3}, d > 6 */
+  SFFT_INVALID_ARG = 1,   /* null pointer, d < 1, n_l < 1, b not in {1..4}, bad enum, x aliases y,
+                             short workspace, declared parity not held by the coefficients */
+  SFFT_UNSUPPORTED = 2,   /* level size with a prime factor outside {2, 3, 5, 7}, d > 6 */
   SFFT_OUT_OF_MEMORY = 3, /* device allocation failed */
   SFFT_HIP_ERROR = 4      /* a HIP runtime call or kernel launch failed */
 } sfft_status;
@@ -59,7 +60,7 @@ typedef enum {
 } sfft_method;
 
 typedef enum {
-  SFFT_SCHED_AUTO = 0,    /* breadth-first when its workspace is small, else depth-first */
+  SFFT_SCHED_AUTO = 0,    /* depth-first (the paper's peak memory); sfft_plan_autotune may pick breadth-first */
   SFFT_SCHED_BREADTH = 1, /* all branches of a level per launch: workspace (2^d - 2) vectors */
   SFFT_SCHED_DEPTH = 2    /* Algorithm 1's lazy order: workspace (d - 1) vectors, peak (d + 1) with x, y */
 } sfft_schedule;

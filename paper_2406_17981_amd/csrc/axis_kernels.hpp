@@ -82,7 +82,7 @@ struct PassArgs {
   int64_t mn[6];     // level sizes
   int64_t mst[6];    // strides of the stored array
   int64_t mcomp;     // stored entries per component
-  uint64_t odd_bits; // bit (k*6 + l): stored component k is odd along level l (k < 9, d <= 6)
+  uint8_t odd[16];   // bit l of odd[k]: stored component k is odd along level l
   // filled by the launchers: block and column decoding without 64-bit division
   FastDiv fd_a, fd_b;  // strided: tiles per branch, inner; leaf: rhs groups, tile groups of 8
   int idx32;           // every decoded index fits in 32 bits
@@ -515,7 +515,7 @@ __global__ void __launch_bounds__((Geo<Real, L>::RBMAX * Geo<Real, L>::SL)) k_le
   if constexpr (MIR) {
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
-      const uint32_t odd = (uint32_t)(a.odd_bits >> (k * 6)) & 0x3fu;
+      const uint32_t odd = a.odd[k];
       osign |= (uint32_t)(__builtin_popcount(mbits & odd) & 1) << k;
       lodd |= ((odd >> (a.d - 1)) & 1u) << k;
     }
@@ -524,9 +524,12 @@ __global__ void __launch_bounds__((Geo<Real, L>::RBMAX * Geo<Real, L>::SL)) k_le
   // symbols requested ahead: parity 0, entries 0..3, before the forward
   // transforms; parity 1, entries 0 and 1, before parity 0's product
   constexpr int MSP = (E % 2 == 0) ? 2 : 1;
-  constexpr int NPF = (MSP == 2 && E >= 4) ? 2 : 1;
+  // groups requested ahead: two of parity 0 and one of parity 1 for up to 9
+  // stored components; larger blocks (b = 4) keep one group, registers allow
+  constexpr int NPF = (MSP == 2 && E >= 4 && NS <= 9) ? 2 : 1;
+  constexpr bool PF1 = NS <= 9;
   C2 pf[NPF][NS];
-  C2 pf1[NS];
+  C2 pf1[PF1 ? NS : 1];
   auto sym_base = [&](int p) {
     return (const C*)a.sym + q * a.sym_bs + ((int64_t)p * a.ntiles + tile) * (NS * E * SL);
   };
@@ -560,7 +563,7 @@ __global__ void __launch_bounds__((Geo<Real, L>::RBMAX * Geo<Real, L>::SL)) k_le
   if constexpr (MIR) mir_group(0, 0, mpf, mpf_flip);
   // mulBrn for one child p: w[.][m] <- S_p[., .](m) w[.][m]
   auto block_product = [&](C (&w)[B][E], int p) {
-    if constexpr (!MIR && MSP == 2 && NPAR == 2) {  // the embedding baseline has one child
+    if constexpr (!MIR && MSP == 2 && NPAR == 2 && PF1) {  // the embedding baseline has one child
       if (p == 0) {
 #pragma unroll
         for (int k = 0; k < NS; ++k) pf1[k] = *(const C2*)(sym_base(1) + sym_offset(k, 0, slane, E, SL));
@@ -594,7 +597,8 @@ __global__ void __launch_bounds__((Geo<Real, L>::RBMAX * Geo<Real, L>::SL)) k_le
         if constexpr (MIR) {
         } else if constexpr (MS == 2) {
           const C2 v = (p == 0 && m0 < 2 * NPF) ? pf[m0 / 2][k]
-                       : (p == 1 && m0 == 0) ? pf1[k] : *(const C2*)(sp + sym_offset(k, m0, slane, E, SL));
+                       : (PF1 && NPAR == 2 && p == 1 && m0 == 0) ? pf1[PF1 ? k : 0]
+                                                                 : *(const C2*)(sp + sym_offset(k, m0, slane, E, SL));
           sm[0][k] = mk<C>(v.x, v.y);
           sm[1][k] = mk<C>(v.z, v.w);
         } else {
@@ -704,11 +708,18 @@ struct AxisOps {
   int RBMAX;           // leaf: most right-hand sides per workgroup
   pass_fn strided[2];   // [0] FWD2, [1] INV2
   pass_fn contig[2];
-  pass_fn leaf[5][3][3];    // [B][NPAR][block symmetry], null where not built
-  pass_fn leaf_mirror[5][3];  // [B][block symmetry], NPAR = 2, mirrored symbol storage
+  struct LeafRow {
+    pass_fn f[3][3];  // [NPAR][block symmetry]
+  };
+  struct MirRow {
+    pass_fn f[3];     // [block symmetry]
+  };
+  LeafRow leaf[5];    // [B]: general symbol storage, null where not built
+  MirRow leaf_mirror[5];  // [B]: NPAR = 2, mirrored symbol storage
 };
 
 constexpr int64_t kIdx32 = (int64_t)1 << 31;
+constexpr size_t kMaxLds = 160 * 1024;  // LDS of one gfx950 workgroup
 // passes of at least this many workgroups (many per CU) use the
 // XCD-contiguous block order (1.4% on 256x256x128 passes); smaller launches
 // keep dispatch order (their start latency counts), except narrow tiles
@@ -785,8 +796,39 @@ hipError_t launch_leaf(const PassArgs& a, hipStream_t s) {
     b.fd_b = FastDiv::make((uint32_t)((a.ntiles + 7) / 8));
   }
   const size_t smem = (size_t)rb * row_bytes;
+  if (smem > kMaxLds) return hipErrorInvalidConfiguration;  // beyond a workgroup's LDS
   hipLaunchKernelGGL((k_leaf<Real, L, B, NPAR, MIR, BS>), dim3((unsigned)blocks), dim3(rb * G::SL), smem, s, b);
   return hipGetLastError();
+}
+
+template <typename Real, int L, int B> constexpr AxisOps::LeafRow leaf_row_general() {
+  AxisOps::LeafRow r{};
+  if constexpr (B == 1) {  // a scalar block has no block symmetry to exploit
+    for (int bs = 0; bs < 3; ++bs) {
+      r.f[1][bs] = launch_leaf<Real, L, 1, 1>;
+      r.f[2][bs] = launch_leaf<Real, L, 1, 2>;
+    }
+  } else {
+    r.f[1][0] = launch_leaf<Real, L, B, 1, false, 0>;
+    r.f[1][1] = launch_leaf<Real, L, B, 1, false, 1>;
+    r.f[1][2] = launch_leaf<Real, L, B, 1, false, 2>;
+    r.f[2][0] = launch_leaf<Real, L, B, 2, false, 0>;
+    r.f[2][1] = launch_leaf<Real, L, B, 2, false, 1>;
+    r.f[2][2] = launch_leaf<Real, L, B, 2, false, 2>;
+  }
+  return r;
+}
+
+template <typename Real, int L, int B> constexpr AxisOps::MirRow leaf_row_mirror() {
+  AxisOps::MirRow r{};
+  if constexpr (B == 1) {
+    for (int bs = 0; bs < 3; ++bs) r.f[bs] = launch_leaf<Real, L, 1, 2, true>;
+  } else {
+    r.f[0] = launch_leaf<Real, L, B, 2, true, 0>;
+    r.f[1] = launch_leaf<Real, L, B, 2, true, 1>;
+    r.f[2] = launch_leaf<Real, L, B, 2, true, 2>;
+  }
+  return r;
 }
 
 template <typename Real, int L> const AxisOps* make_ops() {
@@ -795,23 +837,10 @@ template <typename Real, int L> const AxisOps* make_ops() {
       L, G::T, G::E, G::W, G::P, G::LT, G::LE, G::PL, G::NTL, G::RBMAX,
       {launch_strided<Real, L, 0>, launch_strided<Real, L, 1>},
       {launch_contig<Real, L, 0>, launch_contig<Real, L, 1>},
-      {{},
-       {{},
-        {launch_leaf<Real, L, 1, 1>, launch_leaf<Real, L, 1, 1>, launch_leaf<Real, L, 1, 1>},
-        {launch_leaf<Real, L, 1, 2>, launch_leaf<Real, L, 1, 2>, launch_leaf<Real, L, 1, 2>}},
-       {},
-       {{},
-        {launch_leaf<Real, L, 3, 1, false, 0>, launch_leaf<Real, L, 3, 1, false, 1>,
-         launch_leaf<Real, L, 3, 1, false, 2>},
-        {launch_leaf<Real, L, 3, 2, false, 0>, launch_leaf<Real, L, 3, 2, false, 1>,
-         launch_leaf<Real, L, 3, 2, false, 2>}},
-       {}},
-      {{},
-       {launch_leaf<Real, L, 1, 2, true>, launch_leaf<Real, L, 1, 2, true>, launch_leaf<Real, L, 1, 2, true>},
-       {},
-       {launch_leaf<Real, L, 3, 2, true, 0>, launch_leaf<Real, L, 3, 2, true, 1>,
-        launch_leaf<Real, L, 3, 2, true, 2>},
-       {}},
+      {{}, leaf_row_general<Real, L, 1>(), leaf_row_general<Real, L, 2>(), leaf_row_general<Real, L, 3>(),
+       leaf_row_general<Real, L, 4>()},
+      {{}, leaf_row_mirror<Real, L, 1>(), leaf_row_mirror<Real, L, 2>(), leaf_row_mirror<Real, L, 3>(),
+       leaf_row_mirror<Real, L, 4>()},
   };
   return &ops;
 }

@@ -301,35 +301,61 @@ sfft_status sfft_plan_autotune(sfft_plan plan, int64_t nrhs, int use_cache, void
   hipError_t he = hipMalloc(&x, vbytes);
   if (he == hipSuccess) he = hipMalloc(&y, vbytes);
   if (he == hipSuccess && wsmax) he = hipMalloc(&ws, wsmax);
-  if (he == hipSuccess) he = hipMemsetAsync(x, 0, vbytes, st);
+  // a nonzero input (every byte 0x3c: normal numbers in FP32 and FP64)
+  if (he == hipSuccess) he = hipMemsetAsync(x, 0x3c, vbytes, st);
   if (he == hipSuccess) he = hipEventCreate(&e0);
   if (he == hipSuccess) he = hipEventCreate(&e1);
   if (he != hipSuccess) s = sfft_rt_hip_fail(he, "autotune buffers");
-  double best = 1e300;
-  int bs = old_sched, br = old_rb;
+  // each candidate: one warm-up apply, then three trials of `reps` applies
+  // (reps sized so a trial lasts about 2 ms, at least 3), keeping the fastest
+  // trial; depth-first (the paper's peak memory) wins unless breadth-first is
+  // more than 3% faster
+  double best = 1e300, best_depth = 1e300;
+  int bs = old_sched, br = old_rb, bdr = old_rb;
+  auto time_reps = [&](int reps, double* us) -> sfft_status {
+    he = hipEventRecord(e0, st);
+    sfft_status r = SFFT_OK;
+    for (int i = 0; i < reps && r == SFFT_OK; ++i) r = sfft_rt_apply_one(plan, x, y, nrhs, ws, wsmax, st);
+    if (r != SFFT_OK) return r;
+    if (he == hipSuccess) he = hipEventRecord(e1, st);
+    if (he == hipSuccess) he = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+    if (he != hipSuccess) return sfft_rt_hip_fail(he, "autotune timing");
+    *us = 1e3 * ms / reps;
+    return SFFT_OK;
+  };
   for (auto& c : cand) {
     if (s != SFFT_OK) break;
     plan->sched = c.first;
     plan->rb_pref = c.second;
     s = sfft_rt_apply_one(plan, x, y, nrhs, ws, wsmax, st);  // warm-up
-    const int reps = 3;
-    if (s == SFFT_OK) he = hipEventRecord(e0, st);
-    for (int i = 0; i < reps && s == SFFT_OK; ++i) s = sfft_rt_apply_one(plan, x, y, nrhs, ws, wsmax, st);
+    double est = 0.0;
+    if (s == SFFT_OK) s = time_reps(1, &est);
     if (s != SFFT_OK) break;
-    he = hipEventRecord(e1, st);
-    if (he == hipSuccess) he = hipEventSynchronize(e1);
-    float ms = 0.f;
-    if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
-    if (he != hipSuccess) {
-      s = sfft_rt_hip_fail(he, "autotune timing");
-      break;
+    int reps = est > 0.0 ? (int)(2000.0 / est) : 3;
+    reps = reps < 3 ? 3 : (reps > 200 ? 200 : reps);
+    double cbest = 1e300;
+    for (int trial = 0; trial < 3 && s == SFFT_OK; ++trial) {
+      double us = 0.0;
+      s = time_reps(reps, &us);
+      if (s == SFFT_OK && us < cbest) cbest = us;
     }
-    const double us = 1e3 * ms / reps;
-    if (us < best) {
-      best = us;
+    if (s != SFFT_OK) break;
+    if (cbest < best) {
+      best = cbest;
       bs = c.first;
       br = c.second;
     }
+    if (c.first == SFFT_SCHED_DEPTH && cbest < best_depth) {
+      best_depth = cbest;
+      bdr = c.second;
+    }
+  }
+  if (s == SFFT_OK && bs == SFFT_SCHED_BREADTH && best_depth < 1e300 && best > 0.97 * best_depth) {
+    bs = SFFT_SCHED_DEPTH;
+    br = bdr;
+    best = best_depth;
   }
   (void)hipStreamSynchronize(st);
   if (e0) (void)hipEventDestroy(e0);

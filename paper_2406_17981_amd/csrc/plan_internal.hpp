@@ -42,11 +42,15 @@ struct sfft_plan_s {
   // and the stored block components: comp_of[k] = a*b + c of stored component k
   int bsym = 0;
   int ns = 1;
-  int comp_of[9] = {0};
-  // mirrored symbol storage (compressed = 1)
+  int comp_of[16] = {0};
+  // mirrored symbol storage (compressed = 1): the declared per-(component,
+  // level) parity [(a*b + c)*d + l] (checked against the coefficients at
+  // creation and update) and, per stored component k, bit l of odd[k] set
+  // when that component is odd along level l
   int64_t mst[kMaxD] = {0};
   int64_t mcomp = 0;
-  uint64_t odd_bits = 0;
+  int32_t parity[16 * kMaxD] = {0};
+  uint8_t odd[16] = {0};
   // right-hand sides per leaf workgroup chosen by the autotuner (0: automatic)
   int rb_pref = 0;
   size_t table_bytes = 0;

@@ -327,6 +327,47 @@ __global__ void __launch_bounds__(256) k_block_symmetry(const double2* __restric
   }
 }
 
+// Declared per-(component, level) parity of the generator, checked exactly
+// (Section II.C storage relies on it): for every block component ab with a
+// declared parity and every level l, t(.., -r_l, ..)[ab] must equal
+// t(.., r_l, ..)[ab] (EVEN) or its negation (ODD) at every offset; bit l of
+// flags[ab] is set where it does not. The offset -r_l sits at index
+// 2(n_l - 1) - i_l of the index i_l of r_l.
+struct ParityCheck {
+  int d;
+  int nab;
+  int64_t st[kMaxD];       // strides of the offset array per level
+  int64_t ext[kMaxD];      // extents 2 n_l - 1
+  int8_t par[16 * kMaxD];  // [(a*b + c)*d + l]
+};
+
+__global__ void __launch_bounds__(256) k_parity_check(const double2* __restrict__ coeffs, int64_t ncoef,
+                                                      ParityCheck pc, unsigned* flags) {
+  __shared__ unsigned wg[16];
+  if (threadIdx.x < 16) wg[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t total = ncoef * pc.nab;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int ab = (int)(idx / ncoef);
+    const int64_t e = idx - (int64_t)ab * ncoef;
+    const double2 v = coeffs[idx];
+    unsigned bits = 0;
+    for (int l = 0; l < pc.d; ++l) {
+      const int pr = pc.par[ab * pc.d + l];
+      if (pr == SFFT_PARITY_NONE) continue;
+      const int64_t il = (e / pc.st[l]) % pc.ext[l];
+      const int64_t mirror = e + (pc.ext[l] - 1 - 2 * il) * pc.st[l];
+      const double2 w = coeffs[(int64_t)ab * ncoef + mirror];
+      const bool ok = pr == SFFT_PARITY_EVEN ? (w.x == v.x && w.y == v.y) : (w.x == -v.x && w.y == -v.y);
+      if (!ok) bits |= 1u << l;
+    }
+    if (bits) atomicOr(&wg[ab], bits);
+  }
+  __syncthreads();
+  if (threadIdx.x < (unsigned)pc.nab && wg[threadIdx.x]) atomicOr(&flags[threadIdx.x], wg[threadIdx.x]);
+}
+
 unsigned grid_for(int64_t total, int block = 256) {
   int64_t g = (total + block - 1) / block;
   if (g > 65536) g = 65536;
@@ -450,12 +491,12 @@ sfft_status run_leaf(const sfft_plan_s* p, const void* in, void* out, int64_t in
       a.mst[m] = p->mst[m];
     }
     a.mcomp = p->mcomp;
-    a.odd_bits = p->odd_bits;
-    f = o->leaf_mirror[p->b][p->bsym];
+    for (int k = 0; k < p->ns; ++k) a.odd[k] = p->odd[k];
+    f = o->leaf_mirror[p->b].f[p->bsym];
   } else {
     a.sym = (const char*)p->sym + (size_t)(q0 * p->sym_bs) * p->esz;
     a.sym_bs = p->sym_bs;
-    f = o->leaf[p->b][p->method == SFFT_SPLIT ? 2 : 1][p->bsym];
+    f = o->leaf[p->b].f[p->method == SFFT_SPLIT ? 2 : 1][p->bsym];
   }
   if (!f) return fail(SFFT_UNSUPPORTED, "no leaf kernel for this block size");
   ProfScope ps(p, SFFT_KIND_LEAF, st);
@@ -683,6 +724,44 @@ sfft_status detect_block_symmetry(const double2* coeffs, int b, int64_t ncoef, h
   return SFFT_OK;
 }
 
+// Checks a declared parity mask against the coefficients (k_parity_check);
+// SFFT_INVALID_ARG naming the first (component, level) where it fails.
+sfft_status check_parity(const double2* coeffs, int b, int d, const int64_t* n, const int32_t* parity,
+                         hipStream_t st) {
+  ParityCheck pc;
+  std::memset(&pc, 0, sizeof(pc));
+  pc.d = d;
+  pc.nab = b * b;
+  int64_t ncoef = 1;
+  for (int l = d - 1; l >= 0; --l) {
+    pc.st[l] = ncoef;
+    pc.ext[l] = 2 * n[l] - 1;
+    ncoef *= 2 * n[l] - 1;
+  }
+  for (int i = 0; i < b * b * d; ++i) pc.par[i] = (int8_t)parity[i];
+  unsigned* flags = nullptr;
+  HIP_TRY(tmp_alloc((void**)&flags, 16 * sizeof(unsigned), st), "parity flags allocation");
+  unsigned h[16] = {0};
+  hipError_t e = hipMemsetAsync(flags, 0, 16 * sizeof(unsigned), st);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_parity_check, dim3(grid_for(ncoef * b * b)), dim3(256), 0, st, coeffs, ncoef, pc, flags);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(h, flags, 16 * sizeof(unsigned), hipMemcpyDeviceToHost, st);
+  tmp_free(flags, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "parity check");
+  for (int ab = 0; ab < b * b; ++ab)
+    for (int l = 0; l < d; ++l)
+      if (h[ab] & (1u << l))
+        return fail(SFFT_INVALID_ARG, "declared parity " +
+                                          std::string(parity[ab * d + l] == SFFT_PARITY_EVEN ? "EVEN" : "ODD") +
+                                          " of block component (" + std::to_string(ab / b) + ", " +
+                                          std::to_string(ab % b) + ") along level " + std::to_string(l + 1) +
+                                          " does not hold for the coefficients");
+  return SFFT_OK;
+}
+
 sfft_status build_symbols(sfft_plan_s* p, const double2* coeffs, hipStream_t st) {
   const int d = p->d;
   Dims dm;
@@ -836,7 +915,7 @@ sfft_status sfft_plan_create(sfft_plan* out, int d, const int64_t* n, int b, con
   if (d < 1) return fail(SFFT_INVALID_ARG, "d must be >= 1");
   if (d > kMaxD) return fail(SFFT_UNSUPPORTED, "d > 6");
   if (b < 1) return fail(SFFT_INVALID_ARG, "b must be >= 1");
-  if (b != 1 && b != 3) return fail(SFFT_UNSUPPORTED, "block size must be 1 or 3");
+  if (b > 4) return fail(SFFT_INVALID_ARG, "block size must be 1, 2, 3 or 4");
   if (dtype != SFFT_C64 && dtype != SFFT_C128) return fail(SFFT_INVALID_ARG, "bad dtype");
   if (method != SFFT_SPLIT && method != SFFT_EMBED) return fail(SFFT_INVALID_ARG, "bad method");
   if (schedule < SFFT_SCHED_AUTO || schedule > SFFT_SCHED_DEPTH) return fail(SFFT_INVALID_ARG, "bad schedule");
@@ -883,6 +962,8 @@ sfft_status sfft_plan_create(sfft_plan* out, int d, const int64_t* n, int b, con
     for (int l = 0; l < d; ++l) bytes *= (double)(n[l] + 1);
     if (bytes >= 4294967296.0)
       return fail(SFFT_UNSUPPORTED, "mirrored storage holds at most 4 GiB per block component");
+    sfft_status sp = check_parity((const double2*)coeffs, b, d, n, parity, (hipStream_t)stream);
+    if (sp != SFFT_OK) return sp;
     mirror = true;
   }
 
@@ -903,13 +984,10 @@ sfft_status sfft_plan_create(sfft_plan* out, int d, const int64_t* n, int b, con
     p->L[l] = method == SFFT_SPLIT ? n[l] : 2 * n[l];
     p->ops[l] = find_ops(dtype, p->L[l]);
   }
-  // schedule: depth-first when the breadth-first workspace would exceed 8 GiB
-  if (schedule == SFFT_SCHED_AUTO) {
-    const double bw = (double)(((int64_t(1) << d) - 2) * max_nrhs * b * p->s) * p->esz;
-    p->sched = bw > 8.0 * (1 << 30) ? SFFT_SCHED_DEPTH : SFFT_SCHED_BREADTH;
-  } else {
-    p->sched = schedule;
-  }
+  // schedule: Algorithm 1's lazy depth-first order (peak (d+1) vectors with x
+  // and y) unless the caller asks otherwise; sfft_plan_autotune switches to
+  // breadth-first where that is measurably faster
+  p->sched = schedule == SFFT_SCHED_AUTO ? SFFT_SCHED_DEPTH : schedule;
   const AxisOps* lo = p->ops[d - 1];
   p->npen = 1;
   for (int l = 0; l < d - 1; ++l) p->npen *= p->L[l];
@@ -934,9 +1012,10 @@ sfft_status sfft_plan_create(sfft_plan* out, int d, const int64_t* n, int b, con
       p->mst[l] = p->mcomp;
       p->mcomp *= n[l] + 1;
     }
+    for (int i = 0; i < b * b * d; ++i) p->parity[i] = parity[i];
     for (int k = 0; k < p->ns; ++k)
       for (int l = 0; l < d; ++l)
-        if (parity[p->comp_of[k] * d + l] == SFFT_PARITY_ODD) p->odd_bits |= uint64_t(1) << (k * 6 + l);
+        if (parity[p->comp_of[k] * d + l] == SFFT_PARITY_ODD) p->odd[k] |= (uint8_t)(1u << l);
     p->sym_bs = 0;
     p->sym_bytes = (size_t)(p->ns * p->mcomp) * p->esz;
   } else {
@@ -971,6 +1050,10 @@ sfft_status sfft_plan_update(sfft_plan plan, const void* coeffs, void* stream) {
   if (bsym != plan->bsym)
     return fail(SFFT_INVALID_ARG, "block symmetry " + std::to_string(bsym) + " differs from the plan's " +
                                       std::to_string(plan->bsym));
+  if (plan->compressed) {
+    s = check_parity((const double2*)coeffs, plan->b, plan->d, plan->n, plan->parity, st);
+    if (s != SFFT_OK) return s;
+  }
   return build_symbols(plan, (const double2*)coeffs, st);
 }
 

@@ -49,12 +49,13 @@ def test_argument_validation_without_a_device():
     assert N.lib.sfft_plan_create(None, 3, n, 1, fake, 0, 0, None, 1, 0, None) == N.INVALID_ARG
     assert N.lib.sfft_plan_create(ctypes.byref(h), 0, n, 1, fake, 0, 0, None, 1, 0, None) == N.INVALID_ARG
     assert N.lib.sfft_plan_create(ctypes.byref(h), 7, n, 1, fake, 0, 0, None, 1, 0, None) == N.UNSUPPORTED
-    assert N.lib.sfft_plan_create(ctypes.byref(h), 3, n, 2, fake, 0, 0, None, 1, 0, None) == N.UNSUPPORTED
+    assert N.lib.sfft_plan_create(ctypes.byref(h), 3, n, 5, fake, 0, 0, None, 1, 0, None) == N.INVALID_ARG
+    assert b"block size" in N.lib.sfft_last_error()
     assert N.lib.sfft_plan_create(ctypes.byref(h), 3, n, 1, None, 0, 0, None, 1, 0, None) == N.INVALID_ARG
     assert N.lib.sfft_plan_create(ctypes.byref(h), 3, n, 1, fake, 5, 0, None, 1, 0, None) == N.INVALID_ARG
-    n7 = (ctypes.c_int64 * 3)(16, 7, 16)
-    assert N.lib.sfft_plan_create(ctypes.byref(h), 3, n7, 1, fake, 0, 0, None, 1, 0, None) == N.UNSUPPORTED
-    assert b"7" in N.lib.sfft_last_error() or b"14" in N.lib.sfft_last_error()
+    n11 = (ctypes.c_int64 * 3)(16, 11, 16)  # prime factor 11: outside {2, 3, 5, 7}
+    assert N.lib.sfft_plan_create(ctypes.byref(h), 3, n11, 1, fake, 0, 0, None, 1, 0, None) == N.UNSUPPORTED
+    assert b"11" in N.lib.sfft_last_error() or b"22" in N.lib.sfft_last_error()
     assert N.lib.sfft_apply(None, fake, fake, 1, None, 0, None) == N.INVALID_ARG
     assert N.lib.sfft_plan_update(None, fake, None) == N.INVALID_ARG
     assert b"null" in N.lib.sfft_last_error()

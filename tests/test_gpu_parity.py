@@ -162,6 +162,48 @@ def test_long_levels_match_oracle(sf, grid, b, dtype):
         assert err <= TOL[dtype], (sched, err)
 
 
+MIXED_RADIX = [((6, 80), 3), ((96, 10), 1), ((10, 96), 3), ((80, 12), 1), ((384, 6), 3), ((6, 384), 1),
+               ((4, 80, 96), 3), ((96, 6, 80), 1), ((384, 4, 6), 3)]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("grid,b", MIXED_RADIX)
+def test_mixed_radix_levels_match_oracle(sf, grid, b, dtype):
+    """Levels of length 80 ([2,8,5] passes, [5,4,4] leaf), 96 ([4,8,3] / [2,4,4,3])
+    and 384 ([4,8,4,3] / [2,4,4,4,3]) in the strided and the leaf position, whose
+    FP64 symbols come from 160-, 192- and 768-point transforms; these are the
+    lengths of the uneven-grid batch (96 x 80 x 64, 512 x 384) and of the 96^3
+    serving grid. Every output against the FP64 oracle, both schedules."""
+    coeffs = wl.iid_coeffs(71, grid, b)
+    x = wl.vectors(72, grid, b, 2)
+    want = oracle.embed_matvec(coeffs, x)
+    for sched in ("breadth", "depth"):
+        got = _run(sf, coeffs, x, dtype, "split", sched)
+        err = wl.relative_l2(got, want)
+        _say(f"mixed radix {grid} b={b} {dtype} {sched} rel_l2={err:.3e}")
+        assert err <= TOL[dtype], (sched, err)
+    got = _run(sf, coeffs, x, dtype, "embed")
+    assert wl.relative_l2(got, want) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("grid", [(6, 80), (96, 10), (384, 6), (6, 384), (4, 80, 96), (96, 6, 80)])
+def test_mixed_radix_levels_mirrored(sf, grid, dtype):
+    """Green blocks stored mirrored (Section II.C) on levels of length 80, 96 and
+    384: the leaf's mirror reads (bin M > n read as 2n - M) on odd lengths of the
+    even-bin and odd-bin halves, both schedules."""
+    coeffs = wl.green_coeffs(grid, 0.6)
+    x = wl.vectors(73, grid, 3, 2)
+    want = oracle.embed_matvec(coeffs, x)
+    for sched in ("breadth", "depth"):
+        info = {}
+        got = _run(sf, coeffs, x, dtype, "split", sched, parity=wl.green_parity(len(grid)), info=info)
+        assert info["compressed"] == 1
+        err = wl.relative_l2(got, want)
+        _say(f"mixed radix mirrored {grid} {dtype} {sched} rel_l2={err:.3e}")
+        assert err <= TOL[dtype], (sched, err)
+
+
 @pytest.mark.parametrize("grid,nrhs", [((64, 64, 64), 16), ((64, 24, 10), 401)])
 def test_large_launch_matches_single_rhs_applies(sf, grid, nrhs):
     """b=3, complex64, breadth-first, many right-hand sides: 64^3 with 16 of them
@@ -255,10 +297,91 @@ def test_mirrored_symbols_odd_scalar(sf, grid):
     par = np.full((1, 1, len(grid)), wl.ODD, dtype=np.int32)
     got = _run(sf, coeffs, x, "c128", "split", parity=par)
     assert wl.relative_l2(got, want) <= 1e-12
-    # declaring the wrong symmetry gives a wrong product (the declaration is trusted)
+    # a declared symmetry that the coefficients do not have is refused at
+    # plan creation (checked exactly on the device), naming the level
     bad = np.full((1, 1, len(grid)), wl.EVEN, dtype=np.int32)
-    got = _run(sf, coeffs, x, "c128", "split", parity=bad)
-    assert wl.relative_l2(got, want) > 1e-3
+    with pytest.raises(sf.SfftError, match="INVALID_ARG.*level 1"):
+        sf.Plan(grid, 1, torch.from_numpy(coeffs).cuda(), dtype="c128", parity=bad)
+    # one level wrong, the others right: still refused
+    bad = par.copy()
+    bad[0, 0, -1] = wl.EVEN
+    with pytest.raises(sf.SfftError, match=f"level {len(grid)}"):
+        sf.Plan(grid, 1, torch.from_numpy(coeffs).cuda(), dtype="c128", parity=bad)
+
+
+def test_declared_parity_checked_exactly(sf):
+    """The parity check is exact: a single coefficient changed by one ulp
+    breaks it, at creation and at update (where the plan keeps its symbols)."""
+    grid = (6, 10, 12)
+    green = wl.green_coeffs(grid, 0.9)
+    par = wl.green_parity(3)
+    near = green.copy()
+    near[0, 1, 2, 3, 4] = np.nextafter(near[0, 1, 2, 3, 4].real, np.inf) + 1j * near[0, 1, 2, 3, 4].imag
+    with pytest.raises(sf.SfftError, match="component \\(0, 1\\)"):
+        sf.Plan(grid, 3, torch.from_numpy(near).cuda(), dtype="c64", parity=par)
+    x = torch.from_numpy(wl.vectors(24, grid, 3, 1).astype(np.complex64)).cuda()
+    plan = sf.Plan(grid, 3, torch.from_numpy(green).cuda(), dtype="c64", parity=par)
+    y0 = plan.apply(x)
+    # block-symmetric but with one (0,1)/(1,0) pair perturbed alike: same
+    # block symmetry, broken parity
+    near[1, 0, 2, 3, 4] = near[0, 1, 2, 3, 4]
+    with pytest.raises(sf.SfftError, match="INVALID_ARG"):
+        plan.update(torch.from_numpy(near).cuda())
+    assert torch.equal(plan.apply(x), y0)
+    plan.close()
+
+
+def _blocks_with_symmetry(seed, grid, b, kind):
+    c = wl.iid_coeffs(seed, grid, b)
+    if kind == "sym":
+        c = c + np.swapaxes(c, 0, 1)
+    elif kind == "anti":
+        c = c - np.swapaxes(c, 0, 1)
+    return c
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("b", [2, 4])
+@pytest.mark.parametrize("grid", [(24,), (10, 12), (6, 10, 12), (16, 8, 64), (4, 3, 2, 5)])
+def test_block_sizes_two_and_four(sf, grid, b, dtype):
+    """b = 2 and b = 4 blocks (Algorithm 1's block data T[bId] for any block
+    size): general blocks and exactly (anti)symmetric ones, whose b(b+1)/2
+    stored components the plan detects, against the FP64 oracle, both
+    schedules and the embedding baseline."""
+    x = wl.vectors(81, grid, b, 2)
+    for kind, bs in (("iid", 0), ("sym", 1), ("anti", 2)):
+        coeffs = _blocks_with_symmetry(80, grid, b, kind)
+        want = oracle.dense_matvec(coeffs, x) if math.prod(grid) * b <= 4096 else oracle.embed_matvec(coeffs, x)
+        for sched in ("breadth", "depth"):
+            info = {}
+            got = _run(sf, coeffs, x, dtype, "split", sched, info=info)
+            assert info["block_symmetry"] == bs, kind
+            err = wl.relative_l2(got, want)
+            _say(f"b={b} {grid} {kind} {dtype} {sched} rel_l2={err:.3e}")
+            assert err <= TOL[dtype], (kind, sched, err)
+        got = _run(sf, coeffs, x, dtype, "embed")
+        assert wl.relative_l2(got, want) <= TOL[dtype], (kind, "embed")
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("b", [1, 2, 4])
+@pytest.mark.parametrize("grid", [(10, 12), (6, 10, 12), (5, 8, 16)])
+def test_mirrored_storage_any_block_size(sf, grid, b, dtype):
+    """Mirrored symbols (Section II.C) for blocks of 1, 2 and 4 with a random
+    even/odd pattern per (component, level), coefficients exactly of that
+    parity."""
+    d = len(grid)
+    par = np.random.default_rng(82 + b).integers(1, 3, (b, b, d)).astype(np.int32)
+    coeffs = wl.parity_coeffs(83, grid, b, par)
+    x = wl.vectors(84, grid, b, 2)
+    want = oracle.embed_matvec(coeffs, x)
+    for sched in ("breadth", "depth"):
+        info = {}
+        got = _run(sf, coeffs, x, dtype, "split", sched, parity=par, info=info)
+        assert info["compressed"] == 1
+        err = wl.relative_l2(got, want)
+        _say(f"mirrored b={b} {grid} {dtype} {sched} rel_l2={err:.3e}")
+        assert err <= TOL[dtype], (sched, err)
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
@@ -274,13 +397,16 @@ def test_green_64_mirrored_full_size(sf, green64, dtype):
 
 
 @pytest.fixture(scope="module")
-def large_points():
-    rng = np.random.default_rng(5020)
-    n = wl.LARGE_256["n"]
-    pts = np.stack([rng.integers(0, v, 4) for v in n], axis=1)
-    # corners: the projection boundary
-    extra = np.array([[0, 0, 0], [n[0] - 1, n[1] - 1, n[2] - 1], [0, n[1] - 1, n[2] // 2]])
-    return np.concatenate([pts, extra])
+def large_golden():
+    """FP64 oracle values of the 256 x 256 x 128 products at 128 grid points
+    (tests/golden/make_large_rows.py: corners, both ends of every axis, first
+    and last pencils of leaf tiles, random interior points)."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "large_256_rows.npz")
+    g = np.load(path)
+    cfg = wl.LARGE_256
+    assert tuple(g["n"]) == tuple(cfg["n"]) and float(g["k"]) == cfg["k"] and int(g["seed_x"]) == cfg["seed_x"]
+    return {k: g[k] for k in g.files}
 
 
 def _large_case(sf, coeffs, x, pts, dtype, parity, schedule):
@@ -300,25 +426,57 @@ def _large_case(sf, coeffs, x, pts, dtype, parity, schedule):
     return got, info
 
 
-def test_large_green_and_skew_full_size(sf, large_points):
+def test_large_green_and_skew_full_size(sf, large_golden):
     """256 x 256 x 128 grid, 3x3 blocks, 8 right-hand sides, complex64 (FP64 symbols):
-    Green k=1.3 (general and mirrored symbols) and the skew-symmetric kernel
-    (mirrored), each against direct sums at sampled output points."""
+    Green k=1.3 and the skew-symmetric kernel, general and mirrored symbols, both
+    schedules, each against the stored FP64 oracle values at 128 grid points of
+    every right-hand side (per-point relative error too, so one wrong pencil or
+    tile cannot hide in the norm)."""
     cfg = wl.LARGE_256
     n, nrhs = cfg["n"], cfg["nrhs"]
+    pts = large_golden["points"]
     x = wl.vectors(cfg["seed_x"], n, 3, nrhs)
     for name, make, par in (("green", lambda: wl.green_coeffs(n, cfg["k"]), wl.green_parity(3)),
                             ("skew", lambda: wl.skew_coeffs(n, cfg["k"]), wl.skew_parity(3))):
         coeffs = make()
-        want = oracle.sampled_rows(coeffs, x, large_points)
-        cases = [(par, "depth")] if name == "skew" else [(None, "depth"), (par, "breadth")]
+        want = large_golden[name]
+        cases = [(None, "depth"), (par, "depth")] if name == "skew" else \
+            [(None, "depth"), (None, "breadth"), (par, "depth"), (par, "breadth")]
         for parity, sched in cases:
-            got, info = _large_case(sf, coeffs, x, large_points, "c64", parity, sched)
+            got, info = _large_case(sf, coeffs, x, pts, "c64", parity, sched)
             err = wl.relative_l2(got, want)
-            _say(f"large {name} mirrored={parity is not None} rel_l2={err:.3e} "
+            scale = np.linalg.norm(want, axis=(0, 1)).max()
+            worst = float(np.abs(got - want).max() / scale)
+            _say(f"large {name} mirrored={parity is not None} {sched} rel_l2={err:.3e} worst={worst:.3e} "
                  f"symbol_bytes={info['symbol_bytes']} workspace={info['workspace_bytes']}")
             assert err <= 1e-5
+            assert worst <= 1e-5
         del coeffs
+
+
+def test_serving_grid_96(sf):
+    """The 96^3 grid of the serving stream (every level of length 96: [4,8,3]
+    passes, [2,4,4,3] leaf, 192-point FP64 symbol transforms), 3x3 Green blocks,
+    complex64, depth-first as the server runs it, general and mirrored symbols,
+    against direct sums at sampled points and the grid's corners."""
+    n = (96, 96, 96)
+    coeffs = wl.green_coeffs(n, 1.1)
+    x = wl.vectors(63, n, 3, 1)
+    rng = np.random.default_rng(64)
+    corners = np.array([[0, 0, 0], [95, 95, 95], [0, 0, 95], [95, 0, 0], [0, 95, 0], [48, 47, 95]])
+    pts = np.concatenate([np.stack([rng.integers(0, 96, 26) for _ in range(3)], axis=1), corners])
+    want = oracle.sampled_rows(coeffs, x, pts)
+    idx = torch.from_numpy(np.ravel_multi_index(pts.T, n)).cuda()
+    for parity in (None, wl.green_parity(3)):
+        _say(f"serving grid n={n} mirrored={parity is not None}")
+        plan = sf.Plan(n, 3, torch.from_numpy(coeffs).cuda(), dtype="c64", parity=parity, max_nrhs=1,
+                       schedule="depth")
+        y = plan.apply(torch.from_numpy(x.astype(np.complex64)).cuda())
+        got = y.reshape(1, 3, -1)[:, :, idx].cpu().numpy().astype(np.complex128)
+        plan.close()
+        err = wl.relative_l2(got, want)
+        _say(f"serving grid 96^3 mirrored={parity is not None} rel_l2={err:.3e}")
+        assert err <= TOL["c64"]
 
 
 @pytest.mark.parametrize("mirrored", [False, True])

@@ -187,6 +187,29 @@ def skew_parity(d: int) -> np.ndarray:
     return m
 
 
+def parity_coeffs(seed: int, n: Sequence[int], b: int, parity: np.ndarray) -> np.ndarray:
+    """I.i.d. complex-normal coefficients made exactly even or odd per
+    (component, level): parity is an int array (b, b, d) of EVEN / ODD / NONE;
+    along a level marked EVEN the array is replaced by (c + c mirrored)/2,
+    along one marked ODD by (c - c mirrored)/2 (its r_l = 0 plane becomes 0).
+    Mirroring an axis of offsets maps r_l to -r_l; the two halves are formed by
+    the same IEEE operations, so the symmetry holds bit for bit."""
+    n = _grid(n)
+    c = iid_coeffs(seed, n, b)
+    parity = np.asarray(parity).reshape(b, b, len(n))
+    for a in range(b):
+        for cc in range(b):
+            comp = c[a, cc]
+            for l in range(len(n)):
+                f = np.flip(comp, axis=l)
+                if parity[a, cc, l] == EVEN:
+                    comp = (comp + f) / 2
+                elif parity[a, cc, l] == ODD:
+                    comp = (comp - f) / 2
+            c[a, cc] = comp
+    return c
+
+
 def delta_coeffs(n: Sequence[int], b: int = 1) -> np.ndarray:
     """t(0) = I, t(r != 0) = 0: the identity matrix."""
     n = _grid(n)
