@@ -182,6 +182,31 @@ def pmc_summarize(fetch_dir, write_dir, out_path):
     print(json.dumps(rec))
 
 
+def prof_summarize(db_path, out_path, title, command):
+    """Kernel statistics from a rocprofv3 results database (--kernel-trace):
+    launches, mean / min / max duration per kernel and workgroup count, with
+    the registers and LDS of each kernel, as a Markdown table."""
+    import sqlite3
+    con = sqlite3.connect(db_path)
+    rows = con.execute(
+        "select name, grid_x / workgroup_x, count(*), avg(duration), min(duration), max(duration), "
+        "sum(duration), max(vgpr_count), max(lds_size) from kernels group by name, grid_x, workgroup_x "
+        "order by sum(duration) desc").fetchall()
+    total = sum(r[6] for r in rows)
+    lines = [f"# {title}", "", "Command (repository root, one MI355X):", "```", command, "```", "",
+             "| kernel | workgroups | launches | mean (us) | min (us) | max (us) | share of kernel time | VGPRs | LDS (B) |",
+             "|---|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    for name, wg, cnt, avg, mn, mx, tot, vgpr, lds in rows:
+        short = name.replace("(sfft::PassArgs)", "").replace("void ", "")
+        if len(short) > 90:
+            short = short[:87] + "..."
+        lines.append(f"| `{short}` | {wg} | {cnt} | {avg / 1e3:.1f} | {mn / 1e3:.1f} | {mx / 1e3:.1f} | "
+                     f"{100.0 * tot / total:.1f}% | {vgpr} | {lds} |")
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(f"wrote {out_path}")
+
+
 # kernels of one depth-first 256x256x128 apply (8 right-hand sides) and their
 # algorithmic bytes per launch: a leaf reads and writes one branch vector
 # (1.61 GB each) and reads the quarter of the 3.22 GB of symbols its branch
@@ -248,15 +273,16 @@ def cpu_baseline_large(coeffs, x_host, budget_s):
     timed loop) on one right-hand side of the 256x256x128 workload, with
     scipy.fft using all host cores and then one core."""
     import oracle
+    import oracle.toeplitz as OT
     cores = len(os.sched_getaffinity(0))
-    oracle.set_workers(cores)
+    OT.set_workers(cores)
     t0 = time.perf_counter()
     C = oracle.embed_symbol(coeffs)
     t_sym = time.perf_counter() - t0
     log(f"[cpu] embedded symbol in {t_sym:.1f} s ({cores} workers)")
     runs, ref = {}, None
     for workers, budget in ((cores, budget_s), (1, 0.0)):
-        oracle.set_workers(workers)
+        OT.set_workers(workers)
         reps, t0 = 0, time.perf_counter()
         while True:
             y = oracle.embed_matvec_with_symbol(C, x_host[:1])
@@ -268,7 +294,7 @@ def cpu_baseline_large(coeffs, x_host, budget_s):
         wall = time.perf_counter() - t0
         runs[workers] = dict(matvecs_per_s=round(reps / wall, 5), reps=reps, wall_s=round(wall, 2))
         log(f"[cpu] workers={workers}: {reps} matvecs in {wall:.1f} s")
-    oracle.set_workers(None)
+    OT.set_workers(None)
     del C
     best = runs[cores]
     return ref, dict(value=best["matvecs_per_s"], unit="matvecs/s", cores=cores, kind="oracle",
@@ -832,6 +858,8 @@ def main():
                          "green64: the 64^3 one-RHS configuration; "
                          "batch: 8 uneven-grid problems, 64 RHS, one graph; serve: the Poisson stream")
     ap.add_argument("--pmc-summarize", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON"))
+    ap.add_argument("--prof-summarize", nargs=4, metavar=("RESULTS_DB", "OUT_MD", "TITLE", "COMMAND"),
+                    help="write a kernel-statistics table from a rocprofv3 --kernel-trace results database")
     args = ap.parse_args()
     steps_default, warmup_default = {"large": (20, 5), "batch": (50, 5), "green64": (1000, 2000)}.get(
         args.workload, (1, 0))
@@ -840,6 +868,9 @@ def main():
     if args.warmup is None:
         args.warmup = warmup_default
 
+    if args.prof_summarize:
+        prof_summarize(*args.prof_summarize)
+        return
     if args.pmc_summarize:
         (pmc_summarize_large if args.workload == "large" else pmc_summarize)(*args.pmc_summarize)
         return

@@ -85,6 +85,7 @@ typedef struct {
   int64_t vector_elems;    /* b * prod(n_l): entries of one right-hand side */
   int block_symmetry;      /* 0, or 1 / 2 when t[a,c] = t[c,a] / -t[c,a] at every offset:
                               the symbol then stores the b(b+1)/2 components a <= c */
+  size_t adjoint_symbol_bytes; /* device bytes of the T^H symbols (0 until sfft_plan_enable_adjoint) */
 } sfft_info;
 
 /* Build a plan and its Fourier-space symbols.
@@ -154,6 +155,19 @@ sfft_status sfft_workspace_size(sfft_plan plan, int64_t nrhs, size_t* bytes);
 sfft_status sfft_apply(sfft_plan plan, const void* x, void* y, int64_t nrhs, void* workspace,
                        size_t ws_bytes, void* stream);
 
+/* The conjugate transpose, y = T^H x: T^H is block Toeplitz with generator
+ * t^H(r) = t(-r)^H, whose embedded symbol is the conjugate transpose of T's at
+ * every bin (Section II's embedding with the generator reversed), so the
+ * plan's parity parts T[bId] serve it conjugated and transposed.
+ * sfft_plan_enable_adjoint allocates and fills these symbols once (the
+ * plan's symbol size again; synchronises `stream`); sfft_plan_update refreshes
+ * them. sfft_apply_adjoint takes the arguments and workspace of sfft_apply,
+ * allocates nothing, and returns SFFT_INVALID_ARG before the adjoint is
+ * enabled. */
+sfft_status sfft_plan_enable_adjoint(sfft_plan plan, void* stream);
+sfft_status sfft_apply_adjoint(sfft_plan plan, const void* x, void* y, int64_t nrhs, void* workspace,
+                               size_t ws_bytes, void* stream);
+
 /* Several independent products in one call: problem i is plans[i] applied to
  * x[i] -> y[i] with nrhs[i] right-hand sides (host arrays of device
  * pointers; workspace at least sfft_workspace_size_multi bytes, problem i at
@@ -198,6 +212,39 @@ sfft_status sfft_arnoldi_scratch_size(int njobs, const sfft_arnoldi_job* jobs, s
 sfft_status sfft_arnoldi_step_multi(int njobs, const sfft_arnoldi_job* jobs, int dtype, void* scratch,
                                     size_t scratch_bytes, void* stream);
 
+/* Restarted GMRES(m) for the scattering operator A = I - diag(chi) T (T the
+ * plans' block-Toeplitz matrix, chi a per-entry susceptibility, typically
+ * nonzero on a small region): the Krylov solve whose matvecs the split
+ * product accelerates (the paper's introduction). Mixed-precision iterative
+ * refinement: every cycle runs up to m Arnoldi steps with products of `lo`
+ * (complex64 or complex128), each step's Hessenberg column comes back to the
+ * host for Givens rotations, the correction is added to x in FP64, and the
+ * true residual b - A x is recomputed in FP64 with `hi` (a complex128 plan of
+ * the same operator; it may be lo itself when lo is complex128). Stops when
+ * ||b - A x|| <= tol ||b|| or after max_cycles cycles.
+ *   chi, rhs  device complex128 (b, n_1, ..., n_d): the diagonal of chi and b.
+ *   x         device complex128 (b, n...): the initial guess on entry, the
+ *             solution on return.
+ *   m         Krylov steps per cycle, 1..64.
+ *   workspace device, sfft_gmres_workspace_size bytes; nothing is allocated.
+ *   stream    every kernel runs on it; the call returns when the solve is done
+ *             (it synchronises after each Arnoldi step to read H).
+ *   info      host, may be NULL: cycles, products and the final FP64 relative
+ *             residual (recomputed, not estimated). */
+typedef struct {
+  int64_t cycles;                /* restart cycles run */
+  int64_t matvecs;               /* products with T in lo's dtype */
+  int64_t fp64_matvecs;          /* products with T in FP64 (true residuals) */
+  double rel_residual;           /* ||b - A x|| / ||b||, FP64, at return */
+  double rel_residual_estimate;  /* the last inner least-squares estimate */
+  int converged;                 /* rel_residual <= tol */
+} sfft_gmres_info;
+
+sfft_status sfft_gmres_workspace_size(sfft_plan lo, sfft_plan hi, int m, size_t* bytes);
+sfft_status sfft_gmres_solve(sfft_plan lo, sfft_plan hi, const void* chi, const void* rhs, void* x, int m,
+                             int max_cycles, double tol, void* workspace, size_t ws_bytes, void* stream,
+                             sfft_gmres_info* info);
+
 /* Times the plan's candidate schedules (breadth-first and depth-first for
  * SFFT_SPLIT with d > 1) and leaf right-hand-side groupings (1, 2, 4, 8 per
  * workgroup, within the kernel's limit) at nrhs right-hand sides on `stream`,
@@ -234,7 +281,10 @@ sfft_status sfft_plan_destroy(sfft_plan plan);
 const char* sfft_status_string(sfft_status s);
 /* Message of the calling thread's last failed call ("" if none). */
 const char* sfft_last_error(void);
-/* 1 if kernels for pencil length L are built, else 0. */
+/* Kernels for pencil length L: 1 when length-specialised kernels are built
+ * (register-resident radix plans), 2 when L is served by the runtime-length
+ * kernels (2 <= L <= 4096 with prime factors in {2, 3, 5, 7}: pencil tiles
+ * staged whole in LDS), 0 otherwise. */
 int sfft_length_supported(int64_t L);
 
 #ifdef __cplusplus

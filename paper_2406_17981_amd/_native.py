@@ -27,6 +27,7 @@ EXPORTS = [
     "sfft_apply_multi", "sfft_plan_info", "sfft_plan_destroy", "sfft_status_string",
     "sfft_last_error", "sfft_length_supported", "sfft_profile_enable", "sfft_profile_read",
     "sfft_plan_autotune", "sfft_arnoldi_scratch_size", "sfft_arnoldi_step_multi", "sfft_plan_update",
+    "sfft_plan_enable_adjoint", "sfft_apply_adjoint", "sfft_gmres_workspace_size", "sfft_gmres_solve",
 ]
 KIND_FORWARD, KIND_LEAF, KIND_INVERSE, KIND_COPY = range(4)
 
@@ -37,6 +38,7 @@ class SfftInfo(C.Structure):
         ("method", C.c_int), ("schedule", C.c_int), ("compressed", C.c_int),
         ("max_nrhs", C.c_int64), ("symbol_bytes", C.c_size_t), ("table_bytes", C.c_size_t),
         ("workspace_bytes", C.c_size_t), ("vector_elems", C.c_int64), ("block_symmetry", C.c_int),
+        ("adjoint_symbol_bytes", C.c_size_t),
     ]
 
 
@@ -44,6 +46,13 @@ class ArnoldiJob(C.Structure):
     _fields_ = [
         ("V", C.c_void_p), ("ldv", C.c_int64), ("m", C.c_int64), ("w", C.c_void_p),
         ("vout", C.c_void_p), ("n", C.c_int64), ("hcol", C.c_void_p),
+    ]
+
+
+class GmresInfo(C.Structure):
+    _fields_ = [
+        ("cycles", C.c_int64), ("matvecs", C.c_int64), ("fp64_matvecs", C.c_int64),
+        ("rel_residual", C.c_double), ("rel_residual_estimate", C.c_double), ("converged", C.c_int),
     ]
 
 
@@ -69,6 +78,11 @@ def _load():
     lib.sfft_plan_info.argtypes = [vp, C.POINTER(SfftInfo)]
     lib.sfft_plan_destroy.argtypes = [vp]
     lib.sfft_plan_update.argtypes = [vp, vp, vp]
+    lib.sfft_plan_enable_adjoint.argtypes = [vp, vp]
+    lib.sfft_apply_adjoint.argtypes = [vp, vp, vp, i64, vp, sz, vp]
+    lib.sfft_gmres_workspace_size.argtypes = [vp, vp, C.c_int, C.POINTER(sz)]
+    lib.sfft_gmres_solve.argtypes = [vp, vp, vp, vp, vp, C.c_int, C.c_int, C.c_double, vp, sz, vp,
+                                     C.POINTER(GmresInfo)]
     lib.sfft_status_string.argtypes = [C.c_int]
     lib.sfft_status_string.restype = C.c_char_p
     lib.sfft_last_error.argtypes = []

@@ -58,6 +58,8 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     units.append((os.path.join(CSRC, "runtime.hip"), os.path.join(BUILD, "runtime.o"), []))
     units.append((os.path.join(CSRC, "batch.hip"), os.path.join(BUILD, "batch.o"), []))
     units.append((os.path.join(CSRC, "krylov.hip"), os.path.join(BUILD, "krylov.o"), []))
+    units.append((os.path.join(CSRC, "generic_kernels.hip"), os.path.join(BUILD, "generic_kernels.o"), []))
+    units.append((os.path.join(CSRC, "gmres.hip"), os.path.join(BUILD, "gmres.o"), []))
     # biggest lengths first so the slowest compiles start early
     units.sort(key=lambda u: -int(re.search(r"(\d+)", os.path.basename(u[1])).group(1))
                if "kernels_L" in u[1] else 0)

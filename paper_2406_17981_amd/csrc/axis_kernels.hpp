@@ -64,6 +64,7 @@ struct PassArgs {
   int64_t outer;     // per branch: pencils along the axis are (outer, inner)
   int64_t inner;
   const void* tw;    // 2L entries exp(-i pi m / L)
+  int64_t len;       // pencil length L (read by the runtime-length kernels only)
   int use_phase;     // FWD2/INV2: multiply the odd child by Phi / conj(Phi)
   // LEAF only
   const void* sym;   // symbols for branch q at sym + q*sym_bs
@@ -716,6 +717,7 @@ struct AxisOps {
   };
   LeafRow leaf[5];    // [B]: general symbol storage, null where not built
   MirRow leaf_mirror[5];  // [B]: NPAR = 2, mirrored symbol storage
+  int generic;        // 1: runtime-length kernels (pencil tiles staged whole in LDS)
 };
 
 constexpr int64_t kIdx32 = (int64_t)1 << 31;
@@ -841,6 +843,7 @@ template <typename Real, int L> const AxisOps* make_ops() {
        leaf_row_general<Real, L, 4>()},
       {{}, leaf_row_mirror<Real, L, 1>(), leaf_row_mirror<Real, L, 2>(), leaf_row_mirror<Real, L, 3>(),
        leaf_row_mirror<Real, L, 4>()},
+      0,
   };
   return &ops;
 }

@@ -124,6 +124,37 @@ template <int DIR, typename C> __device__ __forceinline__ void dft5(C* v) {
   v[3] = csub(e2, o2);
 }
 
+// Radix 7: with p_j = v_j + v_{7-j} and m_j = v_j - v_{7-j} (j = 1..3),
+// X[k] = v_0 + sum_j p_j cos(2 pi jk/7) + DIR i sum_j m_j sin(2 pi jk/7) and
+// X[7-k] the same with the sine sum negated (k = 1..3).
+template <int DIR, typename C> __device__ __forceinline__ void dft7(C* v) {
+  using R = decltype(C::x);
+  const R c1 = (R)0.62348980185873353052500488400424;   // cos(2 pi / 7)
+  const R c2 = (R)-0.22252093395631440428890256449680;  // cos(4 pi / 7)
+  const R c3 = (R)-0.90096886790241912623610231950745;  // cos(6 pi / 7)
+  const R s1 = (R)0.78183148246802980870844452667406;   // sin(2 pi / 7)
+  const R s2 = (R)0.97492791218182360701813168299393;   // sin(4 pi / 7)
+  const R s3 = (R)0.43388373911755812047576833284836;   // sin(6 pi / 7)
+  const C a0 = v[0];
+  const C p1 = cadd(v[1], v[6]), m1 = csub(v[1], v[6]);
+  const C p2 = cadd(v[2], v[5]), m2 = csub(v[2], v[5]);
+  const C p3 = cadd(v[3], v[4]), m3 = csub(v[3], v[4]);
+  // cos(2 pi jk/7) and sin(2 pi jk/7) for jk mod 7 = 4, 5, 6 are c3, c2, c1 and -s3, -s2, -s1
+  const C e1 = cadd(a0, cadd(cscale(p1, c1), cadd(cscale(p2, c2), cscale(p3, c3))));
+  const C e2 = cadd(a0, cadd(cscale(p1, c2), cadd(cscale(p2, c3), cscale(p3, c1))));
+  const C e3 = cadd(a0, cadd(cscale(p1, c3), cadd(cscale(p2, c1), cscale(p3, c2))));
+  const C o1 = mul_di<DIR>(cadd(cscale(m1, s1), cadd(cscale(m2, s2), cscale(m3, s3))));
+  const C o2 = mul_di<DIR>(csub(cscale(m1, s2), cadd(cscale(m2, s3), cscale(m3, s1))));
+  const C o3 = mul_di<DIR>(cadd(csub(cscale(m1, s3), cscale(m2, s1)), cscale(m3, s2)));
+  v[0] = cadd(a0, cadd(p1, cadd(p2, p3)));
+  v[1] = cadd(e1, o1);
+  v[6] = csub(e1, o1);
+  v[2] = cadd(e2, o2);
+  v[5] = csub(e2, o2);
+  v[3] = cadd(e3, o3);
+  v[4] = csub(e3, o3);
+}
+
 template <int DIR, typename C> __device__ __forceinline__ void dft8(C* v) {
   using R = decltype(C::x);
   const R h = (R)0.70710678118654752440084436210485;  // sqrt(1/2)
@@ -266,6 +297,7 @@ template <int R, int DIR, typename C> __device__ __forceinline__ void dft(C* v) 
   else if constexpr (R == 3) dft3<DIR>(v);
   else if constexpr (R == 4) dft4<DIR>(v);
   else if constexpr (R == 5) dft5<DIR>(v);
+  else if constexpr (R == 7) dft7<DIR>(v);
   else if constexpr (R == 8) dft8<DIR>(v);
   else if constexpr (R == 16) dft16<DIR>(v);
   else static_assert(R == 2, "unsupported radix");

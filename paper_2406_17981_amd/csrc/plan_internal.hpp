@@ -51,6 +51,11 @@ struct sfft_plan_s {
   int64_t mcomp = 0;
   int32_t parity[16 * kMaxD] = {0};
   uint8_t odd[16] = {0};
+  // symbols of the conjugate transpose T^H (sfft_plan_enable_adjoint): the
+  // same layout with component (a, c) holding conj of component (c, a), and
+  // the odd-level bits of the component each stored one comes from
+  void* sym_adj = nullptr;
+  uint8_t odd_adj[16] = {0};
   // right-hand sides per leaf workgroup chosen by the autotuner (0: automatic)
   int rb_pref = 0;
   size_t table_bytes = 0;
@@ -78,6 +83,7 @@ struct sfft_plan_s {
     for (int l = 0; l < kMaxD; ++l)
       if (tw[l]) (void)hipFree(tw[l]);
     if (sym) (void)hipFree(sym);
+    if (sym_adj) (void)hipFree(sym_adj);
     if (pool) (void)hipFree(pool);
   }
 };
@@ -86,7 +92,7 @@ sfft_status sfft_rt_fail(sfft_status s, const std::string& msg);
 sfft_status sfft_rt_hip_fail(hipError_t e, const char* what);
 size_t sfft_rt_workspace_elems(const sfft_plan_s* p, int64_t nrhs);
 sfft_status sfft_rt_apply_one(sfft_plan_s* p, const void* x, void* y, int64_t nrhs, void* ws, size_t ws_bytes,
-                              hipStream_t st);
+                              hipStream_t st, bool adj = false);
 int sfft_rt_leaf_rbmax(const sfft_plan_s* p);
 // drops cached graphs that reference the plan (called before it is freed)
 void sfft_rt_forget_plan(const sfft_plan_s* p);

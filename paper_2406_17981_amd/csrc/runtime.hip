@@ -30,6 +30,7 @@ using sfft::PassArgs;
 #define SFFT_X(L) extern "C" const AxisOps* sfft_ops_##L(int);
 #include "lengths.def"
 #undef SFFT_X
+extern "C" const AxisOps* sfft_ops_generic(int dtype, int64_t L);
 
 namespace {
 
@@ -41,8 +42,18 @@ const AxisOps* find_ops(int dtype, int64_t L) {
 #include "lengths.def"
 #undef SFFT_X
     default:
-      return nullptr;
+      return sfft_ops_generic(dtype, L);  // runtime-length kernels, or null
   }
+}
+
+// LDS the runtime-length kernels of one level need: a pass stages up to three
+// rows of the pencil length (two for a forward pass or a pass without a
+// second child), a leaf 2b + 1 rows (split) or b + 1 (embedding).
+bool generic_fits(const AxisOps* o, int dtype, int b, int npar, bool leaf, bool inv_two) {
+  if (!o || !o->generic) return true;
+  const size_t esz = dtype == SFFT_C64 ? 8 : 16;
+  const size_t rows = leaf ? (size_t)(npar == 2 ? 2 * b : b) + 1 : (inv_two ? 3 : 2);
+  return rows * (size_t)o->L * esz <= sfft::kMaxLds;
 }
 
 thread_local std::string g_err;
@@ -403,6 +414,7 @@ PassArgs base_args(const sfft_plan_s* p, int l, int64_t nv) {
   std::memset(&a, 0, sizeof(a));
   level_geom(p, l, nv, a.outer, a.inner);
   a.tw = p->tw[l];
+  a.len = p->L[l];
   a.nq = 1;
   return a;
 }
@@ -458,7 +470,7 @@ sfft_status run_pass(const sfft_plan_s* p, int l, int mode, const PassArgs& a, h
 // Leaf pass over branches q0 .. q0+nq-1 of levels 1..d-1 (q0 only matters
 // for the symbols: its bits are the branch's parities).
 sfft_status run_leaf(const sfft_plan_s* p, const void* in, void* out, int64_t in_bs, int64_t nq, int64_t q0,
-                     int64_t nrhs, hipStream_t st) {
+                     int64_t nrhs, hipStream_t st, bool adj) {
   const int l = p->d - 1;
   const AxisOps* o = p->ops[l];
   PassArgs a;
@@ -469,6 +481,7 @@ sfft_status run_leaf(const sfft_plan_s* p, const void* in, void* out, int64_t in
   a.out_bs = in_bs;
   a.nq = nq;
   a.tw = p->tw[l];
+  a.len = p->L[l];
   a.npen = p->npen;
   a.nrhs = nrhs;
   a.ntiles = p->ntiles;
@@ -481,8 +494,9 @@ sfft_status run_leaf(const sfft_plan_s* p, const void* in, void* out, int64_t in
   }
   a.rb = rb;
   sfft::pass_fn f;
+  const void* sym = adj ? p->sym_adj : p->sym;
   if (p->compressed) {
-    a.sym = p->sym;
+    a.sym = sym;
     a.sym_bs = 0;
     a.q0 = q0;
     a.d = p->d;
@@ -491,10 +505,10 @@ sfft_status run_leaf(const sfft_plan_s* p, const void* in, void* out, int64_t in
       a.mst[m] = p->mst[m];
     }
     a.mcomp = p->mcomp;
-    for (int k = 0; k < p->ns; ++k) a.odd[k] = p->odd[k];
+    for (int k = 0; k < p->ns; ++k) a.odd[k] = adj ? p->odd_adj[k] : p->odd[k];
     f = o->leaf_mirror[p->b].f[p->bsym];
   } else {
-    a.sym = (const char*)p->sym + (size_t)(q0 * p->sym_bs) * p->esz;
+    a.sym = (const char*)sym + (size_t)(q0 * p->sym_bs) * p->esz;
     a.sym_bs = p->sym_bs;
     f = o->leaf[p->b].f[p->method == SFFT_SPLIT ? 2 : 1][p->bsym];
   }
@@ -509,10 +523,10 @@ sfft_status run_leaf(const sfft_plan_s* p, const void* in, void* out, int64_t in
 // transformed; dst receives that branch's merged result. Level l's odd child
 // lives in workspace vector l-1.
 sfft_status split_depth(const sfft_plan_s* p, int l, const void* src, void* dst, int64_t q, int64_t nrhs,
-                        char* ws, hipStream_t st) {
+                        char* ws, hipStream_t st, bool adj) {
   const int64_t V = vec_elems(p, nrhs);
   const int64_t nv = nrhs * p->b;
-  if (l == p->d - 1) return run_leaf(p, src, dst, V, 1, q, nrhs, st);
+  if (l == p->d - 1) return run_leaf(p, src, dst, V, 1, q, nrhs, st, adj);
   void* odd = ws + (size_t)l * V * p->esz;
   PassArgs a = base_args(p, l, nv);
   a.in = src;
@@ -521,8 +535,8 @@ sfft_status split_depth(const sfft_plan_s* p, int l, const void* src, void* dst,
   a.use_phase = 1;
   sfft_status s = run_pass(p, l, 0, a, st);
   if (s != SFFT_OK) return s;
-  if ((s = split_depth(p, l + 1, dst, dst, 2 * q, nrhs, ws, st)) != SFFT_OK) return s;
-  if ((s = split_depth(p, l + 1, odd, odd, 2 * q + 1, nrhs, ws, st)) != SFFT_OK) return s;
+  if ((s = split_depth(p, l + 1, dst, dst, 2 * q, nrhs, ws, st, adj)) != SFFT_OK) return s;
+  if ((s = split_depth(p, l + 1, odd, odd, 2 * q + 1, nrhs, ws, st, adj)) != SFFT_OK) return s;
   PassArgs b = base_args(p, l, nv);
   b.in = dst;
   b.in1 = odd;
@@ -534,11 +548,11 @@ sfft_status split_depth(const sfft_plan_s* p, int l, const void* src, void* dst,
 // Breadth-first: level l's 2^(l+1) branch vectors live contiguously in
 // workspace block l (branch index C-order over the parities of levels 0..l).
 sfft_status split_breadth(const sfft_plan_s* p, const void* x, void* y, int64_t nrhs, char* ws,
-                          hipStream_t st) {
+                          hipStream_t st, bool adj) {
   const int d = p->d;
   const int64_t V = vec_elems(p, nrhs);
   const int64_t nv = nrhs * p->b;
-  if (d == 1) return run_leaf(p, x, y, V, 1, 0, nrhs, st);
+  if (d == 1) return run_leaf(p, x, y, V, 1, 0, nrhs, st, adj);
   char* blk[kMaxD];
   size_t off = 0;
   for (int l = 0; l < d - 1; ++l) {
@@ -557,7 +571,7 @@ sfft_status split_breadth(const sfft_plan_s* p, const void* x, void* y, int64_t 
     a.use_phase = 1;
     if ((s = run_pass(p, l, 0, a, st)) != SFFT_OK) return s;
   }
-  if ((s = run_leaf(p, blk[d - 2], blk[d - 2], V, int64_t(1) << (d - 1), 0, nrhs, st)) != SFFT_OK)
+  if ((s = run_leaf(p, blk[d - 2], blk[d - 2], V, int64_t(1) << (d - 1), 0, nrhs, st, adj)) != SFFT_OK)
     return s;
   for (int l = d - 2; l >= 0; --l) {
     PassArgs a = base_args(p, l, nv);
@@ -575,7 +589,8 @@ sfft_status split_breadth(const sfft_plan_s* p, const void* x, void* y, int64_t 
 
 // Standard circulant embedding: pad, transform every level of the 2^d-times
 // larger vector, block multiply, inverse transforms, project.
-sfft_status embed_apply(const sfft_plan_s* p, const void* x, void* y, int64_t nrhs, char* ws, hipStream_t st) {
+sfft_status embed_apply(const sfft_plan_s* p, const void* x, void* y, int64_t nrhs, char* ws, hipStream_t st,
+                        bool adj) {
   const int d = p->d;
   const int64_t nv = nrhs * p->b;
   Dims dm;
@@ -608,7 +623,7 @@ sfft_status embed_apply(const sfft_plan_s* p, const void* x, void* y, int64_t nr
     if ((s = run_pass(p, l, 0, a, st)) != SFFT_OK) return s;
   }
   const int64_t Vbig = big;
-  if ((s = run_leaf(p, ws, ws, Vbig, 1, 0, nrhs, st)) != SFFT_OK) return s;
+  if ((s = run_leaf(p, ws, ws, Vbig, 1, 0, nrhs, st, adj)) != SFFT_OK) return s;
   for (int l = d - 2; l >= 0; --l) {
     PassArgs a = base_args(p, l, nv);
     a.in = ws;
@@ -652,6 +667,7 @@ sfft_status fft64_inplace(const Dims& dm, double2* a, void* const* tw64, hipStre
     pa.out = a;
     pa.nq = 1;
     pa.tw = tw64[l];
+    pa.len = L;
     hipError_t e = (l == dm.d - 1) ? o->contig[0](pa, st) : o->strided[0](pa, st);
     if (e != hipSuccess) return hip_fail(e, "FP64 symbol transform");
   }
@@ -677,6 +693,16 @@ void tmp_free(void* p, hipStream_t st) {
   if (!p) return;
   if (pools_supported()) (void)hipFreeAsync(p, st);
   else (void)hipFree(p);
+}
+// Returns the stream-ordered pool's cached blocks to the device once the
+// transient buffers of a plan creation are freed (their stream synchronised),
+// so a plan holds only its own memory afterwards.
+void trim_pool() {
+  if (!pools_supported()) return;
+  int dev = 0;
+  hipMemPool_t pool = nullptr;
+  if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess && pool)
+    (void)hipMemPoolTrimTo(pool, 0);
 }
 
 sfft_status make_table(int dtype, int64_t L, void** out, size_t* bytes, hipStream_t st, bool transient = false) {
@@ -778,6 +804,7 @@ sfft_status build_symbols(sfft_plan_s* p, const double2* coeffs, hipStream_t st)
     for (int l = 0; l < d; ++l) tmp_free(tw64[l], st);
     tmp_free(tmp, st);
     (void)hipStreamSynchronize(st);
+    trim_pool();
   };
   for (int l = 0; l < d && s == SFFT_OK; ++l) s = make_table(SFFT_C128, 2 * p->n[l], &tw64[l], nullptr, st, true);
   if (s == SFFT_OK) {
@@ -834,6 +861,57 @@ sfft_status build_symbols(sfft_plan_s* p, const double2* coeffs, hipStream_t st)
   return s;
 }
 
+// Symbols of T^H from those of T: the generator of T^H is t(-r)^H, whose
+// embedded transform is the conjugate transpose of T's at every bin, so the
+// parity parts T^H[bId] are conj(T[bId])^T. Stored component k of the adjoint
+// is sign * conj(stored component src[k]) of the same (branch, parity, tile)
+// block, per_comp entries per component.
+struct AdjPerm {
+  int src[16];
+  int neg[16];
+};
+
+template <typename C>
+__global__ void k_adjoint_symbols(const C* __restrict__ src, C* __restrict__ dst, int64_t per_comp, int NS,
+                                  AdjPerm pm, int64_t total) {
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t blk = idx / (NS * per_comp);
+    const int64_t w = idx - blk * NS * per_comp;
+    const int k = (int)(w / per_comp);
+    const int64_t r = w - (int64_t)k * per_comp;
+    const C v = src[(blk * NS + pm.src[k]) * per_comp + r];
+    dst[idx] = pm.neg[k] ? sfft::mk<C>(-v.x, v.y) : sfft::mk<C>(v.x, -v.y);
+  }
+}
+
+sfft_status build_adjoint(sfft_plan_s* p, hipStream_t st) {
+  AdjPerm pm;
+  std::memset(&pm, 0, sizeof(pm));
+  for (int k = 0; k < p->ns; ++k) {
+    const int a = p->comp_of[k] / p->b, c = p->comp_of[k] % p->b;
+    pm.src[k] = k;
+    if (p->bsym == 0) {  // all b^2 components stored: (a, c) of T^H comes from (c, a) of T
+      for (int j = 0; j < p->ns; ++j)
+        if (p->comp_of[j] == c * p->b + a) pm.src[k] = j;
+    }
+    pm.neg[k] = p->bsym == 2;  // t[c, a] = -t[a, c]
+    p->odd_adj[k] = p->odd[pm.src[k]];
+  }
+  const int64_t total = (int64_t)(p->sym_bytes / p->esz);
+  const AxisOps* lo = p->ops[p->d - 1];
+  const int64_t per_comp = p->compressed ? p->mcomp : (int64_t)lo->LE * lo->NTL;
+  if (p->dtype == SFFT_C64)
+    hipLaunchKernelGGL(k_adjoint_symbols<float2>, dim3(grid_for(total)), dim3(256), 0, st, (const float2*)p->sym,
+                       (float2*)p->sym_adj, per_comp, p->ns, pm, total);
+  else
+    hipLaunchKernelGGL(k_adjoint_symbols<double2>, dim3(grid_for(total)), dim3(256), 0, st, (const double2*)p->sym,
+                       (double2*)p->sym_adj, per_comp, p->ns, pm, total);
+  HIP_TRY(hipGetLastError(), "adjoint symbol launch");
+  HIP_TRY(hipStreamSynchronize(st), "adjoint symbols");
+  return SFFT_OK;
+}
+
 bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb) {
   const char* x = (const char*)a;
   const char* y = (const char*)b;
@@ -841,7 +919,7 @@ bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb) {
 }
 
 sfft_status apply_one(sfft_plan_s* p, const void* x, void* y, int64_t nrhs, void* ws, size_t ws_bytes,
-                      hipStream_t st) {
+                      hipStream_t st, bool adj) {
   if (nrhs < 0) return fail(SFFT_INVALID_ARG, "nrhs must be >= 0");
   if (nrhs == 0) return SFFT_OK;  // empty batch: nothing is read or written
   if (!x || !y) return fail(SFFT_INVALID_ARG, "x and y must be non-null device pointers");
@@ -869,9 +947,10 @@ sfft_status apply_one(sfft_plan_s* p, const void* x, void* y, int64_t nrhs, void
       ws = p->pool;
     }
   }
-  if (p->method == SFFT_EMBED) return embed_apply(p, x, y, nrhs, (char*)ws, st);
-  if (p->sched == SFFT_SCHED_DEPTH && p->d > 1) return split_depth(p, 0, x, y, 0, nrhs, (char*)ws, st);
-  return split_breadth(p, x, y, nrhs, (char*)ws, st);
+  if (adj && !p->sym_adj) return fail(SFFT_INVALID_ARG, "adjoint symbols not built (sfft_plan_enable_adjoint)");
+  if (p->method == SFFT_EMBED) return embed_apply(p, x, y, nrhs, (char*)ws, st, adj);
+  if (p->sched == SFFT_SCHED_DEPTH && p->d > 1) return split_depth(p, 0, x, y, 0, nrhs, (char*)ws, st, adj);
+  return split_breadth(p, x, y, nrhs, (char*)ws, st, adj);
 }
 
 }  // namespace
@@ -881,8 +960,8 @@ sfft_status sfft_rt_fail(sfft_status s, const std::string& msg) { return fail(s,
 sfft_status sfft_rt_hip_fail(hipError_t e, const char* what) { return hip_fail(e, what); }
 size_t sfft_rt_workspace_elems(const sfft_plan_s* p, int64_t nrhs) { return workspace_elems(p, nrhs); }
 sfft_status sfft_rt_apply_one(sfft_plan_s* p, const void* x, void* y, int64_t nrhs, void* ws, size_t ws_bytes,
-                              hipStream_t st) {
-  return apply_one(p, x, y, nrhs, ws, ws_bytes, st);
+                              hipStream_t st, bool adj) {
+  return apply_one(p, x, y, nrhs, ws, ws_bytes, st, adj);
 }
 int sfft_rt_leaf_rbmax(const sfft_plan_s* p) { return p->ops[p->d - 1]->RBMAX; }
 
@@ -904,7 +983,10 @@ const char* sfft_status_string(sfft_status s) {
 
 const char* sfft_last_error(void) { return g_err.c_str(); }
 
-int sfft_length_supported(int64_t L) { return find_ops(SFFT_C64, L) != nullptr ? 1 : 0; }
+int sfft_length_supported(int64_t L) {
+  const AxisOps* o = find_ops(SFFT_C64, L);
+  return o == nullptr ? 0 : (o->generic ? 2 : 1);
+}
 
 sfft_status sfft_plan_create(sfft_plan* out, int d, const int64_t* n, int b, const void* coeffs, int dtype,
                              int method, const int32_t* parity, int64_t max_nrhs, int schedule, void* stream) {
@@ -948,10 +1030,23 @@ sfft_status sfft_plan_create(sfft_plan* out, int d, const int64_t* n, int b, con
     n = n_eff;
   }
   for (int l = 0; l < d; ++l) {
-    if (!find_ops(dtype, 2 * n[l]))
+    int64_t r = n[l];
+    for (int f : {2, 3, 5, 7})
+      while (r % f == 0) r /= f;
+    if (r != 1)
+      return fail(SFFT_UNSUPPORTED, "level size " + std::to_string(n[l]) + " has the prime factor " +
+                                        std::to_string(r) + " (only 2, 3, 5 and 7 are supported)");
+    if (n[l] > 2048)
+      return fail(SFFT_UNSUPPORTED, "level size " + std::to_string(n[l]) + " above 2048");
+    // the FP64 symbol generator transforms 2 n_l points along level l
+    if (!find_ops(SFFT_C128, 2 * n[l]) || !generic_fits(find_ops(SFFT_C128, 2 * n[l]), SFFT_C128, b, 1, false, false))
       return fail(SFFT_UNSUPPORTED, "no kernels for length " + std::to_string(2 * n[l]));
-    if (method == SFFT_SPLIT && !find_ops(dtype, n[l]))
-      return fail(SFFT_UNSUPPORTED, "no kernels for length " + std::to_string(n[l]));
+    const int64_t L = method == SFFT_SPLIT ? n[l] : 2 * n[l];
+    const AxisOps* o = find_ops(dtype, L);
+    const bool leaf = l == d - 1;
+    if (!o || !generic_fits(o, dtype, b, method == SFFT_SPLIT ? 2 : 1, leaf, method == SFFT_SPLIT))
+      return fail(SFFT_UNSUPPORTED, "level of length " + std::to_string(L) + " needs more LDS than a workgroup has "
+                                    "for b = " + std::to_string(b) + " in this dtype");
   }
   bool mirror = false;
   if (parity && method == SFFT_SPLIT) {
@@ -1054,7 +1149,9 @@ sfft_status sfft_plan_update(sfft_plan plan, const void* coeffs, void* stream) {
     s = check_parity((const double2*)coeffs, plan->b, plan->d, plan->n, plan->parity, st);
     if (s != SFFT_OK) return s;
   }
-  return build_symbols(plan, (const double2*)coeffs, st);
+  s = build_symbols(plan, (const double2*)coeffs, st);
+  if (s == SFFT_OK && plan->sym_adj) s = build_adjoint(plan, st);
+  return s;
 }
 
 sfft_status sfft_workspace_size(sfft_plan plan, int64_t nrhs, size_t* bytes) {
@@ -1067,7 +1164,25 @@ sfft_status sfft_workspace_size(sfft_plan plan, int64_t nrhs, size_t* bytes) {
 sfft_status sfft_apply(sfft_plan plan, const void* x, void* y, int64_t nrhs, void* workspace, size_t ws_bytes,
                        void* stream) {
   if (!plan) return fail(SFFT_INVALID_ARG, "plan is null");
-  return apply_one(plan, x, y, nrhs, workspace, ws_bytes, (hipStream_t)stream);
+  return apply_one(plan, x, y, nrhs, workspace, ws_bytes, (hipStream_t)stream, false);
+}
+
+sfft_status sfft_plan_enable_adjoint(sfft_plan plan, void* stream) {
+  if (!plan) return fail(SFFT_INVALID_ARG, "plan is null");
+  if (plan->sym_adj) return SFFT_OK;
+  HIP_TRY(hipMalloc(&plan->sym_adj, plan->sym_bytes), "adjoint symbol allocation");
+  sfft_status s = build_adjoint(plan, (hipStream_t)stream);
+  if (s != SFFT_OK) {
+    (void)hipFree(plan->sym_adj);
+    plan->sym_adj = nullptr;
+  }
+  return s;
+}
+
+sfft_status sfft_apply_adjoint(sfft_plan plan, const void* x, void* y, int64_t nrhs, void* workspace,
+                               size_t ws_bytes, void* stream) {
+  if (!plan) return fail(SFFT_INVALID_ARG, "plan is null");
+  return apply_one(plan, x, y, nrhs, workspace, ws_bytes, (hipStream_t)stream, true);
 }
 
 sfft_status sfft_workspace_size_multi(int nprob, const sfft_plan* plans, const int64_t* nrhs, size_t* bytes) {
@@ -1097,6 +1212,7 @@ sfft_status sfft_plan_info(sfft_plan plan, sfft_info* info) {
   info->table_bytes = plan->table_bytes;
   info->workspace_bytes = workspace_elems(plan, plan->max_nrhs) * plan->esz;
   info->vector_elems = plan->b * plan->s;
+  info->adjoint_symbol_bytes = plan->sym_adj ? plan->sym_bytes : 0;
   return SFFT_OK;
 }
 

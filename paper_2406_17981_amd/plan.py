@@ -89,7 +89,7 @@ class Plan:
                     schedule=inf.schedule, compressed=inf.compressed, max_nrhs=inf.max_nrhs,
                     symbol_bytes=inf.symbol_bytes, table_bytes=inf.table_bytes,
                     workspace_bytes=inf.workspace_bytes, vector_elems=inf.vector_elems,
-                    block_symmetry=inf.block_symmetry)
+                    block_symmetry=inf.block_symmetry, adjoint_symbol_bytes=inf.adjoint_symbol_bytes)
 
     def workspace_size(self, nrhs: int) -> int:
         out = C.c_size_t()
@@ -107,8 +107,9 @@ class Plan:
 
     # -- apply -----------------------------------------------------------
     def apply(self, x: torch.Tensor, y: Optional[torch.Tensor] = None,
-              workspace: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
-        """y = T x; x is (nrhs, b, *n) (or (b, *n)) of the plan dtype, on the device."""
+              workspace: Optional[torch.Tensor] = None, stream=None, adjoint: bool = False) -> torch.Tensor:
+        """y = T x (or y = T^H x with adjoint=True, after enable_adjoint()); x is
+        (nrhs, b, *n) (or (b, *n)) of the plan dtype, on the device."""
         _require_device(x, "x", self.torch_dtype)
         squeeze = x.dim() == self.d + 1
         xs = x.unsqueeze(0) if squeeze else x
@@ -126,13 +127,19 @@ class Plan:
             if not workspace.is_cuda or not workspace.is_contiguous():
                 raise ValueError("workspace must be a contiguous device tensor")
             ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
-        st = N.lib.sfft_apply(self.handle, C.c_void_p(xs.data_ptr()), C.c_void_p(y.data_ptr()), nrhs,
-                              C.c_void_p(ws_ptr) if ws_ptr else None, ws_bytes,
-                              C.c_void_p(_stream_handle(stream)))
-        N.check(st, "sfft_apply")
+        fn = N.lib.sfft_apply_adjoint if adjoint else N.lib.sfft_apply
+        st = fn(self.handle, C.c_void_p(xs.data_ptr()), C.c_void_p(y.data_ptr()), nrhs,
+                C.c_void_p(ws_ptr) if ws_ptr else None, ws_bytes, C.c_void_p(_stream_handle(stream)))
+        N.check(st, "sfft_apply_adjoint" if adjoint else "sfft_apply")
         return y.view(x.shape) if squeeze else y
 
     __call__ = apply
+
+    def enable_adjoint(self, stream=None) -> None:
+        """Build the symbols of T^H (sfft_plan_enable_adjoint) so that
+        apply(..., adjoint=True) computes y = T^H x."""
+        N.check(N.lib.sfft_plan_enable_adjoint(self.handle, C.c_void_p(_stream_handle(stream))),
+                "sfft_plan_enable_adjoint")
 
     def autotune(self, nrhs: int = 1, use_cache: bool = True, stream=None) -> float:
         """Pick the fastest schedule / leaf grouping for nrhs right-hand sides on
@@ -221,3 +228,40 @@ def apply_multi(plans: Sequence[Plan], xs: Sequence[torch.Tensor], ys: Sequence[
                                 workspace.numel(), C.c_void_p(_stream_handle(stream)))
     N.check(st, "sfft_apply_multi")
     return ys
+
+
+def gmres_workspace_size(lo: Plan, hi: Plan, m: int) -> int:
+    out = C.c_size_t()
+    N.check(N.lib.sfft_gmres_workspace_size(lo.handle, hi.handle, int(m), C.byref(out)),
+            "sfft_gmres_workspace_size")
+    return int(out.value)
+
+
+def gmres_solve(lo: Plan, hi: Plan, chi: torch.Tensor, rhs: torch.Tensor, x: Optional[torch.Tensor] = None,
+                m: int = 30, max_cycles: int = 50, tol: float = 1e-6,
+                workspace: Optional[torch.Tensor] = None, stream=None):
+    """Solve (I - diag(chi) T) x = rhs by restarted GMRES(m) (sfft_gmres_solve):
+    Krylov steps with lo's products, the true residual in FP64 with hi (a
+    complex128 plan of the same T). chi, rhs, x: complex128 device tensors of
+    shape (b, *n); x holds the initial guess (zero when None) and receives the
+    solution. Returns (x, info dict)."""
+    shape = (lo.b,) + lo.n
+    for name, t in (("chi", chi), ("rhs", rhs)):
+        _require_device(t, name, torch.complex128)
+        if tuple(t.shape) != shape:
+            raise ValueError(f"{name} must have shape {shape}")
+    if x is None:
+        x = torch.zeros(shape, dtype=torch.complex128, device=rhs.device)
+    _require_device(x, "x", torch.complex128)
+    if tuple(x.shape) != shape:
+        raise ValueError(f"x must have shape {shape}")
+    if workspace is None:
+        workspace = torch.empty(gmres_workspace_size(lo, hi, m), dtype=torch.uint8, device=rhs.device)
+    inf = N.GmresInfo()
+    N.check(N.lib.sfft_gmres_solve(lo.handle, hi.handle, C.c_void_p(chi.data_ptr()), C.c_void_p(rhs.data_ptr()),
+                                   C.c_void_p(x.data_ptr()), int(m), int(max_cycles), float(tol),
+                                   C.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                   C.c_void_p(_stream_handle(stream)), C.byref(inf)), "sfft_gmres_solve")
+    return x, dict(cycles=inf.cycles, matvecs=inf.matvecs, fp64_matvecs=inf.fp64_matvecs,
+                   rel_residual=inf.rel_residual, rel_residual_estimate=inf.rel_residual_estimate,
+                   converged=bool(inf.converged))

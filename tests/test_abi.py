@@ -35,7 +35,10 @@ def test_host_only_calls():
     from paper_2406_17981_amd import _native as N
     assert N.lib.sfft_status_string(N.INVALID_ARG) == b"SFFT_INVALID_ARG"
     assert N.lib.sfft_length_supported(64) == 1
-    assert N.lib.sfft_length_supported(7) == 0
+    for L in (7, 9, 14, 15, 21, 25, 35, 36, 49, 100, 343, 1000, 2187, 4096):  # runtime-length kernels
+        assert N.lib.sfft_length_supported(L) == 2, L
+    for L in (0, 1, 11, 22, 26, 4097, 5000, 8192):
+        assert N.lib.sfft_length_supported(L) == 0, L
     for L in (16, 40, 48, 64, 80, 96, 128, 160, 192, 256, 384, 512, 768, 1024, 2048):
         assert N.lib.sfft_length_supported(L) == 1, L
 

@@ -653,3 +653,138 @@ def test_plan_update_equals_a_fresh_plan(sf, dtype, kind, mirrored, method):
     torch.cuda.synchronize()
     plan.close()
     fresh.close()
+
+
+# ---------------------------------------------------------------------------
+# Level sizes without length-specialised kernels (runtime-length kernels)
+# ---------------------------------------------------------------------------
+RUNTIME_LENGTHS = [((7,), 1), ((14, 9), 3), ((21, 10), 2), ((35, 6, 4), 1), ((49, 5), 4), ((9, 15, 25), 3),
+                   ((36, 100), 1), ((6, 7, 8), 3), ((12, 343), 1), ((1000,), 2), ((2, 1960), 1), ((28, 3, 14), 4)]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("grid,b", RUNTIME_LENGTHS)
+def test_runtime_length_levels_match_oracle(sf, grid, b, dtype):
+    """Level sizes with prime factors in {2, 3, 5, 7} but no length-specialised
+    kernels (7, 9, 14, 15, 21, 25, 35, 36, 49, 100, 343, 1000, 1960 and the
+    FP64 symbol lengths 2 n_l, e.g. 686, 2000, 3920) run on the runtime-length
+    kernels (radix 8, 4, 2, 3, 5, 7 stages in LDS), alone and next to
+    length-specialised levels; every output against the FP64 oracle, both
+    schedules and the embedding baseline."""
+    from paper_2406_17981_amd import _native as N
+    assert any(N.lib.sfft_length_supported(v) == 2 for v in grid)
+    coeffs = wl.iid_coeffs(91, grid, b)
+    x = wl.vectors(92, grid, b, 2)
+    want = oracle.dense_matvec(coeffs, x) if math.prod(grid) * b <= 4096 else oracle.embed_matvec(coeffs, x)
+    for sched in ("breadth", "depth"):
+        got = _run(sf, coeffs, x, dtype, "split", sched)
+        err = wl.relative_l2(got, want)
+        _say(f"runtime length {grid} b={b} {dtype} {sched} rel_l2={err:.3e}")
+        assert err <= TOL[dtype], (sched, err)
+    got = _run(sf, coeffs, x, dtype, "embed")
+    assert wl.relative_l2(got, want) <= TOL[dtype], "embed"
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("grid", [(14, 9), (7, 21, 5), (25, 6, 49), (15,)])
+def test_runtime_length_levels_mirrored(sf, grid, dtype):
+    """Mirrored symbols (Section II.C) on runtime-length levels, odd and even
+    sizes, b = 3 with a random even/odd pattern and block symmetry."""
+    d = len(grid)
+    par = np.random.default_rng(93).integers(1, 3, (3, 3, d)).astype(np.int32)
+    par = np.maximum(par, np.swapaxes(par, 0, 1))  # symmetric pattern, so symmetric blocks can carry it
+    coeffs = wl.parity_coeffs(94, grid, 3, par)
+    coeffs = (coeffs + np.swapaxes(coeffs, 0, 1)) / 2
+    x = wl.vectors(95, grid, 3, 2)
+    want = oracle.embed_matvec(coeffs, x)
+    for sched in ("breadth", "depth"):
+        info = {}
+        got = _run(sf, coeffs, x, dtype, "split", sched, parity=par, info=info)
+        assert info["compressed"] == 1 and info["block_symmetry"] == 1
+        err = wl.relative_l2(got, want)
+        _say(f"runtime length mirrored {grid} {dtype} {sched} rel_l2={err:.3e}")
+        assert err <= TOL[dtype], (sched, err)
+
+
+def test_unsupported_level_sizes(sf):
+    """Prime factors outside {2, 3, 5, 7} and sizes above 2048 are refused
+    before any device work, naming the size."""
+    for grid in ((11,), (8, 22), (4096,)):
+        coeffs = torch.zeros((1, 1) + tuple(2 * v - 1 for v in grid), dtype=torch.complex128, device="cuda")
+        with pytest.raises(sf.SfftError, match="UNSUPPORTED"):
+            sf.Plan(grid, 1, coeffs, dtype="c64")
+
+
+# ---------------------------------------------------------------------------
+# Adjoint: y = T^H x from the plan's symbols conjugated and transposed
+# ---------------------------------------------------------------------------
+ADJ_CASES = [((10, 12), 1, "iid", None), ((6, 10, 12), 3, "iid", None), ((6, 10, 12), 3, "green", "mirrored"),
+             ((8, 6, 10), 3, "skew", "mirrored"), ((8, 6, 10), 3, "skew", None), ((5, 8, 16), 2, "parity", "mirrored"),
+             ((4, 3, 2, 5), 4, "iid", None), ((14, 9), 4, "sym", None), ((7, 10), 2, "anti", None)]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("grid,b,kind,storage", ADJ_CASES)
+def test_adjoint_matches_oracle(sf, grid, b, kind, storage, dtype):
+    """sfft_apply_adjoint against the FP64 oracle's product with the generator
+    t^H(r) = t(-r)^H (general, block-symmetric, block-antisymmetric and mirrored
+    storage, b = 1..4, a runtime-length level), both schedules and the
+    embedding baseline; plus <u, T v> = <T^H u, v> on the device results."""
+    d = len(grid)
+    par = None
+    if kind == "green":
+        coeffs, par = wl.green_coeffs(grid, 0.8), wl.green_parity(d)
+    elif kind == "skew":
+        coeffs, par = wl.skew_coeffs(grid, 1.2), wl.skew_parity(d)
+    elif kind == "parity":
+        par = np.random.default_rng(96).integers(1, 3, (b, b, d)).astype(np.int32)
+        coeffs = wl.parity_coeffs(97, grid, b, par)
+    else:
+        coeffs = _blocks_with_symmetry(98, grid, b, kind)
+    if storage != "mirrored":
+        par = None
+    x = wl.vectors(99, grid, b, 2)
+    want = oracle.embed_matvec(oracle.adjoint_coeffs(coeffs), x)
+    want_fwd = oracle.embed_matvec(coeffs, x)
+    cd = torch.from_numpy(coeffs).cuda()
+    xd = torch.from_numpy(x.astype(NP[dtype])).cuda()
+    runs = [("split", "breadth"), ("split", "depth")] + ([("embed", "auto")] if par is None else [])
+    for method, sched in runs:
+        _say(f"adjoint {grid} b={b} {kind} {storage} {dtype} {method} {sched}")
+        plan = sf.Plan(grid, b, cd, dtype=dtype, method=method, parity=par, max_nrhs=2, schedule=sched)
+        ws = plan.alloc_workspace(2)
+        with pytest.raises(sf.SfftError, match="INVALID_ARG"):
+            plan.apply(xd, workspace=ws, adjoint=True)  # not enabled yet
+        plan.enable_adjoint()
+        assert plan.info()["adjoint_symbol_bytes"] == plan.info()["symbol_bytes"]
+        yh = plan.apply(xd, workspace=ws, adjoint=True)
+        yf = plan.apply(xd, workspace=ws)
+        torch.cuda.synchronize()
+        gh = yh.cpu().numpy().astype(np.complex128)
+        gf = yf.cpu().numpy().astype(np.complex128)
+        plan.close()
+        err = wl.relative_l2(gh, want)
+        _say(f"adjoint rel_l2={err:.3e}")
+        assert err <= TOL[dtype], (method, sched, err)
+        assert wl.relative_l2(gf, want_fwd) <= TOL[dtype]
+        # <x_1, T x_0> = <T^H x_1, x_0> with the device products
+        lhs = np.vdot(x[1], gf[0])
+        rhs = np.vdot(gh[1], x[0])
+        assert abs(lhs - rhs) <= 10 * TOL[dtype] * np.linalg.norm(x[1]) * np.linalg.norm(gf[0])
+
+
+def test_adjoint_follows_plan_update(sf):
+    """After sfft_plan_update the adjoint symbols are those of the new operator."""
+    grid = (16, 12, 10)
+    ca, cb = wl.green_coeffs(grid, 0.7), wl.green_coeffs(grid, 1.1)
+    ca[0, 0] *= 1 + 0.5j  # no longer Hermitian-like: T^H differs from T
+    cb[0, 0] *= 1 - 0.3j
+    x = wl.vectors(100, grid, 3, 1)
+    plan = sf.Plan(grid, 3, torch.from_numpy(ca).cuda(), dtype="c128", parity=wl.green_parity(3))
+    plan.enable_adjoint()
+    plan.update(torch.from_numpy(cb).cuda())
+    y = plan.apply(torch.from_numpy(x).cuda(), adjoint=True)
+    torch.cuda.synchronize()
+    want = oracle.embed_matvec(oracle.adjoint_coeffs(cb), x)
+    assert wl.relative_l2(y.cpu().numpy(), want) <= 1e-12
+    plan.close()
