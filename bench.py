@@ -121,16 +121,18 @@ def pmc_probe(workload="green64"):
         cfg = wl.LARGE_256
         n, nrhs = cfg["n"], cfg["nrhs"]
         cd = wl.green_coeffs_device(n, cfg["k"])
-        plan = sf.Plan(n, 3, cd, dtype="c64", max_nrhs=nrhs, schedule="depth")
-        del cd
-        torch.cuda.empty_cache()
         x = torch.from_numpy(wl.vectors(cfg["seed_x"], n, 3, nrhs).astype(np.complex64)).cuda()
         y = torch.empty_like(x)
-        ws = plan.alloc_workspace(nrhs)
-        for _ in range(3):
-            plan.apply(x, y, ws)
-        torch.cuda.synchronize()
-        log("pmc probe done")
+        for parity in (None, wl.green_parity(3)):  # general, then mirrored symbols
+            plan = sf.Plan(n, 3, cd, dtype="c64", max_nrhs=nrhs, schedule="depth", parity=parity)
+            ws = plan.alloc_workspace(nrhs)
+            for _ in range(3):
+                plan.apply(x, y, ws)
+            torch.cuda.synchronize()
+            plan.close()
+            del ws
+            torch.cuda.empty_cache()
+            log(f"pmc probe: {'mirrored' if parity is not None else 'general'} symbols done")
         return
     coeffs, x_host = wl.green_64(1)
     plan = sf.Plan(wl.GREEN_64["n"], 3, torch.from_numpy(coeffs).cuda(), dtype="c64", method="split")
@@ -213,6 +215,9 @@ def prof_summarize(db_path, out_path, title, command):
 # needs; a pass moves three branch vectors
 LARGE_PMC_KERNELS = {
     "sfft::k_leaf<float, 128, 3, 2, false, 1>": 2 * 1610612736 + 805306368,
+    # mirrored symbols: a branch's parities select a quarter of the stored
+    # 6 x 257 x 257 x 129 entries along the outer two levels
+    "sfft::k_leaf<float, 128, 3, 2, true, 1>": 2 * 1610612736 + 6 * 129 * 129 * 129 * 8,
     "sfft::k_strided<float, 256, 0, 256>": 3 * 1610612736,
     "sfft::k_strided<float, 256, 1, 256>": 3 * 1610612736,
 }
@@ -302,6 +307,35 @@ def cpu_baseline_large(coeffs, x_host, budget_s):
                             f"b=3 Green workload through oracle.embed_matvec_with_symbol, symbol transformed "
                             f"once beforehand ({t_sym:.1f} s, not timed); scipy.fft workers={cores}",
                      cpu_model=cpu_model(), per_workers={str(k): v for k, v in runs.items()})
+
+
+def pmc_counters_table(pmc_dir, out_path, title, command):
+    """Median per-dispatch value of every counter of a rocprofv3 --pmc run
+    (CSV output) for the 256x256x128 leaf kernels, as a Markdown table."""
+    import csv
+    import glob
+    rows = []
+    for f in glob.glob(os.path.join(pmc_dir, "**", "*counter_collection.csv"), recursive=True):
+        rows += list(csv.DictReader(open(f)))
+    vals = {}
+    for r in rows:
+        name = r["Kernel_Name"]
+        for k in LARGE_PMC_KERNELS:
+            if name.startswith("void " + k):
+                vals.setdefault(k, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    counters = sorted({c for v in vals.values() for c in v})
+    lines = [f"# {title}", "", "Command (repository root, one MI355X):", "```", command, "```", "",
+             "Median per dispatch over the probe's launches of each kernel.", "",
+             "| kernel | " + " | ".join(counters) + " |", "|---|" + "---:|" * len(counters)]
+    for k, cv in vals.items():
+        cells = []
+        for c in counters:
+            v = sorted(cv.get(c, []))
+            cells.append(f"{v[len(v) // 2]:.4g}" if v else "")
+        lines.append(f"| `{k}` | " + " | ".join(cells) + " |")
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(f"wrote {out_path}")
 
 
 def bench_large(args):
@@ -463,10 +497,14 @@ def bench_large(args):
         "split_vs_embed": {
             "speedup": round(g["green_embed"]["ms_per_apply"] / g["green_split_depth"]["ms_per_apply"], 3),
             "device_bytes_ratio_embed_over_split": round(
-                g["green_embed"]["measured_device_bytes"] / g["green_split_depth"]["measured_device_bytes"], 3),
+                g["green_embed"]["model_device_bytes"] / g["green_split_depth"]["model_device_bytes"], 3),
             "device_bytes_ratio_embed_over_split_mirrored": round(
-                g["green_embed"]["measured_device_bytes"] / g["green_split_depth_mirrored"]["measured_device_bytes"],
-                3),
+                g["green_embed"]["model_device_bytes"] / g["green_split_depth_mirrored"]["model_device_bytes"], 3),
+            "measured_device_bytes_ratio_embed_over_split": round(
+                g["green_embed"]["measured_device_bytes"] / g["green_split_depth"]["measured_device_bytes"], 3),
+            "device_bytes_note": "model: symbols + tables + workspace + x + y as the plans report them; measured: "
+                                 "hipMemGetInfo before plan creation and after the workspace allocation, plus x and "
+                                 "y (it can include plan-creation scratch the stream-ordered pool keeps cached)",
             "skew_speedup_mirrored": round(g["skew_embed"]["ms_per_apply"]
                                            / g["skew_split_depth_mirrored"]["ms_per_apply"], 3)},
         "fp64_residual_c64_vs_c128": float(f"{fp64_rel:.3e}"),
@@ -860,6 +898,8 @@ def main():
     ap.add_argument("--pmc-summarize", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON"))
     ap.add_argument("--prof-summarize", nargs=4, metavar=("RESULTS_DB", "OUT_MD", "TITLE", "COMMAND"),
                     help="write a kernel-statistics table from a rocprofv3 --kernel-trace results database")
+    ap.add_argument("--pmc-table", nargs=4, metavar=("PMC_DIR", "OUT_MD", "TITLE", "COMMAND"),
+                    help="write the leaf kernels' counters of a rocprofv3 --pmc run (CSV) as a table")
     args = ap.parse_args()
     steps_default, warmup_default = {"large": (20, 5), "batch": (50, 5), "green64": (1000, 2000)}.get(
         args.workload, (1, 0))
@@ -870,6 +910,9 @@ def main():
 
     if args.prof_summarize:
         prof_summarize(*args.prof_summarize)
+        return
+    if args.pmc_table:
+        pmc_counters_table(*args.pmc_table)
         return
     if args.pmc_summarize:
         (pmc_summarize_large if args.workload == "large" else pmc_summarize)(*args.pmc_summarize)

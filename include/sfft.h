@@ -184,6 +184,20 @@ sfft_status sfft_apply_multi(int nprob, const sfft_plan* plans, const void* cons
                              void* const* y, const int64_t* nrhs, void* workspace, size_t ws_bytes,
                              void* stream);
 
+/* Independent products issued in one call without a graph, each with its own
+ * caller workspace: problem i is plans[i] applied to x[i] -> y[i] (nrhs[i]
+ * right-hand sides, workspaces[i] of ws_bytes[i] bytes, NULL when 0 is
+ * needed), on internal streams forked from `stream` and joined back to it, so
+ * the problems' kernels overlap and later work on `stream` sees every result.
+ * For loops that change the set of problems every call (a serving step), where
+ * a cached graph would rarely be replayed. status (host, nprob entries)
+ * receives each problem's own result; a failing problem does not stop the
+ * others. Returns SFFT_OK unless the call itself is malformed or a fork/join
+ * fails. */
+sfft_status sfft_apply_each(int nprob, const sfft_plan* plans, const void* const* x, void* const* y,
+                            const int64_t* nrhs, void* const* workspaces, const size_t* ws_bytes, void* stream,
+                            sfft_status* status);
+
 sfft_status sfft_plan_info(sfft_plan plan, sfft_info* info);
 
 /* One step of independent Arnoldi processes (Krylov chains of matvecs, the

@@ -193,7 +193,63 @@ void sfft_rt_forget_plan(const sfft_plan_s* p) {
   }
 }
 
+namespace {
+
+#define HIP_OK(expr, what)                                \
+  do {                                                    \
+    hipError_t e_ = (expr);                               \
+    if (e_ != hipSuccess) return sfft_rt_hip_fail(e_, what); \
+  } while (0)
+
+// Fork / join events of sfft_apply_each on the current device's side
+// streams (created once with them, reused under g_mu).
+hipEvent_t g_fork = nullptr;
+hipEvent_t g_join[kSideStreams] = {nullptr};
+int g_ev_dev = -1;
+
+sfft_status ensure_events() {
+  if (g_ev_dev == g_dev && g_fork) return SFFT_OK;
+  if (g_fork) {
+    (void)hipEventDestroy(g_fork);
+    for (auto& e : g_join) (void)hipEventDestroy(e);
+  }
+  hipError_t e = hipEventCreateWithFlags(&g_fork, hipEventDisableTiming);
+  for (int i = 0; i < kSideStreams && e == hipSuccess; ++i)
+    e = hipEventCreateWithFlags(&g_join[i], hipEventDisableTiming);
+  if (e != hipSuccess) return sfft_rt_hip_fail(e, "batch events");
+  g_ev_dev = g_dev;
+  return SFFT_OK;
+}
+
+}  // namespace
+
 extern "C" {
+
+sfft_status sfft_apply_each(int nprob, const sfft_plan* plans, const void* const* x, void* const* y,
+                            const int64_t* nrhs, void* const* workspaces, const size_t* ws_bytes, void* stream,
+                            sfft_status* status) {
+  if (nprob < 0 || (nprob > 0 && (!plans || !x || !y || !nrhs || !workspaces || !ws_bytes || !status)))
+    return sfft_rt_fail(SFFT_INVALID_ARG, "null argument");
+  if (nprob == 0) return SFFT_OK;
+  hipStream_t st = (hipStream_t)stream;
+  std::lock_guard<std::mutex> lock(g_mu);
+  sfft_status s = ensure_streams();
+  if (s == SFFT_OK) s = ensure_events();
+  if (s != SFFT_OK) return s;
+  HIP_OK(hipEventRecord(g_fork, st), "fork record");
+  const int nside = nprob < kSideStreams ? nprob : kSideStreams;
+  for (int k = 0; k < nside; ++k) HIP_OK(hipStreamWaitEvent(g_side[k], g_fork, 0), "fork wait");
+  for (int i = 0; i < nprob; ++i) {
+    status[i] = plans[i] ? sfft_rt_apply_one(plans[i], x[i], y[i], nrhs[i], workspaces[i], ws_bytes[i],
+                                             g_side[i % kSideStreams])
+                         : sfft_rt_fail(SFFT_INVALID_ARG, "plan is null");
+  }
+  for (int k = 0; k < nside; ++k) {
+    HIP_OK(hipEventRecord(g_join[k], g_side[k]), "join record");
+    HIP_OK(hipStreamWaitEvent(st, g_join[k], 0), "join wait");
+  }
+  return SFFT_OK;
+}
 
 sfft_status sfft_apply_multi(int nprob, const sfft_plan* plans, const void* const* x, void* const* y,
                              const int64_t* nrhs, void* workspace, size_t ws_bytes, void* stream) {

@@ -694,17 +694,6 @@ void tmp_free(void* p, hipStream_t st) {
   if (pools_supported()) (void)hipFreeAsync(p, st);
   else (void)hipFree(p);
 }
-// Returns the stream-ordered pool's cached blocks to the device once the
-// transient buffers of a plan creation are freed (their stream synchronised),
-// so a plan holds only its own memory afterwards.
-void trim_pool() {
-  if (!pools_supported()) return;
-  int dev = 0;
-  hipMemPool_t pool = nullptr;
-  if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess && pool)
-    (void)hipMemPoolTrimTo(pool, 0);
-}
-
 sfft_status make_table(int dtype, int64_t L, void** out, size_t* bytes, hipStream_t st, bool transient = false) {
   const size_t esz = dtype == SFFT_C64 ? 8 : 16;
   const size_t nb = (size_t)(2 * L) * esz;
@@ -804,7 +793,6 @@ sfft_status build_symbols(sfft_plan_s* p, const double2* coeffs, hipStream_t st)
     for (int l = 0; l < d; ++l) tmp_free(tw64[l], st);
     tmp_free(tmp, st);
     (void)hipStreamSynchronize(st);
-    trim_pool();
   };
   for (int l = 0; l < d && s == SFFT_OK; ++l) s = make_table(SFFT_C128, 2 * p->n[l], &tw64[l], nullptr, st, true);
   if (s == SFFT_OK) {

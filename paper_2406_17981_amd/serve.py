@@ -23,7 +23,12 @@ The server
 * keeps the plans of finished requests for reuse: a new request on the same
   grid takes one over and only regenerates its symbols (sfft_plan_update),
   so admission allocates and frees no device memory; idle plans count
-  against the budget and are closed when an admission needs the room.
+  against the budget and are closed when an admission needs the room;
+* isolates failures: a request larger than the whole budget, one whose
+  admission raises (say an allocation failure) and one whose step or
+  completion fails end alone with an error result, their memory returned;
+  the others carry on. Requests can be cancelled (queued, waiting or
+  active) and may carry a deadline after which they are cancelled.
 
 Every kernel is deterministic and works on one request's buffers only, so a
 request's results are bitwise the same alone and in any mix.
@@ -51,10 +56,12 @@ class Request:
     k: float                       # Green-function wavenumber
     steps: int = 30                # matvecs in the chain
     seed: int = 0                  # seeds the start vector
+    deadline: Optional[float] = None  # seconds after arrival; cancelled when exceeded
     # filled by the server
     admitted: Optional[float] = None
     done: Optional[float] = None
     result: Optional[dict] = None
+    status: str = "pending"        # "ok", "error" or "cancelled" once it has left the server
 
     @property
     def latency(self) -> Optional[float]:
@@ -91,8 +98,10 @@ class Executor:
     def admit(self, req: Request) -> object:
         raise NotImplementedError
 
-    def step(self, slots: Sequence[object]) -> None:
-        """One Arnoldi step for each slot."""
+    def step(self, slots: Sequence[object]) -> Optional[List[tuple]]:
+        """One Arnoldi step for each slot. Returns (index into slots, message)
+        for every slot whose step failed (None or [] when all succeeded); a
+        failed slot takes no further steps."""
         raise NotImplementedError
 
     def finish_start(self, slot: object) -> None:
@@ -128,8 +137,12 @@ class _Slot:
     done_steps: int = 0
 
 
+ADMITTED, WAIT, REJECTED = "admitted", "wait", "rejected"
+
+
 class Server:
-    """Admission by HBM budget, continuous batching, completion bookkeeping."""
+    """Admission by HBM budget, continuous batching, completion bookkeeping,
+    per-request failure isolation and cancellation."""
 
     def __init__(self, executor: Executor, budget_bytes: int, max_active: int = 256,
                  clock: Callable[[], float] = time.perf_counter, sleep: Callable[[float], None] = time.sleep):
@@ -143,35 +156,76 @@ class Server:
         self.steps_run = 0
         self.batch_sizes: List[int] = []
         self.time_in = dict(admit=0.0, step=0.0, finish=0.0)  # host seconds per phase
+        self.failed = 0
+        self.cancelled = 0
+        self._cancel = set()
 
-    def _try_admit(self, req: Request, now: float, active: List[_Slot], draining: int = 0) -> bool:
+    def cancel(self, rid: int) -> None:
+        """Cancels request rid wherever it is (not yet arrived, queued, active);
+        takes effect at the next server step boundary. Thread-safe."""
+        self._cancel.add(rid)
+
+    def _end(self, req: Request, status: str, result: Optional[dict], t0: float, finished: List[Request]) -> None:
+        req.status = status
+        req.result = result
+        req.done = self.clock() - t0
+        if status == "error":
+            self.failed += 1
+        elif status == "cancelled":
+            self.cancelled += 1
+        finished.append(req)
+
+    def _try_admit(self, req: Request, now: float, active: List[_Slot], draining: int = 0) -> str:
         resident, transient = self.ex.bytes_needed(req)
         if resident + transient > self.budget:
-            raise ValueError(f"request {req.rid} needs {resident + transient} bytes, budget {self.budget}")
+            req.result = dict(error=f"needs {resident + transient} bytes, more than the budget of {self.budget}")
+            return REJECTED
         if len(active) + draining >= self.max_active:
-            return False
+            return WAIT
         if self.reserved + resident + transient + self.ex.idle_bytes(req) > self.budget and self.ex.idle_bytes(req):
             self.ex.trim(req)
         if self.reserved + resident + transient + self.ex.idle_bytes(req) > self.budget:
-            return False
+            return WAIT
         self.reserved += resident + transient
         self.peak_reserved = max(self.peak_reserved, self.reserved)
         t = self.clock()
-        handle = self.ex.admit(req)
-        self.time_in["admit"] += self.clock() - t
+        try:
+            handle = self.ex.admit(req)
+        except Exception as e:  # noqa: BLE001  (one request's failure must not end the others)
+            self.reserved -= resident + transient
+            req.result = dict(error=f"admission failed: {type(e).__name__}: {e}")
+            return REJECTED
+        finally:
+            self.time_in["admit"] += self.clock() - t
         self.reserved -= transient
         req.admitted = now
         active.append(_Slot(req, handle, resident))
-        return True
+        return ADMITTED
+
+    def _retire(self, s: _Slot, status: str, result: dict, t0: float, finished: List[Request]) -> None:
+        """Ends an active or draining slot that did not complete normally."""
+        try:
+            self.ex.release(s.handle)
+        except Exception as e:  # noqa: BLE001
+            result = dict(result, release_error=f"{type(e).__name__}: {e}")
+        self.reserved -= s.reserved
+        self._end(s.req, status, result, t0, finished)
 
     def _complete(self, s: _Slot, t0: float, finished: List[Request]) -> None:
         t = self.clock()
-        s.req.result = self.ex.finish(s.handle)
-        s.req.done = self.clock() - t0
+        try:
+            result = self.ex.finish(s.handle)
+        except Exception as e:  # noqa: BLE001
+            self._retire(s, "error", dict(error=f"completion failed: {type(e).__name__}: {e}"), t0, finished)
+            self.time_in["finish"] += self.clock() - t
+            return
         self.ex.release(s.handle)
         self.time_in["finish"] += self.clock() - t
         self.reserved -= s.reserved
-        finished.append(s.req)
+        self._end(s.req, "ok", result, t0, finished)
+
+    def _expired(self, req: Request, now: float) -> bool:
+        return req.rid in self._cancel or (req.deadline is not None and now - req.arrival > req.deadline)
 
     def run(self, requests: Sequence[Request]) -> List[Request]:
         pending = sorted(requests, key=lambda r: r.arrival)
@@ -193,8 +247,28 @@ class Server:
             while i < len(pending) and pending[i].arrival <= now:
                 queue.append(pending[i])
                 i += 1
-            while queue and self._try_admit(queue[0], self.clock() - t0, active, len(draining)):
-                queue.pop(0)
+            # cancellations and deadlines (queued and active requests)
+            keep = []
+            for r in queue:
+                if self._expired(r, now):
+                    self._end(r, "cancelled", dict(cancelled=True), t0, finished)
+                else:
+                    keep.append(r)
+            queue = keep
+            keep = []
+            for s in active:
+                if self._expired(s.req, now):
+                    self._retire(s, "cancelled", dict(cancelled=True, steps_done=s.done_steps), t0, finished)
+                else:
+                    keep.append(s)
+            active = keep
+            while queue:
+                outcome = self._try_admit(queue[0], self.clock() - t0, active, len(draining))
+                if outcome == WAIT:
+                    break
+                r = queue.pop(0)
+                if outcome == REJECTED:
+                    self._end(r, "error", r.result, t0, finished)
             if not active:
                 if draining:
                     self.ex.finish_wait(draining[0].handle)
@@ -202,12 +276,17 @@ class Server:
                     self.sleep(max(0.0, pending[i].arrival - (self.clock() - t0)))
                 continue
             t = self.clock()
-            self.ex.step([s.handle for s in active])
+            failures = self.ex.step([s.handle for s in active]) or []
             self.time_in["step"] += self.clock() - t
             self.steps_run += 1
             self.batch_sizes.append(len(active))
+            bad = dict(failures)
             still = []
-            for s in active:
+            for k, s in enumerate(active):
+                if k in bad:
+                    self._retire(s, "error", dict(error=f"step failed: {bad[k]}", steps_done=s.done_steps), t0,
+                                 finished)
+                    continue
                 s.done_steps += 1
                 if s.done_steps >= s.req.steps:
                     self.ex.finish_start(s.handle)
@@ -219,14 +298,18 @@ class Server:
 
 
 def latency_summary(reqs: Sequence[Request]) -> dict:
-    lat = np.array([r.latency for r in reqs if r.latency is not None])
+    """Latency percentiles and throughput over the requests that completed
+    (failed and cancelled ones are counted apart)."""
+    ok = [r for r in reqs if r.latency is not None and r.status in ("ok", "pending")]
+    lat = np.array([r.latency for r in ok])
     if lat.size == 0:
         return {}
-    span = max(r.done for r in reqs) - min(r.arrival for r in reqs)
-    mv = sum(r.steps for r in reqs)
+    span = max(r.done for r in ok) - min(r.arrival for r in ok)
+    mv = sum(r.steps for r in ok)
     return dict(requests=int(lat.size), p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
                 mean_s=float(lat.mean()), max_s=float(lat.max()), span_s=float(span),
-                requests_per_s=float(lat.size / span), matvecs_per_s=float(mv / span))
+                requests_per_s=float(lat.size / span), matvecs_per_s=float(mv / span),
+                failed=sum(r.status == "error" for r in reqs), cancelled=sum(r.status == "cancelled" for r in reqs))
 
 
 # ---------------------------------------------------------------------------
@@ -334,8 +417,12 @@ class GpuExecutor(Executor):
         # Hessenberg matrix stored by columns: Hc[j] is column j (contiguous);
         # Hc[steps][0] receives ||b||
         Hc = torch.zeros((req.steps + 1, req.steps + 1), dtype=torch.complex128, device="cuda")
-        slot = dict(req=req, plan=plan, basis=basis, w=torch.empty(vlen, dtype=self.tdt, device="cuda"), Hc=Hc,
-                    ws=plan.alloc_workspace(1), j=0, shape=(1, b) + tuple(n))
+        ws = plan.alloc_workspace(1)
+        w = torch.empty(vlen, dtype=self.tdt, device="cuda")
+        slot = dict(req=req, plan=plan, basis=basis, w=w, Hc=Hc, ws=ws, j=0, shape=(1, b) + tuple(n),
+                    # raw pointers for the one-call step (sfft_apply_each)
+                    ptr=(plan.handle.value, basis.data_ptr(), vlen * self.esz, w.data_ptr(),
+                         ws.data_ptr() if ws is not None else 0, ws.numel() if ws is not None else 0))
         # v_0 = b / ||b|| (an Arnoldi job with an empty basis)
         self._arnoldi([dict(V=basis, m=0, w=basis[0], vout=basis[0], hcol=Hc[req.steps])])
         return slot
@@ -369,23 +456,32 @@ class GpuExecutor(Executor):
         while len(self._inflight) > self.max_ahead:
             self._inflight.pop(0).synchronize()
 
-    def step(self, slots) -> None:
-        torch = self.torch
-        ev = torch.cuda.Event()
-        ev.record(self.main)
-        for i, s in enumerate(slots):  # w = T v_j, spread over streams
-            st = self.streams[i % len(self.streams)]
-            st.wait_event(ev)
-            s["plan"].apply(s["basis"][s["j"]].view(s["shape"]), s["w"].view(s["shape"]), s["ws"], stream=st)
-        for st in self.streams:
-            self.main.wait_stream(st)
-        jobs = []
-        for s in slots:
+    def step(self, slots):
+        """w = T v_j for every slot in one native call (sfft_apply_each: the
+        products spread over forked streams and joined back), then one batched
+        Arnoldi step; slots whose product failed are reported and skipped."""
+        N = self.N
+        k = len(slots)
+        plans, xs, ys = (C.c_void_p * k)(), (C.c_void_p * k)(), (C.c_void_p * k)()
+        nr, wss, wsb = (C.c_int64 * k)(*([1] * k)), (C.c_void_p * k)(), (C.c_size_t * k)()
+        status = (C.c_int * k)()
+        for i, s in enumerate(slots):
+            ph, base, vb, wp, wsp, wsn = s["ptr"]
+            plans[i], xs[i], ys[i], wss[i], wsb[i] = ph, base + s["j"] * vb, wp, wsp or None, wsn
+        N.check(N.lib.sfft_apply_each(k, plans, xs, ys, nr, wss, wsb, C.c_void_p(self.main.cuda_stream), status),
+                "sfft_apply_each")
+        failures, jobs = [], []
+        for i, s in enumerate(slots):
+            if status[i] != N.OK:
+                failures.append((i, f"{N._status_name(status[i])}"))
+                continue
             j = s["j"]
             jobs.append(dict(V=s["basis"], m=j + 1, w=s["w"], vout=s["basis"][j + 1], hcol=s["Hc"][j]))
             s["j"] = j + 1
-        self._arnoldi(jobs)
+        if jobs:
+            self._arnoldi(jobs)
         self._throttle()
+        return failures
 
     def finish_start(self, slot) -> None:
         torch = self.torch
@@ -453,10 +549,11 @@ class SingleRequestExecutor(GpuExecutor):
     """The plain path: one request at a time, no overlap (used with
     max_active=1), same kernels; typically FP64 and full symbols."""
 
-    def step(self, slots) -> None:
+    def step(self, slots):
         for s in slots:
             s["plan"].apply(s["basis"][s["j"]].view(s["shape"]), s["w"].view(s["shape"]), s["ws"], stream=self.main)
             j = s["j"]
             self._arnoldi([dict(V=s["basis"], m=j + 1, w=s["w"], vout=s["basis"][j + 1], hcol=s["Hc"][j])])
             s["j"] = j + 1
         self._throttle()
+        return []

@@ -64,7 +64,9 @@ def test_gmres_green_32(sf, lo_dtype, m, tol):
 
 
 def test_gmres_trivial_cases(sf):
-    """chi = 0 gives x = b after one cycle of one step; b = 0 gives x = 0 with
+    """chi = 0 (A = I) gives x = b with at most two complex64 products (one
+    step leaves the complex64 rounding of b / ||b||, which one more step, in
+    the same cycle or after an FP64 restart, removes); b = 0 gives x = 0 with
     nothing to do; a wrong plan pairing or workspace is refused."""
     n, b = (8, 6, 10), 3
     coeffs = wl.green_coeffs(n, 0.9)
@@ -74,8 +76,8 @@ def test_gmres_trivial_cases(sf):
     rhs = torch.from_numpy(wl.vectors(504, n, b, 1)[0]).cuda()
     zero = torch.zeros_like(rhs)
     x, info = sf.gmres_solve(lo, hi, zero, rhs, m=5, tol=1e-12)
-    assert info["converged"] and info["matvecs"] == 1
-    assert torch.allclose(x, rhs, rtol=0, atol=1e-6 * rhs.abs().max().item())
+    assert info["converged"] and info["cycles"] <= 2 and info["matvecs"] <= 2, info
+    assert torch.allclose(x, rhs, rtol=0, atol=1e-11 * rhs.abs().max().item())
     x, info = sf.gmres_solve(lo, hi, zero, zero, m=5, tol=1e-12)
     assert info["converged"] and info["matvecs"] == 0 and torch.count_nonzero(x) == 0
     other = sf.Plan((8, 6, 12), b, torch.from_numpy(wl.green_coeffs((8, 6, 12), 0.9)).cuda(), dtype="c128")

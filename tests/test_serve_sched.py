@@ -104,11 +104,96 @@ def test_max_active_slots_are_reused():
     assert len(done) == 7 and max(srv.batch_sizes) == 2
 
 
-def test_request_larger_than_budget_is_an_error():
-    reqs = [Request(rid=0, arrival=0.0, n=(64, 64), k=1.0, steps=3)]
-    srv, ex, _ = _make(budget=100, sizes={(64, 64): 1000})
-    with pytest.raises(ValueError):
-        srv.run(reqs)
+def test_request_larger_than_budget_fails_alone():
+    """An oversized request ends with an error result; the requests around it
+    are served normally and every byte is returned."""
+    reqs = [Request(rid=0, arrival=0.0, n=(8, 8), k=1.0, steps=3),
+            Request(rid=1, arrival=0.0, n=(64, 64), k=1.0, steps=3),
+            Request(rid=2, arrival=0.001, n=(8, 8), k=1.0, steps=3)]
+    srv, ex, _ = _make(budget=100, sizes={(64, 64): 1000, (8, 8): 10})
+    done = {r.rid: r for r in srv.run(reqs)}
+    assert done[1].status == "error" and "budget" in done[1].result["error"]
+    assert done[0].status == "ok" and done[2].status == "ok"
+    assert done[0].result["steps"] == 3 and done[2].result["steps"] == 3
+    assert srv.reserved == 0 and srv.failed == 1
+
+
+class FailingExecutor(MockExecutor):
+    """Admission of `bad_admit` raises (an allocation failure); the step of
+    `bad_step` fails at its second step."""
+
+    def __init__(self, *a, bad_admit=(), bad_step=(), **k):
+        super().__init__(*a, **k)
+        self.bad_admit, self.bad_step = set(bad_admit), set(bad_step)
+        self.released = []
+
+    def admit(self, req):
+        if req.rid in self.bad_admit:
+            raise MemoryError("hipMalloc: out of memory (injected)")
+        return super().admit(req)
+
+    def step(self, slots):
+        super().step(slots)
+        return [(i, "HIP_ERROR (injected)") for i, r in enumerate(slots)
+                if r.rid in self.bad_step and self.steps[r.rid] == 2]
+
+    def release(self, slot):
+        self.released.append(slot.rid)
+
+
+def _make_failing(budget, sizes, **kw):
+    clock = FakeClock()
+    ref = [None]
+    ex = FailingExecutor(clock, ref, sizes, **kw)
+    srv = Server(ex, budget, clock=clock, sleep=clock.sleep)
+    ref[0] = srv
+    return srv, ex, clock
+
+
+def test_admission_and_step_failures_are_isolated():
+    """One admission raising and one request's step failing end those two
+    requests with error results (the failed step's slot is released and its
+    memory returned); the rest finish with their full step counts."""
+    reqs = [Request(rid=i, arrival=0.001 * i, n=(8, 8), k=1.0, steps=4) for i in range(6)]
+    srv, ex, _ = _make_failing(budget=1000, sizes={(8, 8): 10}, bad_admit={1}, bad_step={3})
+    done = {r.rid: r for r in srv.run(reqs)}
+    assert len(done) == 6
+    assert done[1].status == "error" and "out of memory" in done[1].result["error"]
+    assert done[3].status == "error" and done[3].result["steps_done"] == 1 and "injected" in done[3].result["error"]
+    for rid in (0, 2, 4, 5):
+        assert done[rid].status == "ok" and done[rid].result["steps"] == 4
+    assert 3 in ex.released and 1 not in ex.released
+    assert srv.reserved == 0 and srv.failed == 2
+    summ = latency_summary(list(done.values()))
+    assert summ["requests"] == 4 and summ["failed"] == 2
+
+
+def test_cancellation_and_deadlines():
+    """A cancelled queued request never runs; a cancelled active one stops at
+    the next step boundary and is released; a request past its deadline is
+    cancelled; the others are unaffected."""
+    reqs = [Request(rid=0, arrival=0.0, n=(8, 8), k=1.0, steps=50),
+            Request(rid=1, arrival=0.0, n=(8, 8), k=1.0, steps=5),
+            Request(rid=2, arrival=0.0, n=(8, 8), k=1.0, steps=50),
+            Request(rid=3, arrival=0.0, n=(8, 8), k=1.0, steps=500, deadline=0.1),
+            Request(rid=4, arrival=0.0, n=(8, 8), k=1.0, steps=5)]
+    srv, ex, clock = _make_failing(budget=60, sizes={(8, 8): 10})
+    orig_step = ex.step
+
+    def step(slots):
+        if ex.steps.get(0) == 10:
+            srv.cancel(0)   # active
+            srv.cancel(2)   # ... and another one
+        return orig_step(slots)
+    ex.step = step
+    srv.cancel(1)           # cancelled before it is admitted
+    done = {r.rid: r for r in srv.run(reqs)}
+    assert done[1].status == "cancelled" and 1 not in ex.steps
+    assert done[0].status == "cancelled" and done[0].result["steps_done"] == 11
+    assert done[2].status == "cancelled" and done[2].result["steps_done"] == 11
+    assert done[3].status == "cancelled" and done[3].result["steps_done"] < 500
+    assert done[4].status == "ok" and done[4].result["steps"] == 5
+    assert srv.reserved == 0 and srv.cancelled == 4
 
 
 def test_poisson_stream_statistics():
