@@ -155,6 +155,20 @@ sfft_status sfft_workspace_size(sfft_plan plan, int64_t nrhs, size_t* bytes);
 sfft_status sfft_apply(sfft_plan plan, const void* x, void* y, int64_t nrhs, void* workspace,
                        size_t ws_bytes, void* stream);
 
+/* sfft_apply for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc. The
+ * same product as sfft_apply (same kernels and schedule), with the workspace
+ * taken from a static device array of the library (128 MiB per device, held
+ * until the process ends) instead of a caller buffer or a plan-owned pool; the
+ * call allocates nothing and records no profiling events.
+ *   Errors: SFFT_INVALID_ARG when the workspace sfft_workspace_size reports for
+ *   nrhs exceeds 128 MiB (nothing is launched), and as sfft_apply otherwise.
+ * Every call on one device shares that device's array: calls that overlap on
+ * one device (other host threads, or other streams not ordered after this
+ * one) race on it. The array needs no clearing (every pass writes before it
+ * reads). The current device must be the plan's device. */
+sfft_status sfft_apply_noalloc(sfft_plan plan, const void* x, void* y, int64_t nrhs, void* stream);
+
 /* The conjugate transpose, y = T^H x: T^H is block Toeplitz with generator
  * t^H(r) = t(-r)^H, whose embedded symbol is the conjugate transpose of T's at
  * every bin (Section II's embedding with the generator reversed), so the

@@ -389,6 +389,39 @@ unsigned grid_for(int64_t total, int block = 256) {
 }  // namespace
 
 
+// Scratch of sfft_apply_noalloc: a file-scope device array (each device holds
+// its own copy, in the library's code object, for the life of the process).
+// Host code never uses the array's name as an address: the device address
+// comes from hipGetSymbolAddress, once per device with that device current.
+constexpr size_t kNoAllocScratchBytes = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {nullptr};
+
+// Device address of the current device's scratch array (looked up once per device).
+sfft_status noalloc_scratch(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(SFFT_UNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!ptr) return fail(SFFT_HIP_ERROR, "hipGetSymbolAddress(scratch) returned null");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return SFFT_OK;
+}
+
+}  // namespace
+
 namespace {
 
 int64_t vec_elems(const sfft_plan_s* p, int64_t nrhs) { return nrhs * p->b * p->s; }
@@ -431,13 +464,17 @@ hipEvent_t take_event(sfft_plan_s* p) {
 }
 
 // RAII bracket: records an event pair around one launch when its kind is profiled.
+// Set while sfft_apply_noalloc runs on this thread: the profiling hooks then
+// record nothing (taking an event may create one).
+thread_local bool g_noalloc = false;
+
 struct ProfScope {
   sfft_plan_s* p;
   hipStream_t st;
   int kind;
   hipEvent_t a = nullptr, b = nullptr;
   ProfScope(const sfft_plan_s* pc, int k, hipStream_t s) : p(const_cast<sfft_plan_s*>(pc)), st(s), kind(k) {
-    if (p->prof_mask & (1u << k)) {
+    if (!g_noalloc && (p->prof_mask & (1u << k))) {
       {
         std::lock_guard<std::mutex> g(p->prof_mu);
         a = take_event(p);
@@ -1153,6 +1190,25 @@ sfft_status sfft_apply(sfft_plan plan, const void* x, void* y, int64_t nrhs, voi
                        void* stream) {
   if (!plan) return fail(SFFT_INVALID_ARG, "plan is null");
   return apply_one(plan, x, y, nrhs, workspace, ws_bytes, (hipStream_t)stream, false);
+}
+
+sfft_status sfft_apply_noalloc(sfft_plan plan, const void* x, void* y, int64_t nrhs, void* stream) {
+  if (!plan) return fail(SFFT_INVALID_ARG, "plan is null");
+  if (nrhs < 0) return fail(SFFT_INVALID_ARG, "nrhs must be >= 0");
+  const size_t need = nrhs == 0 ? 0 : workspace_elems(plan, nrhs) * plan->esz;
+  if (need > kNoAllocScratchBytes)
+    return fail(SFFT_INVALID_ARG, "sfft_apply_noalloc needs " + std::to_string(need) +
+                                      " bytes of workspace; its static scratch holds " +
+                                      std::to_string(kNoAllocScratchBytes));
+  void* ws = nullptr;
+  if (need > 0) {
+    sfft_status s = noalloc_scratch(&ws);
+    if (s != SFFT_OK) return s;
+  }
+  g_noalloc = true;
+  sfft_status s = apply_one(plan, x, y, nrhs, ws, need, (hipStream_t)stream, false);
+  g_noalloc = false;
+  return s;
 }
 
 sfft_status sfft_plan_enable_adjoint(sfft_plan plan, void* stream) {
