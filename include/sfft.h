@@ -169,6 +169,32 @@ sfft_status sfft_apply(sfft_plan plan, const void* x, void* y, int64_t nrhs, voi
  * reads). The current device must be the plan's device. */
 sfft_status sfft_apply_noalloc(sfft_plan plan, const void* x, void* y, int64_t nrhs, void* stream);
 
+/* Out-of-core product for vectors that stay in host memory (the paper's
+ * remark on larger systems: the input pre-partitioned into nearly independent
+ * even and odd parts). After the level-1 split the two children are
+ * independent products over levels 2..d, and every level-1 frequency index
+ * of a child is independent of the others, so the product runs as
+ *   1. column slabs of x to the device, level-1 forward pass (both children),
+ *      children back to the host workspace;
+ *   2. per child, slabs of consecutive level-1 indices to the device, levels
+ *      2..d depth-first there (the plan's symbols stay on the device), back;
+ *   3. column slabs of both children to the device, level-1 inverse pass and
+ *      merge, y back to the host.
+ * The device holds the plan and slabs only. Results equal sfft_apply's
+ * depth-first product bit for bit (same kernels, same per-pencil work).
+ *   x_host, y_host  host (nrhs, b, n...) of the plan dtype, preferably pinned
+ *                   (hipHostMalloc) so the copies run asynchronously.
+ *   host_ws         host, 2 * nrhs * b * prod(n) entries: the two children.
+ *   device_ws       device, its size is the budget: sfft_ooc_sizes tells the
+ *                   bytes a budget actually uses (SFFT_INVALID_ARG when one
+ *                   slab does not fit).
+ * Split plans with d >= 2 only (SFFT_UNSUPPORTED otherwise). Synchronous:
+ * returns when y_host is complete. */
+sfft_status sfft_ooc_sizes(sfft_plan plan, int64_t nrhs, size_t device_budget, size_t* host_ws_bytes,
+                           size_t* device_ws_bytes);
+sfft_status sfft_apply_ooc(sfft_plan plan, const void* x_host, void* y_host, int64_t nrhs, void* host_ws,
+                           size_t host_ws_bytes, void* device_ws, size_t device_ws_bytes, void* stream);
+
 /* The conjugate transpose, y = T^H x: T^H is block Toeplitz with generator
  * t^H(r) = t(-r)^H, whose embedded symbol is the conjugate transpose of T's at
  * every bin (Section II's embedding with the generator reversed), so the

@@ -28,7 +28,7 @@ EXPORTS = [
     "sfft_last_error", "sfft_length_supported", "sfft_profile_enable", "sfft_profile_read",
     "sfft_plan_autotune", "sfft_arnoldi_scratch_size", "sfft_arnoldi_step_multi", "sfft_plan_update",
     "sfft_plan_enable_adjoint", "sfft_apply_adjoint", "sfft_gmres_workspace_size", "sfft_gmres_solve",
-    "sfft_apply_noalloc", "sfft_apply_each",
+    "sfft_apply_noalloc", "sfft_apply_each", "sfft_ooc_sizes", "sfft_apply_ooc",
 ]
 KIND_FORWARD, KIND_LEAF, KIND_INVERSE, KIND_COPY = range(4)
 
@@ -82,6 +82,8 @@ def _load():
     lib.sfft_plan_enable_adjoint.argtypes = [vp, vp]
     lib.sfft_apply_adjoint.argtypes = [vp, vp, vp, i64, vp, sz, vp]
     lib.sfft_apply_noalloc.argtypes = [vp, vp, vp, i64, vp]
+    lib.sfft_ooc_sizes.argtypes = [vp, i64, sz, C.POINTER(sz), C.POINTER(sz)]
+    lib.sfft_apply_ooc.argtypes = [vp, vp, vp, i64, vp, sz, vp, sz, vp]
     lib.sfft_apply_each.argtypes = [C.c_int, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), P64, C.POINTER(vp),
                                     C.POINTER(sz), vp, C.POINTER(C.c_int)]
     lib.sfft_gmres_workspace_size.argtypes = [vp, vp, C.c_int, C.POINTER(sz)]

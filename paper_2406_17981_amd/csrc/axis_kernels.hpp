@@ -72,6 +72,12 @@ struct PassArgs {
   int64_t npen;      // pencils per component per right-hand side
   int64_t nrhs;
   int64_t ntiles;    // ceil(npen / P)
+  // a slab of the pencils (out-of-core apply): the launch's pencil 0 is global
+  // pencil pen0 = tile0 * P of a plan whose symbols hold sym_ntiles tiles per
+  // parity (pen0 = tile0 = 0 and sym_ntiles = ntiles for a whole vector)
+  int64_t pen0;
+  int64_t tile0;
+  int64_t sym_ntiles;
   int rb;            // right-hand sides per workgroup
   // LEAF with mirrored symbol storage (Section II.C): per component a
   // (n_1+1) x ... x (n_d+1) array; along level l the first n_l/2+1 entries
@@ -494,7 +500,7 @@ __global__ void __launch_bounds__((Geo<Real, L>::RBMAX * Geo<Real, L>::SL)) k_le
   uint32_t mbits = 0;
   if constexpr (MIR) {
     const int64_t Q = a.q0 + q;
-    int64_t rem = p0 + (g < nh ? g : 0);
+    int64_t rem = a.pen0 + p0 + (g < nh ? g : 0);
     for (int l = a.d - 2; l >= 0; --l) {
       const int64_t n = a.mn[l];
       const int64_t j = rem % n;
@@ -532,7 +538,7 @@ __global__ void __launch_bounds__((Geo<Real, L>::RBMAX * Geo<Real, L>::SL)) k_le
   C2 pf[NPF][NS];
   C2 pf1[PF1 ? NS : 1];
   auto sym_base = [&](int p) {
-    return (const C*)a.sym + q * a.sym_bs + ((int64_t)p * a.ntiles + tile) * (NS * E * SL);
+    return (const C*)a.sym + q * a.sym_bs + ((int64_t)p * a.sym_ntiles + a.tile0 + tile) * (NS * E * SL);
   };
   if constexpr (!MIR && MSP == 2) {
 #pragma unroll
@@ -570,7 +576,7 @@ __global__ void __launch_bounds__((Geo<Real, L>::RBMAX * Geo<Real, L>::SL)) k_le
         for (int k = 0; k < NS; ++k) pf1[k] = *(const C2*)(sym_base(1) + sym_offset(k, 0, slane, E, SL));
       }
     }
-    const C* sp = (const C*)a.sym + q * a.sym_bs + ((int64_t)p * a.ntiles + tile) * (NS * E * SL);
+    const C* sp = (const C*)a.sym + q * a.sym_bs + ((int64_t)p * a.sym_ntiles + a.tile0 + tile) * (NS * E * SL);
     constexpr int MS = (E % 2 == 0) ? 2 : 1;  // entries per symbol load
 #pragma unroll
     for (int m0 = 0; m0 < E; m0 += MS) {

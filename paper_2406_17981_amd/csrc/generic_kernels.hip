@@ -221,7 +221,7 @@ __global__ void __launch_bounds__(256) k_gen_leaf(PassArgs a, GenPlan g) {
   uint32_t osign = 0, lodd = 0;
   if constexpr (MIR) {
     const int64_t Q = a.q0 + q;
-    int64_t rem = pen;
+    int64_t rem = a.pen0 + pen;
     uint32_t mbits = 0;
     for (int l = a.d - 2; l >= 0; --l) {
       const int64_t n = a.mn[l];
@@ -264,7 +264,7 @@ __global__ void __launch_bounds__(256) k_gen_leaf(PassArgs a, GenPlan g) {
       }
     }
     // mulBrn: per bin, the b x b block of child p's symbol times the b spectra
-    const C* sp = (const C*)a.sym + q * a.sym_bs + ((int64_t)p * a.ntiles + pen) * (int64_t)NS * L;
+    const C* sp = (const C*)a.sym + q * a.sym_bs + ((int64_t)p * a.sym_ntiles + a.tile0 + pen) * (int64_t)NS * L;
     for (int m = threadIdx.x; m < L; m += blockDim.x) {
       C sv[NS];
       if constexpr (MIR) {

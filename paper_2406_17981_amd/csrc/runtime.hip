@@ -434,18 +434,30 @@ size_t workspace_elems(const sfft_plan_s* p, int64_t nrhs) {
   return (size_t)(((int64_t(1) << p->d) - 2) * V);
 }
 
-// Pass geometry of level l (0-based) for vectors (nv, L_0, ..., L_{d-1}).
-void level_geom(const sfft_plan_s* p, int l, int64_t nv, int64_t& outer, int64_t& inner) {
+// The part of the vectors one product works on: all of them, or (out-of-core
+// apply) a slab of len0 consecutive level-1 indices, whose leaf pencils are
+// npen consecutive pencils from global pencil pen0 (a tile boundary).
+struct Slab {
+  int64_t len0;     // entries along level 1 (L_0 for whole vectors)
+  int64_t pen0;     // global index of the slab's first leaf pencil
+  int64_t npen;     // leaf pencils per component per right-hand side
+  int first_level;  // level the depth-first walk starts at (0-based)
+};
+
+Slab whole(const sfft_plan_s* p) { return Slab{p->L[0], 0, p->npen, 0}; }
+
+// Pass geometry of level l (0-based) for vectors (nv, len0, L_1, ..., L_{d-1}).
+void level_geom(const sfft_plan_s* p, int l, int64_t nv, int64_t& outer, int64_t& inner, int64_t len0) {
   outer = nv;
-  for (int m = 0; m < l; ++m) outer *= p->L[m];
+  for (int m = 0; m < l; ++m) outer *= m == 0 ? len0 : p->L[m];
   inner = 1;
   for (int m = l + 1; m < p->d; ++m) inner *= p->L[m];
 }
 
-PassArgs base_args(const sfft_plan_s* p, int l, int64_t nv) {
+PassArgs base_args(const sfft_plan_s* p, int l, int64_t nv, int64_t len0) {
   PassArgs a;
   std::memset(&a, 0, sizeof(a));
-  level_geom(p, l, nv, a.outer, a.inner);
+  level_geom(p, l, nv, a.outer, a.inner, len0);
   a.tw = p->tw[l];
   a.len = p->L[l];
   a.nq = 1;
@@ -507,7 +519,7 @@ sfft_status run_pass(const sfft_plan_s* p, int l, int mode, const PassArgs& a, h
 // Leaf pass over branches q0 .. q0+nq-1 of levels 1..d-1 (q0 only matters
 // for the symbols: its bits are the branch's parities).
 sfft_status run_leaf(const sfft_plan_s* p, const void* in, void* out, int64_t in_bs, int64_t nq, int64_t q0,
-                     int64_t nrhs, hipStream_t st, bool adj) {
+                     int64_t nrhs, hipStream_t st, bool adj, const Slab& sl) {
   const int l = p->d - 1;
   const AxisOps* o = p->ops[l];
   PassArgs a;
@@ -519,9 +531,12 @@ sfft_status run_leaf(const sfft_plan_s* p, const void* in, void* out, int64_t in
   a.nq = nq;
   a.tw = p->tw[l];
   a.len = p->L[l];
-  a.npen = p->npen;
+  a.npen = sl.npen;
   a.nrhs = nrhs;
-  a.ntiles = p->ntiles;
+  a.ntiles = (sl.npen + o->PL - 1) / o->PL;
+  a.pen0 = sl.pen0;
+  a.tile0 = sl.pen0 / o->PL;
+  a.sym_ntiles = p->ntiles;
   // right-hand sides per workgroup: they share each symbol load
   int rb = 1;
   if (p->rb_pref > 0) {
@@ -558,23 +573,24 @@ sfft_status run_leaf(const sfft_plan_s* p, const void* in, void* out, int64_t in
 
 // Depth-first (Algorithm 1 order): src holds the branch after levels < l were
 // transformed; dst receives that branch's merged result. Level l's odd child
-// lives in workspace vector l-1.
+// lives in workspace vector l - sl.first_level (levels 0-based).
 sfft_status split_depth(const sfft_plan_s* p, int l, const void* src, void* dst, int64_t q, int64_t nrhs,
-                        char* ws, hipStream_t st, bool adj) {
-  const int64_t V = vec_elems(p, nrhs);
+                        char* ws, hipStream_t st, bool adj, const Slab& sl) {
   const int64_t nv = nrhs * p->b;
-  if (l == p->d - 1) return run_leaf(p, src, dst, V, 1, q, nrhs, st, adj);
-  void* odd = ws + (size_t)l * V * p->esz;
-  PassArgs a = base_args(p, l, nv);
+  const int64_t V = nv * (p->s / p->L[0]) * sl.len0;
+  if (l == p->d - 1) return run_leaf(p, src, dst, V, 1, q, nrhs, st, adj, sl);
+  // the odd child of level l lives in workspace vector l - first_level
+  void* odd = ws + (size_t)(l - sl.first_level) * V * p->esz;
+  PassArgs a = base_args(p, l, nv, sl.len0);
   a.in = src;
   a.out = dst;
   a.out1 = odd;
   a.use_phase = 1;
   sfft_status s = run_pass(p, l, 0, a, st);
   if (s != SFFT_OK) return s;
-  if ((s = split_depth(p, l + 1, dst, dst, 2 * q, nrhs, ws, st, adj)) != SFFT_OK) return s;
-  if ((s = split_depth(p, l + 1, odd, odd, 2 * q + 1, nrhs, ws, st, adj)) != SFFT_OK) return s;
-  PassArgs b = base_args(p, l, nv);
+  if ((s = split_depth(p, l + 1, dst, dst, 2 * q, nrhs, ws, st, adj, sl)) != SFFT_OK) return s;
+  if ((s = split_depth(p, l + 1, odd, odd, 2 * q + 1, nrhs, ws, st, adj, sl)) != SFFT_OK) return s;
+  PassArgs b = base_args(p, l, nv, sl.len0);
   b.in = dst;
   b.in1 = odd;
   b.out = dst;
@@ -589,7 +605,7 @@ sfft_status split_breadth(const sfft_plan_s* p, const void* x, void* y, int64_t 
   const int d = p->d;
   const int64_t V = vec_elems(p, nrhs);
   const int64_t nv = nrhs * p->b;
-  if (d == 1) return run_leaf(p, x, y, V, 1, 0, nrhs, st, adj);
+  if (d == 1) return run_leaf(p, x, y, V, 1, 0, nrhs, st, adj, whole(p));
   char* blk[kMaxD];
   size_t off = 0;
   for (int l = 0; l < d - 1; ++l) {
@@ -598,7 +614,7 @@ sfft_status split_breadth(const sfft_plan_s* p, const void* x, void* y, int64_t 
   }
   sfft_status s;
   for (int l = 0; l < d - 1; ++l) {
-    PassArgs a = base_args(p, l, nv);
+    PassArgs a = base_args(p, l, nv, p->L[0]);
     a.in = l == 0 ? x : (const void*)blk[l - 1];
     a.in_bs = V;
     a.nq = int64_t(1) << l;
@@ -608,10 +624,10 @@ sfft_status split_breadth(const sfft_plan_s* p, const void* x, void* y, int64_t 
     a.use_phase = 1;
     if ((s = run_pass(p, l, 0, a, st)) != SFFT_OK) return s;
   }
-  if ((s = run_leaf(p, blk[d - 2], blk[d - 2], V, int64_t(1) << (d - 1), 0, nrhs, st, adj)) != SFFT_OK)
+  if ((s = run_leaf(p, blk[d - 2], blk[d - 2], V, int64_t(1) << (d - 1), 0, nrhs, st, adj, whole(p))) != SFFT_OK)
     return s;
   for (int l = d - 2; l >= 0; --l) {
-    PassArgs a = base_args(p, l, nv);
+    PassArgs a = base_args(p, l, nv, p->L[0]);
     a.in = blk[l];
     a.in1 = blk[l] + V * p->esz;
     a.in_bs = 2 * V;
@@ -654,15 +670,15 @@ sfft_status embed_apply(const sfft_plan_s* p, const void* x, void* y, int64_t nr
   HIP_TRY(hipGetLastError(), "pad launch");
   sfft_status s;
   for (int l = 0; l < d - 1; ++l) {
-    PassArgs a = base_args(p, l, nv);
+    PassArgs a = base_args(p, l, nv, p->L[0]);
     a.in = ws;
     a.out = ws;
     if ((s = run_pass(p, l, 0, a, st)) != SFFT_OK) return s;
   }
   const int64_t Vbig = big;
-  if ((s = run_leaf(p, ws, ws, Vbig, 1, 0, nrhs, st, adj)) != SFFT_OK) return s;
+  if ((s = run_leaf(p, ws, ws, Vbig, 1, 0, nrhs, st, adj, whole(p))) != SFFT_OK) return s;
   for (int l = d - 2; l >= 0; --l) {
-    PassArgs a = base_args(p, l, nv);
+    PassArgs a = base_args(p, l, nv, p->L[0]);
     a.in = ws;
     a.out = ws;
     if ((s = run_pass(p, l, 1, a, st)) != SFFT_OK) return s;
@@ -974,8 +990,128 @@ sfft_status apply_one(sfft_plan_s* p, const void* x, void* y, int64_t nrhs, void
   }
   if (adj && !p->sym_adj) return fail(SFFT_INVALID_ARG, "adjoint symbols not built (sfft_plan_enable_adjoint)");
   if (p->method == SFFT_EMBED) return embed_apply(p, x, y, nrhs, (char*)ws, st, adj);
-  if (p->sched == SFFT_SCHED_DEPTH && p->d > 1) return split_depth(p, 0, x, y, 0, nrhs, (char*)ws, st, adj);
+  if (p->sched == SFFT_SCHED_DEPTH && p->d > 1) return split_depth(p, 0, x, y, 0, nrhs, (char*)ws, st, adj, whole(p));
   return split_breadth(p, x, y, nrhs, (char*)ws, st, adj);
+}
+
+// Out-of-core apply (the paper's remark on larger systems: the input
+// pre-partitioned into even and odd parts that are processed independently).
+// After the level-1 split the two children are independent products over
+// levels 2..d, and along level 1 (now in the frequency domain) every index
+// j_1 is independent too. So, with x, y and the two children in host memory:
+//   1. column slabs (all of level 1, a range of the other indices) go to the
+//      device, the level-1 forward pass splits them into both children, which
+//      return to the host;
+//   2. for each child, row slabs (a range of j_1, everything else) go to the
+//      device and run levels 2..d depth-first there, results back in place;
+//   3. column slabs of both children come back for the level-1 inverse pass
+//      and merge, which writes y.
+// Device memory holds only slabs (sized from the given budget) and the plan.
+struct OocGeom {
+  int64_t nv, inner, rowlen;  // vectors, columns per level-1 index, entries per (vector, j_1)
+  int64_t w;                  // columns per slab of steps 1 and 3
+  int64_t c;                  // level-1 indices per slab of step 2
+  size_t dev_bytes;           // device workspace used
+};
+
+sfft_status ooc_geometry(const sfft_plan_s* p, int64_t nrhs, size_t budget, OocGeom* g) {
+  if (p->method != SFFT_SPLIT) return fail(SFFT_UNSUPPORTED, "out-of-core apply needs a split plan");
+  if (p->d < 2) return fail(SFFT_UNSUPPORTED, "out-of-core apply needs at least two levels");
+  const int64_t esz = (int64_t)p->esz;
+  g->nv = nrhs * p->b;
+  g->inner = p->s / p->L[0];
+  g->rowlen = g->inner;
+  // step 1 / 3: an input slab and two output slabs of nv x L_0 x w entries
+  const int64_t per_col = 3 * g->nv * p->L[0] * esz;
+  g->w = (int64_t)budget / per_col;
+  if (g->w > g->inner) g->w = g->inner;
+  // step 2: the slab in place plus d - 2 depth-first workspace slabs, each
+  // nv x c x rowlen entries; c keeps the slab's first pencil on a tile boundary
+  const int64_t per_row = (p->d - 1) * g->nv * g->rowlen * esz;
+  const AxisOps* lo = p->ops[p->d - 1];
+  const int64_t pen_per_row = p->npen / p->L[0];
+  int64_t step = 1;
+  while ((step * pen_per_row) % lo->PL) ++step;
+  if (step > p->L[0]) step = p->L[0];  // then one slab holds every level-1 index
+  g->c = (int64_t)budget / per_row;
+  g->c = g->c >= p->L[0] ? p->L[0] : g->c / step * step;
+  if (g->w < 1 || g->c < 1)
+    return fail(SFFT_INVALID_ARG, "device budget too small for one out-of-core slab: need " +
+                                      std::to_string(per_col > per_row * step ? per_col : per_row * step) + " bytes");
+  const int64_t b1 = per_col * g->w, b2 = per_row * g->c;
+  g->dev_bytes = (size_t)(b1 > b2 ? b1 : b2);
+  return SFFT_OK;
+}
+
+// 2-D copy of `rows` runs of `width` bytes between pitched buffers
+hipError_t copy2d(void* dst, size_t dpitch, const void* src, size_t spitch, size_t width, size_t rows,
+                  hipMemcpyKind kind, hipStream_t st) {
+  if (rows == 0 || width == 0) return hipSuccess;
+  return hipMemcpy2DAsync(dst, dpitch, src, spitch, width, rows, kind, st);
+}
+
+sfft_status apply_ooc(sfft_plan_s* p, const void* xh, void* yh, int64_t nrhs, void* host_ws, void* dev_ws,
+                      const OocGeom& g, hipStream_t st) {
+  const size_t esz = p->esz;
+  const int64_t L0 = p->L[0];
+  const size_t V = (size_t)g.nv * p->s;  // entries of all nrhs vectors
+  char* child[2] = {(char*)host_ws, (char*)host_ws + V * esz};
+  char* dev = (char*)dev_ws;
+  sfft_status s;
+  // steps 1 and 3: column slabs [i0, i0 + w) of every (vector, level-1 index) row
+  auto column_pass = [&](int mode) -> sfft_status {
+    const size_t slab = (size_t)g.nv * L0 * g.w;
+    char* A = dev;
+    char* B = dev + slab * esz;
+    char* Cc = dev + 2 * slab * esz;
+    for (int64_t i0 = 0; i0 < g.inner; i0 += g.w) {
+      const int64_t ww = g.inner - i0 < g.w ? g.inner - i0 : g.w;
+      const size_t hp = (size_t)g.inner * esz, dp = (size_t)ww * esz, wid = (size_t)ww * esz;
+      const size_t rows = (size_t)g.nv * L0;
+      PassArgs a = base_args(p, 0, g.nv, L0);
+      a.inner = ww;
+      a.nq = 1;
+      a.use_phase = 1;
+      if (mode == 0) {
+        HIP_TRY(copy2d(A, dp, (const char*)xh + i0 * esz, hp, wid, rows, hipMemcpyHostToDevice, st), "x slab");
+        a.in = A;
+        a.out = B;
+        a.out1 = Cc;
+        if ((s = run_pass(p, 0, 0, a, st)) != SFFT_OK) return s;
+        HIP_TRY(copy2d(child[0] + i0 * esz, hp, B, dp, wid, rows, hipMemcpyDeviceToHost, st), "even slab");
+        HIP_TRY(copy2d(child[1] + i0 * esz, hp, Cc, dp, wid, rows, hipMemcpyDeviceToHost, st), "odd slab");
+      } else {
+        HIP_TRY(copy2d(A, dp, child[0] + i0 * esz, hp, wid, rows, hipMemcpyHostToDevice, st), "even slab");
+        HIP_TRY(copy2d(B, dp, child[1] + i0 * esz, hp, wid, rows, hipMemcpyHostToDevice, st), "odd slab");
+        a.in = A;
+        a.in1 = B;
+        a.out = Cc;
+        if ((s = run_pass(p, 0, 1, a, st)) != SFFT_OK) return s;
+        HIP_TRY(copy2d((char*)yh + i0 * esz, hp, Cc, dp, wid, rows, hipMemcpyDeviceToHost, st), "y slab");
+      }
+    }
+    return SFFT_OK;
+  };
+  if ((s = column_pass(0)) != SFFT_OK) return s;
+  // step 2: row slabs of each child through levels 2..d
+  const int64_t pen_per_row = p->npen / L0;
+  for (int c1 = 0; c1 < 2; ++c1) {
+    for (int64_t j0 = 0; j0 < L0; j0 += g.c) {
+      const int64_t cc = L0 - j0 < g.c ? L0 - j0 : g.c;
+      const size_t hp = (size_t)p->s * esz, wid = (size_t)cc * g.rowlen * esz;
+      char* S = dev;
+      char* ws = dev + (size_t)g.nv * cc * g.rowlen * esz;
+      HIP_TRY(copy2d(S, wid, child[c1] + (size_t)j0 * g.rowlen * esz, hp, wid, g.nv, hipMemcpyHostToDevice, st),
+              "child slab in");
+      const Slab sl{cc, j0 * pen_per_row, cc * pen_per_row, 1};
+      if ((s = split_depth(p, 1, S, S, c1, nrhs, ws, st, false, sl)) != SFFT_OK) return s;
+      HIP_TRY(copy2d(child[c1] + (size_t)j0 * g.rowlen * esz, hp, S, wid, wid, g.nv, hipMemcpyDeviceToHost, st),
+              "child slab out");
+    }
+  }
+  if ((s = column_pass(1)) != SFFT_OK) return s;
+  HIP_TRY(hipStreamSynchronize(st), "out-of-core apply");
+  return SFFT_OK;
 }
 
 }  // namespace
@@ -1209,6 +1345,35 @@ sfft_status sfft_apply_noalloc(sfft_plan plan, const void* x, void* y, int64_t n
   sfft_status s = apply_one(plan, x, y, nrhs, ws, need, (hipStream_t)stream, false);
   g_noalloc = false;
   return s;
+}
+
+sfft_status sfft_ooc_sizes(sfft_plan plan, int64_t nrhs, size_t device_budget, size_t* host_ws_bytes,
+                           size_t* device_ws_bytes) {
+  if (!plan || !host_ws_bytes || !device_ws_bytes) return fail(SFFT_INVALID_ARG, "null argument");
+  if (nrhs < 1) return fail(SFFT_INVALID_ARG, "nrhs must be >= 1");
+  OocGeom g;
+  sfft_status s = ooc_geometry(plan, nrhs, device_budget, &g);
+  if (s != SFFT_OK) return s;
+  *host_ws_bytes = 2 * (size_t)vec_elems(plan, nrhs) * plan->esz;
+  *device_ws_bytes = g.dev_bytes;
+  return SFFT_OK;
+}
+
+sfft_status sfft_apply_ooc(sfft_plan plan, const void* x_host, void* y_host, int64_t nrhs, void* host_ws,
+                           size_t host_ws_bytes, void* device_ws, size_t device_ws_bytes, void* stream) {
+  if (!plan) return fail(SFFT_INVALID_ARG, "plan is null");
+  if (nrhs < 0) return fail(SFFT_INVALID_ARG, "nrhs must be >= 0");
+  if (nrhs == 0) return SFFT_OK;
+  if (!x_host || !y_host || !host_ws || !device_ws) return fail(SFFT_INVALID_ARG, "null pointer");
+  OocGeom g;
+  sfft_status s = ooc_geometry(plan, nrhs, device_ws_bytes, &g);
+  if (s != SFFT_OK) return s;
+  const size_t vb = (size_t)vec_elems(plan, nrhs) * plan->esz;
+  if (host_ws_bytes < 2 * vb) return fail(SFFT_INVALID_ARG, "host workspace too small: need " + std::to_string(2 * vb));
+  if (ranges_overlap(x_host, vb, y_host, vb) || ranges_overlap(host_ws, 2 * vb, x_host, vb) ||
+      ranges_overlap(host_ws, 2 * vb, y_host, vb))
+    return fail(SFFT_INVALID_ARG, "x, y and the host workspace must not overlap");
+  return apply_ooc(plan, x_host, y_host, nrhs, host_ws, device_ws, g, (hipStream_t)stream);
 }
 
 sfft_status sfft_plan_enable_adjoint(sfft_plan plan, void* stream) {

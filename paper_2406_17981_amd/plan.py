@@ -135,6 +135,41 @@ class Plan:
 
     __call__ = apply
 
+    def ooc_sizes(self, nrhs: int, device_budget: int):
+        """(host workspace bytes, device workspace bytes) of apply_ooc for a
+        device budget (sfft_ooc_sizes)."""
+        h, d = C.c_size_t(), C.c_size_t()
+        N.check(N.lib.sfft_ooc_sizes(self.handle, int(nrhs), int(device_budget), C.byref(h), C.byref(d)),
+                "sfft_ooc_sizes")
+        return int(h.value), int(d.value)
+
+    def apply_ooc(self, x: torch.Tensor, y: Optional[torch.Tensor] = None, device_budget: int = 1 << 30,
+                  host_ws: Optional[torch.Tensor] = None, device_ws: Optional[torch.Tensor] = None,
+                  stream=None) -> torch.Tensor:
+        """y = T x with x and y in host memory (sfft_apply_ooc): the device
+        holds the plan and slabs of at most device_budget bytes. x: CPU tensor
+        (nrhs, b, *n) of the plan dtype, preferably pinned."""
+        if x.is_cuda or x.dtype != self.torch_dtype or not x.is_contiguous():
+            raise ValueError(f"x must be a contiguous host tensor of {self.torch_dtype}")
+        xs = x.unsqueeze(0) if x.dim() == self.d + 1 else x
+        if tuple(xs.shape[1:]) != (self.b,) + self.n:
+            raise ValueError(f"x shape {tuple(x.shape)} does not match b={self.b}, n={self.n}")
+        nrhs = xs.shape[0]
+        hb, db = self.ooc_sizes(nrhs, device_budget)
+        if y is None:
+            y = torch.empty(xs.shape, dtype=self.torch_dtype, pin_memory=True)
+        if y.is_cuda or y.dtype != self.torch_dtype or y.numel() != xs.numel() or not y.is_contiguous():
+            raise ValueError("y must be a contiguous host tensor of x's size and dtype")
+        if host_ws is None:
+            host_ws = torch.empty(hb, dtype=torch.uint8, pin_memory=True)
+        if device_ws is None:
+            device_ws = torch.empty(db, dtype=torch.uint8, device="cuda")
+        N.check(N.lib.sfft_apply_ooc(self.handle, C.c_void_p(xs.data_ptr()), C.c_void_p(y.data_ptr()), nrhs,
+                                     C.c_void_p(host_ws.data_ptr()), host_ws.numel(),
+                                     C.c_void_p(device_ws.data_ptr()), device_ws.numel(),
+                                     C.c_void_p(_stream_handle(stream))), "sfft_apply_ooc")
+        return y.view(x.shape)
+
     def enable_adjoint(self, stream=None) -> None:
         """Build the symbols of T^H (sfft_plan_enable_adjoint) so that
         apply(..., adjoint=True) computes y = T^H x."""
