@@ -600,6 +600,7 @@ def bench_serve(args):
         summ["gmres_residual_median"] = float(f"{float(np.median(gm)):.3e}") if gm else None
         summ.update(wall_s=round(time.perf_counter() - t0, 3), server_steps=srv.steps_run,
                     host_s_admit=round(srv.time_in["admit"], 3), host_s_step=round(srv.time_in["step"], 3),
+                    host_s_step_waiting_for_device=round(ex.wait_s, 3),
                     host_s_finish=round(srv.time_in["finish"], 3),
                     mean_batch=round(sum(srv.batch_sizes) / max(len(srv.batch_sizes), 1), 2),
                     peak_reserved_gb=round(srv.peak_reserved / 2 ** 30, 2))

@@ -39,8 +39,11 @@ tested on the host with a mock executor.
 
 from __future__ import annotations
 
+import concurrent.futures as cf
 import ctypes as C
 import math
+import queue as queue_mod
+import threading
 import time
 from dataclasses import dataclass
 from typing import Callable, List, Optional, Sequence
@@ -97,6 +100,16 @@ class Executor:
 
     def admit(self, req: Request) -> object:
         raise NotImplementedError
+
+    def admit_start(self, req: Request) -> cf.Future:
+        """Starts admitting req; the future's result is the slot handle (or
+        the admission's exception). The default admits synchronously."""
+        fut = cf.Future()
+        try:
+            fut.set_result(self.admit(req))
+        except Exception as e:  # noqa: BLE001
+            fut.set_exception(e)
+        return fut
 
     def step(self, slots: Sequence[object]) -> Optional[List[tuple]]:
         """One Arnoldi step for each slot. Returns (index into slots, message)
@@ -159,6 +172,7 @@ class Server:
         self.failed = 0
         self.cancelled = 0
         self._cancel = set()
+        self._admitting = []  # (request, future of its slot, resident, transient bytes)
 
     def cancel(self, rid: int) -> None:
         """Cancels request rid wherever it is (not yet arrived, queued, active);
@@ -180,7 +194,7 @@ class Server:
         if resident + transient > self.budget:
             req.result = dict(error=f"needs {resident + transient} bytes, more than the budget of {self.budget}")
             return REJECTED
-        if len(active) + draining >= self.max_active:
+        if len(active) + draining + len(self._admitting) >= self.max_active:
             return WAIT
         if self.reserved + resident + transient + self.ex.idle_bytes(req) > self.budget and self.ex.idle_bytes(req):
             self.ex.trim(req)
@@ -189,18 +203,32 @@ class Server:
         self.reserved += resident + transient
         self.peak_reserved = max(self.peak_reserved, self.reserved)
         t = self.clock()
-        try:
-            handle = self.ex.admit(req)
-        except Exception as e:  # noqa: BLE001  (one request's failure must not end the others)
-            self.reserved -= resident + transient
-            req.result = dict(error=f"admission failed: {type(e).__name__}: {e}")
-            return REJECTED
-        finally:
-            self.time_in["admit"] += self.clock() - t
-        self.reserved -= transient
+        fut = self.ex.admit_start(req)
+        self.time_in["admit"] += self.clock() - t
         req.admitted = now
-        active.append(_Slot(req, handle, resident))
+        self._admitting.append((req, fut, resident, transient))
         return ADMITTED
+
+    def _collect_admissions(self, active: List[_Slot], t0: float, finished: List[Request], wait: bool) -> None:
+        """Moves finished admissions to the active set (in admission order);
+        with wait, blocks for the oldest one first."""
+        if wait and self._admitting:
+            t = self.clock()
+            cf.wait([self._admitting[0][1]])
+            self.time_in["admit"] += self.clock() - t
+        keep = []
+        for req, fut, resident, transient in self._admitting:
+            if not fut.done():
+                keep.append((req, fut, resident, transient))
+                continue
+            exc = fut.exception()
+            if exc is not None:  # one request's failure must not end the others
+                self.reserved -= resident + transient
+                self._end(req, "error", dict(error=f"admission failed: {type(exc).__name__}: {exc}"), t0, finished)
+            else:
+                self.reserved -= transient
+                active.append(_Slot(req, fut.result(), resident))
+        self._admitting = keep
 
     def _retire(self, s: _Slot, status: str, result: dict, t0: float, finished: List[Request]) -> None:
         """Ends an active or draining slot that did not complete normally."""
@@ -235,7 +263,7 @@ class Server:
         finished: List[Request] = []
         t0 = self.clock()
         i = 0
-        while i < len(pending) or queue or active or draining:
+        while i < len(pending) or queue or active or draining or self._admitting:
             still = []
             for s in draining:
                 if self.ex.finish_ready(s.handle):
@@ -269,10 +297,11 @@ class Server:
                 r = queue.pop(0)
                 if outcome == REJECTED:
                     self._end(r, "error", r.result, t0, finished)
+            self._collect_admissions(active, t0, finished, wait=not active and not draining)
             if not active:
                 if draining:
                     self.ex.finish_wait(draining[0].handle)
-                elif i < len(pending):
+                elif i < len(pending) and not self._admitting:
                     self.sleep(max(0.0, pending[i].arrival - (self.clock() - t0)))
                 continue
             t = self.clock()
@@ -325,7 +354,7 @@ class GpuExecutor(Executor):
     `mirrored` (symbols stored mirrored)."""
 
     def __init__(self, coeff_fn, parity_fn=None, dtype: str = "c64", nstreams: int = 4, mirrored: bool = True,
-                 schedule: str = "depth", keep_basis: bool = False, max_ahead: int = 2):
+                 schedule: str = "depth", keep_basis: bool = False, max_ahead: int = 2, admit_workers: int = 3):
         import torch
         from . import _native as N
         from .plan import Plan
@@ -344,8 +373,8 @@ class GpuExecutor(Executor):
         self.schedule = schedule
         self.streams = [torch.cuda.Stream() for _ in range(nstreams)]
         self.main = torch.cuda.current_stream()
-        # plan creation (coefficients, FP64 symbols) runs on its own stream, so
-        # its completion wait does not drain the other requests' queued steps
+        # plan creation (coefficients, FP64 symbols) runs on streams of its own,
+        # so its completion waits do not drain the other requests' queued steps
         self.admit_stream = torch.cuda.Stream()
         self._scratch = None
         # plans of finished requests by grid, each with the event after its
@@ -355,6 +384,17 @@ class GpuExecutor(Executor):
         # server steps queued on the device beyond the one being issued
         self.max_ahead = max_ahead
         self._inflight = []
+        self.wait_s = 0.0  # host seconds spent waiting for the device to drain queued steps
+        # admissions (coefficients, plan creation or update, basis, start
+        # vector) run on worker threads, each with its own stream and Arnoldi
+        # scratch, so the server keeps issuing steps meanwhile and several
+        # admissions overlap; the idle-plan pool is shared under a lock
+        self._pool = cf.ThreadPoolExecutor(max_workers=admit_workers)
+        self._lock = threading.Lock()
+        self._lanes = queue_mod.Queue()
+        for k in range(admit_workers):
+            self._lanes.put((self.admit_stream if k == 0 else torch.cuda.Stream(), f"_adm_scratch{k}"))
+            setattr(self, f"_adm_scratch{k}", None)
 
     def bytes_needed(self, req: Request) -> tuple:
         n, d, b = req.n, len(req.n), 3
@@ -372,62 +412,95 @@ class GpuExecutor(Executor):
         return int(info["symbol_bytes"] + info["table_bytes"])
 
     def idle_bytes(self, req: Optional[Request] = None) -> int:
-        total = self._idle_total
-        if req is not None and self._idle.get(tuple(req.n)):
-            total -= self._idle[tuple(req.n)][-1][2]
-        return total
+        with self._lock:
+            total = self._idle_total
+            if req is not None and self._idle.get(tuple(req.n)):
+                total -= self._idle[tuple(req.n)][-1][2]
+            return total
 
     def trim(self, req: Optional[Request] = None) -> None:
         keep = tuple(req.n) if req is not None else None
-        for key, lst in list(self._idle.items()):
-            stay = lst[-1:] if key == keep else []
-            for plan, ev, nb in lst[:len(lst) - len(stay)]:
-                ev.synchronize()
-                plan.close()
-                self._idle_total -= nb
-            self._idle[key] = stay
+        with self._lock:
+            for key, lst in list(self._idle.items()):
+                stay = lst[-1:] if key == keep else []
+                for plan, ev, nb in lst[:len(lst) - len(stay)]:
+                    ev.synchronize()
+                    plan.close()
+                    self._idle_total -= nb
+                self._idle[key] = stay
 
     def close(self) -> None:
+        self._pool.shutdown(wait=True)
         self.trim()
 
     def admit(self, req: Request) -> dict:
+        """Synchronous admission (the work admit_start does on the worker)."""
+        slot = self._admit_job(req)
+        self.main.wait_event(slot.pop("ready"))
+        return slot
+
+    def admit_start(self, req: Request) -> cf.Future:
+        return self._pool.submit(self._admit_job, req)
+
+    def _admit_job(self, req: Request) -> dict:
+        """Admission on the admission stream: coefficients, a reused plan's
+        update (after its last use) or a new plan, the Krylov basis with the
+        start vector, and v_0 = b / ||b||. The slot's "ready" event marks the
+        end of this work; its first step waits for it on the main stream."""
+        lane = self._lanes.get()
+        try:
+            return self._admit_on(req, *lane)
+        finally:
+            self._lanes.put(lane)
+
+    def _admit_on(self, req: Request, stream, scratch: str) -> dict:
         torch = self.torch
         n, b = req.n, 3
-        reuse = self._idle.get(tuple(n))
-        with torch.cuda.stream(self.admit_stream):
+        with self._lock:
+            reuse = self._idle.get(tuple(n))
+            entry = reuse.pop() if reuse else None
+            if entry is not None:
+                self._idle_total -= entry[2]
+        with torch.cuda.stream(stream):
             coeffs = self.coeff_fn(n, req.k)
-            if reuse:
+            if entry is not None:
                 # the plan's last applies finish before its symbols change
-                plan, ev, nb = reuse.pop()
-                self._idle_total -= nb
-                self.admit_stream.wait_event(ev)
-                plan.update(coeffs, stream=self.admit_stream)
+                plan, ev, _ = entry
+                stream.wait_event(ev)
+                plan.update(coeffs, stream=stream)
             else:
                 par = self.parity_fn(len(n)) if self.mirrored else None
                 plan = self.Plan(n, b, coeffs, dtype=self.dtype, parity=par, max_nrhs=1, schedule=self.schedule,
-                                 stream=self.admit_stream)
+                                 stream=stream)
             del coeffs
-        vlen = b * math.prod(n)
-        basis = torch.empty((req.steps + 1, vlen), dtype=self.tdt, device="cuda")
-        # start vector b: complex normal, drawn on the device from the request's seed
-        g = torch.Generator(device="cuda").manual_seed(req.seed)
-        real = self.tdt.to_real()
-        basis[0].copy_(torch.complex(torch.randn(vlen, generator=g, dtype=real, device="cuda"),
-                                     torch.randn(vlen, generator=g, dtype=real, device="cuda")))
-        # Hessenberg matrix stored by columns: Hc[j] is column j (contiguous);
-        # Hc[steps][0] receives ||b||
-        Hc = torch.zeros((req.steps + 1, req.steps + 1), dtype=torch.complex128, device="cuda")
-        ws = plan.alloc_workspace(1)
-        w = torch.empty(vlen, dtype=self.tdt, device="cuda")
-        slot = dict(req=req, plan=plan, basis=basis, w=w, Hc=Hc, ws=ws, j=0, shape=(1, b) + tuple(n),
+            vlen = b * math.prod(n)
+            basis = torch.empty((req.steps + 1, vlen), dtype=self.tdt, device="cuda")
+            # start vector b: complex normal, drawn on the device from the request's seed
+            g = torch.Generator(device="cuda").manual_seed(req.seed)
+            real = self.tdt.to_real()
+            basis[0].copy_(torch.complex(torch.randn(vlen, generator=g, dtype=real, device="cuda"),
+                                         torch.randn(vlen, generator=g, dtype=real, device="cuda")))
+            # Hessenberg matrix stored by columns: Hc[j] is column j (contiguous);
+            # Hc[steps][0] receives ||b||
+            Hc = torch.zeros((req.steps + 1, req.steps + 1), dtype=torch.complex128, device="cuda")
+            ws = plan.alloc_workspace(1)
+            w = torch.empty(vlen, dtype=self.tdt, device="cuda")
+            # v_0 = b / ||b|| (an Arnoldi job with an empty basis)
+            self._arnoldi([dict(V=basis, m=0, w=basis[0], vout=basis[0], hcol=Hc[req.steps])],
+                          stream=stream, scratch=scratch)
+            ready = torch.cuda.Event()
+            ready.record(stream)
+        # the buffers are used on the main stream (and streams joined to it)
+        # from now on: freeing them must wait for that work
+        for t in (basis, Hc, ws, w):
+            if t is not None:
+                t.record_stream(self.main)
+        return dict(req=req, plan=plan, basis=basis, w=w, Hc=Hc, ws=ws, j=0, shape=(1, b) + tuple(n), ready=ready,
                     # raw pointers for the one-call step (sfft_apply_each)
                     ptr=(plan.handle.value, basis.data_ptr(), vlen * self.esz, w.data_ptr(),
                          ws.data_ptr() if ws is not None else 0, ws.numel() if ws is not None else 0))
-        # v_0 = b / ||b|| (an Arnoldi job with an empty basis)
-        self._arnoldi([dict(V=basis, m=0, w=basis[0], vout=basis[0], hcol=Hc[req.steps])])
-        return slot
 
-    def _arnoldi(self, jobs):
+    def _arnoldi(self, jobs, stream=None, scratch="_scratch"):
         N = self.N
         arr = (N.ArnoldiJob * len(jobs))()
         for a, jb in zip(arr, jobs):
@@ -440,12 +513,15 @@ class GpuExecutor(Executor):
             a.hcol = jb["hcol"].data_ptr()
         need = C.c_size_t()
         N.check(N.lib.sfft_arnoldi_scratch_size(len(jobs), arr, C.byref(need)), "sfft_arnoldi_scratch_size")
-        if self._scratch is None or self._scratch.numel() < need.value:
-            self._scratch = self.torch.empty(max(int(need.value), 1 << 20), dtype=self.torch.uint8, device="cuda")
+        stream = self.main if stream is None else stream
+        buf = getattr(self, scratch)
+        if buf is None or buf.numel() < need.value:
+            with self.torch.cuda.stream(stream):
+                buf = self.torch.empty(max(int(need.value), 1 << 20), dtype=self.torch.uint8, device="cuda")
+            setattr(self, scratch, buf)
         code = N.C64 if self.dtype == "c64" else N.C128
-        st = self.main.cuda_stream
-        N.check(N.lib.sfft_arnoldi_step_multi(len(jobs), arr, code, C.c_void_p(self._scratch.data_ptr()),
-                                              self._scratch.numel(), C.c_void_p(st)), "sfft_arnoldi_step_multi")
+        N.check(N.lib.sfft_arnoldi_step_multi(len(jobs), arr, code, C.c_void_p(buf.data_ptr()), buf.numel(),
+                                              C.c_void_p(stream.cuda_stream)), "sfft_arnoldi_step_multi")
 
     def _throttle(self) -> None:
         # at most max_ahead server steps queued behind the one being issued, so
@@ -453,8 +529,10 @@ class GpuExecutor(Executor):
         ev = self.torch.cuda.Event()
         ev.record(self.main)
         self._inflight.append(ev)
+        t = time.perf_counter()
         while len(self._inflight) > self.max_ahead:
             self._inflight.pop(0).synchronize()
+        self.wait_s += time.perf_counter() - t
 
     def step(self, slots):
         """w = T v_j for every slot in one native call (sfft_apply_each: the
@@ -466,6 +544,8 @@ class GpuExecutor(Executor):
         nr, wss, wsb = (C.c_int64 * k)(*([1] * k)), (C.c_void_p * k)(), (C.c_size_t * k)()
         status = (C.c_int * k)()
         for i, s in enumerate(slots):
+            if "ready" in s:  # first step after an asynchronous admission
+                self.main.wait_event(s.pop("ready"))
             ph, base, vb, wp, wsp, wsn = s["ptr"]
             plans[i], xs[i], ys[i], wss[i], wsb[i] = ph, base + s["j"] * vb, wp, wsp or None, wsn
         N.check(N.lib.sfft_apply_each(k, plans, xs, ys, nr, wss, wsb, C.c_void_p(self.main.cuda_stream), status),
@@ -540,8 +620,9 @@ class GpuExecutor(Executor):
             ev.record(self.main)
         plan = slot["plan"]
         nb = self._plan_bytes(plan)
-        self._idle.setdefault(tuple(slot["req"].n), []).append((plan, ev, nb))
-        self._idle_total += nb
+        with self._lock:
+            self._idle.setdefault(tuple(slot["req"].n), []).append((plan, ev, nb))
+            self._idle_total += nb
         slot.clear()
 
 
@@ -551,6 +632,8 @@ class SingleRequestExecutor(GpuExecutor):
 
     def step(self, slots):
         for s in slots:
+            if "ready" in s:
+                self.main.wait_event(s.pop("ready"))
             s["plan"].apply(s["basis"][s["j"]].view(s["shape"]), s["w"].view(s["shape"]), s["ws"], stream=self.main)
             j = s["j"]
             self._arnoldi([dict(V=s["basis"], m=j + 1, w=s["w"], vout=s["basis"][j + 1], hcol=s["Hc"][j])])
