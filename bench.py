@@ -518,8 +518,9 @@ def bench_large(args):
 def bench_batch(args):
     """Uneven-grid batch: 48x40x32, 64x64x32, 96x80x64 and 512x384, each with
     scalar (i.i.d.) and 3x3 Green blocks, 8 right-hand sides each (64 in all),
-    complex64. One step = the whole batch, issued either as one apply per
-    problem or as one sfft_apply_multi graph launch."""
+    complex64. One step = the whole batch, issued as one apply per problem, or
+    as one sfft_apply_multi graph launch in each graph form (per-problem
+    chains, grouped lanes) and as the library's timed choice between them."""
     import numpy as np
     import torch
     import workloads as wl
@@ -547,17 +548,32 @@ def bench_batch(args):
         sf.apply_multi(plans, xs, ys, workspace=wsm)
 
     res = {}
-    for name, fn in (("sequential_applies", seq), ("apply_multi_graph", multi)):
+    forms = {}
+    saved = os.environ.get("SFFT_BATCH_MODE")
+    for name, fn, form in (("sequential_applies", seq, None), ("graph_chains", multi, "chains"),
+                           ("graph_grouped", multi, "grouped"), ("apply_multi_graph", multi, "auto")):
+        if form == "auto":
+            os.environ.pop("SFFT_BATCH_MODE", None)
+        elif form is not None:
+            os.environ["SFFT_BATCH_MODE"] = form
         for _ in range(args.warmup):
             fn()
         torch.cuda.synchronize()
+        if form is not None:
+            forms[name] = sf.batch_last_form()
         t0 = time.perf_counter()
         for _ in range(args.steps):
             fn()
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / args.steps
         res[name] = dict(ms_per_batch=round(ms, 4), matvecs_per_s=round(nrhs_total * 1e3 / ms, 1))
+        if name in forms:
+            res[name]["form"] = forms[name]
         log(f"[batch {name}] {ms:.3f} ms per batch of {nrhs_total} RHS")
+    if saved is None:
+        os.environ.pop("SFFT_BATCH_MODE", None)
+    else:
+        os.environ["SFFT_BATCH_MODE"] = saved
     line = {"workload": "batch-8-problems-64rhs-c64",
             "problems": [dict(grid=list(pr["n"]), b=pr["b"], nrhs=int(pr["x"].shape[0]),
                               schedule=["auto", "breadth", "depth"][p.info()["schedule"]], tuned_us=round(t, 1))

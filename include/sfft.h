@@ -211,18 +211,29 @@ sfft_status sfft_apply_adjoint(sfft_plan plan, const void* x, void* y, int64_t n
 /* Several independent products in one call: problem i is plans[i] applied to
  * x[i] -> y[i] with nrhs[i] right-hand sides (host arrays of device
  * pointers; workspace at least sfft_workspace_size_multi bytes, problem i at
- * the 256-byte aligned offset of the preceding problems' sizes). The batch
- * is captured once into a HIP graph with every problem's chain on its own
- * forked stream (so problems run side by side) and replayed by one graph
- * launch on `stream`; the instantiated graph is cached for the same
+ * the 256-byte aligned offset of the preceding problems' sizes; no problem's
+ * y may overlap any problem's x or y). The batch is captured into a HIP graph
+ * and replayed by one graph launch on `stream`, in one of two forms with
+ * bit-identical results: per-problem chains (every problem's launches in its
+ * own schedule on its own forked stream, so problems run side by side) or
+ * grouped lanes (problems with equal level lengths form a lane on its own
+ * forked stream; step k of every member's breadth-first schedule in stage k,
+ * the entries of one kernel in one launch: 2d - 1 stages per lane). The first
+ * call with an argument set captures both, replays each on `stream` a few
+ * times (waiting for them: that call blocks the host for some milliseconds)
+ * and keeps the faster; SFFT_BATCH_MODE=chains or =grouped in the environment
+ * captures only that form. The instantiated graph is cached for the same
  * arguments and dropped when one of its plans is destroyed. SFFT_NO_GRAPH=1
- * in the environment issues the problems one after another instead. A problem
- * with nrhs[i] = 0 is skipped (its x[i], y[i] may be NULL). */
+ * issues the problems one after another instead. A problem with nrhs[i] = 0
+ * is skipped (its x[i], y[i] may be NULL). INVALID_ARG when x[i] == y[i]. */
 sfft_status sfft_workspace_size_multi(int nprob, const sfft_plan* plans, const int64_t* nrhs,
                                       size_t* bytes);
 sfft_status sfft_apply_multi(int nprob, const sfft_plan* plans, const void* const* x,
                              void* const* y, const int64_t* nrhs, void* workspace, size_t ws_bytes,
                              void* stream);
+/* Form of the graph that the last sfft_apply_multi graph launch (any thread)
+ * replayed: 0 per-problem chains, 1 grouped lanes, -1 none yet. */
+int sfft_batch_last_form(void);
 
 /* Independent products issued in one call without a graph, each with its own
  * caller workspace: problem i is plans[i] applied to x[i] -> y[i] (nrhs[i]

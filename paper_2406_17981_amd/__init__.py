@@ -9,9 +9,9 @@ only marshals torch device tensors into it.
 
 from . import _native
 from ._native import SfftError
-from .plan import Plan, apply_multi, gmres_solve, gmres_workspace_size, workspace_size_multi
+from .plan import Plan, apply_multi, batch_last_form, gmres_solve, gmres_workspace_size, workspace_size_multi
 
 supported_length = lambda L: bool(_native.lib.sfft_length_supported(int(L)))  # noqa: E731
 
-__all__ = ["Plan", "apply_multi", "workspace_size_multi", "gmres_solve", "gmres_workspace_size", "SfftError",
+__all__ = ["Plan", "apply_multi", "batch_last_form", "workspace_size_multi", "gmres_solve", "gmres_workspace_size", "SfftError",
            "supported_length"]

@@ -28,7 +28,7 @@ EXPORTS = [
     "sfft_last_error", "sfft_length_supported", "sfft_profile_enable", "sfft_profile_read",
     "sfft_plan_autotune", "sfft_arnoldi_scratch_size", "sfft_arnoldi_step_multi", "sfft_plan_update",
     "sfft_plan_enable_adjoint", "sfft_apply_adjoint", "sfft_gmres_workspace_size", "sfft_gmres_solve",
-    "sfft_apply_noalloc", "sfft_apply_each", "sfft_ooc_sizes", "sfft_apply_ooc",
+    "sfft_apply_noalloc", "sfft_apply_each", "sfft_ooc_sizes", "sfft_apply_ooc", "sfft_batch_last_form",
 ]
 KIND_FORWARD, KIND_LEAF, KIND_INVERSE, KIND_COPY = range(4)
 
@@ -93,6 +93,7 @@ def _load():
     lib.sfft_status_string.restype = C.c_char_p
     lib.sfft_last_error.argtypes = []
     lib.sfft_last_error.restype = C.c_char_p
+    lib.sfft_batch_last_form.argtypes = []
     lib.sfft_length_supported.argtypes = [i64]
     lib.sfft_profile_enable.argtypes = [vp, C.c_uint]
     lib.sfft_profile_read.argtypes = [vp, C.c_int, C.POINTER(C.c_double), P64, C.c_int]

@@ -31,7 +31,9 @@ ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 # Packed FP32 instructions are disabled on purpose; hipcc's host pass warns
 # that it does not know the feature, which is harmless.
-FLAGS = ["-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC",
+# Contraction is off: every fused multiply-add in the kernels is explicit, so
+# results do not depend on which instantiation of a kernel ran.
+FLAGS = ["-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          f"-I{os.path.join(ROOT, 'include')}"]
 
@@ -48,7 +50,19 @@ def _run(cmd):
     return p.returncode, out, time.time() - t0
 
 
-def build(jobs: int | None = None, verbose: bool = False) -> str:
+def _stale(src: str, obj: str) -> bool:
+    """True when obj is missing or older than its source, a header, or this script."""
+    if not os.path.exists(obj):
+        return True
+    deps = [src, __file__] + [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".def"))]
+    deps += [os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))]
+    t = os.path.getmtime(obj)
+    return any(os.path.getmtime(d) > t for d in deps)
+
+
+def build(jobs: int | None = None, verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every unit (incremental=True: only those older than their
+    sources or any header) and link libsfft.so."""
     os.makedirs(BUILD, exist_ok=True)
     jobs = jobs or min(8, os.cpu_count() or 1)
     units = []
@@ -63,7 +77,8 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     # biggest lengths first so the slowest compiles start early
     units.sort(key=lambda u: -int(re.search(r"(\d+)", os.path.basename(u[1])).group(1))
                if "kernels_L" in u[1] else 0)
-    cmds = [[HIPCC] + FLAGS + extra + ["-c", src, "-o", obj] for src, obj, extra in units]
+    cmds = [[HIPCC] + FLAGS + extra + ["-c", src, "-o", obj] for src, obj, extra in units
+            if not incremental or _stale(src, obj)]
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         results = list(ex.map(_run, cmds))
     failed = [(c, r) for c, r in zip(cmds, results) if r[0] != 0]
@@ -87,9 +102,10 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("-j", type=int, default=None)
     ap.add_argument("-v", action="store_true")
+    ap.add_argument("--incremental", action="store_true", help="recompile only out-of-date units")
     a = ap.parse_args()
     t0 = time.time()
-    path = build(a.j, a.v)
+    path = build(a.j, a.v, a.incremental)
     print(f"built {path} in {time.time() - t0:.1f}s")
 
 

@@ -101,10 +101,25 @@ struct PassArgs {
   // store nothing. Branch-free, so the work item needs no second round of
   // argument loads.
   uint32_t xm1, xm2, nblk;
+  // grouped launches (one launch for the same pass of several problems):
+  // this entry's workgroups start at blk_begin (a multiple of 8, so a
+  // workgroup's XCD is the same as in a launch of its own)
+  uint32_t blk_begin;
 };
 
-__device__ __forceinline__ uint32_t work_item(const PassArgs& a) {
-  return (blockIdx.x & 7u) * a.xm1 + (blockIdx.x >> 3) * a.xm2;
+__device__ __forceinline__ uint32_t work_item(const PassArgs& a, uint32_t bid) {
+  return (bid & 7u) * a.xm1 + (bid >> 3) * a.xm2;
+}
+
+// Entry of a grouped launch that holds workgroup bid (entries sorted by blk_begin).
+__device__ __forceinline__ int find_entry(const PassArgs* __restrict__ tab, int nent, uint32_t bid) {
+  int lo = 0, hi = nent - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tab[mid].blk_begin <= bid) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
 }
 
 // Fills the block order fields for a pass of `blocks` workgroups; returns the grid.
@@ -203,7 +218,7 @@ template <> struct PairOf<double2> { using type = double4; };
 // Strided axis: tile of L rows x W = NT / T pencils, lane (c, t) = (tid % W, tid / W).
 // ---------------------------------------------------------------------------
 template <typename Real, int L, int MODE, int NT>
-__global__ void __launch_bounds__(NT) k_strided(PassArgs a) {
+__device__ __forceinline__ void strided_body(const PassArgs& a, uint32_t bid) {
   using C = cx<Real>;
   using G = Geo<Real, L>;
   using Sh = typename G::Sh;
@@ -214,7 +229,7 @@ __global__ void __launch_bounds__(NT) k_strided(PassArgs a) {
   const int64_t cols = a.outer * a.inner;
   // an item past the end (grid rounded up to 8) works on tile 0 and stores
   // nothing; no early exit, which would hold back the other argument loads
-  const uint32_t wi = work_item(a);
+  const uint32_t wi = work_item(a, bid);
   const bool live = wi < a.nblk;
   const uint32_t bx = live ? wi : 0u;
   int64_t q, col, o, i;
@@ -306,6 +321,18 @@ __global__ void __launch_bounds__(NT) k_strided(PassArgs a) {
   }
 }
 
+template <typename Real, int L, int MODE, int NT>
+__global__ void __launch_bounds__(NT) k_strided(PassArgs a) {
+  strided_body<Real, L, MODE, NT>(a, blockIdx.x);
+}
+
+// The same pass for several problems in one launch (entry table in device memory).
+template <typename Real, int L, int MODE, int NT>
+__global__ void __launch_bounds__(NT) k_strided_group(const PassArgs* __restrict__ tab, int nent) {
+  const int e = find_entry(tab, nent, blockIdx.x);
+  strided_body<Real, L, MODE, NT>(tab[e], blockIdx.x - tab[e].blk_begin);
+}
+
 // ---------------------------------------------------------------------------
 // Contiguous axis helpers: a tile of P whole pencils staged through LDS.
 // ---------------------------------------------------------------------------
@@ -348,7 +375,7 @@ __global__ void __launch_bounds__(256) k_contig(PassArgs a) {
   __shared__ C lds[P * LP];
   const int tid = threadIdx.x;
   const int g = tid / T, t = tid % T;
-  const uint32_t wi = work_item(a);
+  const uint32_t wi = work_item(a, blockIdx.x);
   const bool live = wi < a.nblk;  // past the end: tile 0, nothing loaded or stored
   const uint32_t bx = live ? wi : 0u;
   int64_t q, p0;
@@ -432,7 +459,7 @@ __global__ void __launch_bounds__(256) k_contig(PassArgs a) {
 // right-hand-side groups run on the same XCD and share its L2.
 // ---------------------------------------------------------------------------
 template <typename Real, int L, int B, int NPAR, bool MIR, int BS>
-__global__ void __launch_bounds__((Geo<Real, L>::RBMAX * Geo<Real, L>::SL)) k_leaf(PassArgs a) {
+__device__ __forceinline__ void leaf_body(const PassArgs& a, uint32_t bid) {
   using C = cx<Real>;
   using G = Geo<Real, L>;
   using Sh = typename G::LSh;
@@ -449,10 +476,10 @@ __global__ void __launch_bounds__((Geo<Real, L>::RBMAX * Geo<Real, L>::SL)) k_le
   const int rl = gr % RB;
   const int g = gr / RB;
   const int row = g * RB + rl;
-  const int64_t lo = blockIdx.x & 7;
+  const int64_t lo = bid & 7;
   int64_t rg, tile, q;
   if (a.idx32) {
-    const uint32_t t2 = blockIdx.x >> 3;
+    const uint32_t t2 = bid >> 3;
     const uint32_t t3 = a.fd_a.div(t2);
     rg = t2 - t3 * a.fd_a.d;
     const uint32_t t4 = a.fd_b.div(t3);
@@ -461,7 +488,7 @@ __global__ void __launch_bounds__((Geo<Real, L>::RBMAX * Geo<Real, L>::SL)) k_le
   } else {
     const int64_t nrg = (a.nrhs + RB - 1) / RB;
     const int64_t ntiles8 = (a.ntiles + 7) / 8;
-    const int64_t t2 = blockIdx.x >> 3;
+    const int64_t t2 = bid >> 3;
     rg = t2 % nrg;
     const int64_t t3 = t2 / nrg;
     tile = (t3 % ntiles8) * 8 + lo;
@@ -704,10 +731,30 @@ __global__ void __launch_bounds__((Geo<Real, L>::RBMAX * Geo<Real, L>::SL)) k_le
   }
 }
 
+template <typename Real, int L, int B, int NPAR, bool MIR, int BS>
+__global__ void __launch_bounds__((Geo<Real, L>::RBMAX * Geo<Real, L>::SL)) k_leaf(PassArgs a) {
+  leaf_body<Real, L, B, NPAR, MIR, BS>(a, blockIdx.x);
+}
+
+template <typename Real, int L, int B, int NPAR, bool MIR, int BS>
+__global__ void __launch_bounds__((Geo<Real, L>::RBMAX * Geo<Real, L>::SL))
+    k_leaf_group(const PassArgs* __restrict__ tab, int nent) {
+  const int e = find_entry(tab, nent, blockIdx.x);
+  leaf_body<Real, L, B, NPAR, MIR, BS>(tab[e], blockIdx.x - tab[e].blk_begin);
+}
+
 // ---------------------------------------------------------------------------
 // Host-side launch table for one length.
 // ---------------------------------------------------------------------------
 typedef hipError_t (*pass_fn)(const PassArgs&, hipStream_t);
+// Grouped launches: prep fills an entry's launch fields (index decoding,
+// block order, leaf right-hand-side grouping) and returns its workgroups,
+// rounded up to a multiple of 8 (or -1 beyond the 1-D grid); group launches
+// the kernel over a table of prepared entries in device memory.
+typedef int64_t (*prep_fn)(PassArgs&);
+typedef hipError_t (*group_fn)(const PassArgs*, int nent, int64_t blocks, hipStream_t);
+typedef int64_t (*leaf_prep_fn)(PassArgs&, size_t* smem);
+typedef hipError_t (*leaf_group_fn)(const PassArgs*, int nent, int64_t blocks, int rb, size_t smem, hipStream_t);
 
 struct AxisOps {
   int L, T, E, W, P;   // strided / contiguous passes
@@ -724,6 +771,17 @@ struct AxisOps {
   LeafRow leaf[5];    // [B]: general symbol storage, null where not built
   MirRow leaf_mirror[5];  // [B]: NPAR = 2, mirrored symbol storage
   int generic;        // 1: runtime-length kernels (pencil tiles staged whole in LDS)
+  // grouped launches (null for the runtime-length kernels): strided passes
+  // with full-size [0] or half-size [1] workgroups (half null where the tile
+  // would be narrower than a 128-byte line), and the split leaf (NPAR = 2)
+  prep_fn strided_prep[2];
+  group_fn strided_group[2][2];  // [MODE][half]
+  struct LeafGroupRow {
+    leaf_prep_fn prep[3];  // [block symmetry]
+    leaf_group_fn group[3];
+  };
+  LeafGroupRow leaf_group[5];         // [B], general symbols
+  LeafGroupRow leaf_group_mirror[5];  // [B], mirrored symbols
 };
 
 constexpr int64_t kIdx32 = (int64_t)1 << 31;
@@ -733,18 +791,17 @@ constexpr size_t kMaxLds = 160 * 1024;  // LDS of one gfx950 workgroup
 // keep dispatch order (their start latency counts), except narrow tiles
 constexpr int64_t kXcdOrderFrom = 8192;
 
-template <typename Real, int L, int MODE, int NT> hipError_t launch_strided_nt(const PassArgs& a, hipStream_t s) {
+template <typename Real, int L, int NT> int64_t prep_strided_nt(PassArgs& b) {
   constexpr int W = NT / Geo<Real, L>::T;
-  const int64_t cols = a.outer * a.inner;
+  const int64_t cols = b.outer * b.inner;
   const int64_t ntile = (cols + W - 1) / W;
-  const int64_t blocks = a.nq * ntile;
-  if (blocks <= 0) return hipSuccess;
-  if (blocks >= kIdx32) return hipErrorInvalidConfiguration;  // beyond the 1-D grid
-  PassArgs b = a;
+  const int64_t blocks = b.nq * ntile;
+  if (blocks <= 0) return 0;
+  if (blocks >= kIdx32) return -1;  // beyond the 1-D grid
   b.idx32 = blocks < kIdx32 && ntile * W < kIdx32;
   if (b.idx32) {
     b.fd_a = FastDiv::make((uint32_t)ntile);
-    b.fd_b = FastDiv::make((uint32_t)a.inner);
+    b.fd_b = FastDiv::make((uint32_t)b.inner);
   }
   // tiles narrower than a 128-byte line share lines with their neighbours:
   // in dispatch order those neighbours run on different XCDs and each XCD
@@ -752,7 +809,23 @@ template <typename Real, int L, int MODE, int NT> hipError_t launch_strided_nt(c
   // XCD-contiguous order they share one L2 (-20% on a 1024^2 grid)
   constexpr bool narrow = W * (int)sizeof(cx<Real>) < 128;
   const int64_t grid = set_block_order(b, blocks, blocks >= kXcdOrderFrom || (narrow && blocks >= 16));
+  return (grid + 7) / 8 * 8;  // items past nblk store nothing
+}
+
+template <typename Real, int L, int MODE, int NT> hipError_t launch_strided_nt(const PassArgs& a, hipStream_t s) {
+  PassArgs b = a;
+  const int64_t grid = prep_strided_nt<Real, L, NT>(b);
+  if (grid == 0) return hipSuccess;
+  if (grid < 0) return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL((k_strided<Real, L, MODE, NT>), dim3((unsigned)grid), dim3(NT), 0, s, b);
+  return hipGetLastError();
+}
+
+template <typename Real, int L, int MODE, int NT>
+hipError_t group_strided_nt(const PassArgs* tab, int nent, int64_t blocks, hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  if (blocks >= kIdx32) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL((k_strided_group<Real, L, MODE, NT>), dim3((unsigned)blocks), dim3(NT), 0, s, tab, nent);
   return hipGetLastError();
 }
 
@@ -761,10 +834,14 @@ template <typename Real, int L, int MODE, int NT> hipError_t launch_strided_nt(c
 // of the CUs with twice the work of the others, 768 of two spread evenly.
 constexpr int64_t kHalfTilesBelow = 2048;
 
+template <typename Real, int L> constexpr bool half_tiles_ok() {
+  using G = Geo<Real, L>;
+  return (G::W / 2) * (int)sizeof(cx<Real>) >= 128;
+}
+
 template <typename Real, int L, int MODE> hipError_t launch_strided(const PassArgs& a, hipStream_t s) {
   using G = Geo<Real, L>;
-  constexpr bool half_ok = (G::W / 2) * (int)sizeof(cx<Real>) >= 128;
-  if constexpr (half_ok) {
+  if constexpr (half_tiles_ok<Real, L>()) {
     const int64_t cols = a.outer * a.inner;
     const int64_t blocks = a.nq * ((cols + G::W - 1) / G::W);
     if (blocks < kHalfTilesBelow) return launch_strided_nt<Real, L, MODE, G::NT / 2>(a, s);
@@ -786,27 +863,66 @@ template <typename Real, int L, int MODE> hipError_t launch_contig(const PassArg
   return hipGetLastError();
 }
 
-template <typename Real, int L, int B, int NPAR, bool MIR = false, int BS = 0>
-hipError_t launch_leaf(const PassArgs& a, hipStream_t s) {
+// Right-hand sides per leaf workgroup (clamped to the kernel's limit and to
+// 64 KB of LDS), decoding fields, workgroups and LDS bytes.
+template <typename Real, int L, int B, int NPAR, bool MIR, int BS> int64_t prep_leaf(PassArgs& b, size_t* smem) {
   using G = Geo<Real, L>;
   constexpr size_t row_bytes = (size_t)G::PL * G::LLP * sizeof(cx<Real>) * G::template leaf_rows<B, NPAR>();
   constexpr int rb_lds = (int)((64 * 1024) / row_bytes) > 0 ? (int)((64 * 1024) / row_bytes) : 1;
-  int rb = a.rb < 1 ? 1 : (a.rb > G::RBMAX ? G::RBMAX : a.rb);
+  int rb = b.rb < 1 ? 1 : (b.rb > G::RBMAX ? G::RBMAX : b.rb);
   while (rb > rb_lds) rb /= 2;
-  PassArgs b = a;
   b.rb = rb;
-  const int64_t nrg = (a.nrhs + rb - 1) / rb;
-  const int64_t blocks = a.nq * ((a.ntiles + 7) / 8) * nrg * 8;
-  if (blocks <= 0) return hipSuccess;
+  const int64_t nrg = (b.nrhs + rb - 1) / rb;
+  const int64_t blocks = b.nq * ((b.ntiles + 7) / 8) * nrg * 8;
+  if (blocks <= 0) return 0;
   b.idx32 = blocks < kIdx32;
   if (b.idx32) {
     b.fd_a = FastDiv::make((uint32_t)nrg);
-    b.fd_b = FastDiv::make((uint32_t)((a.ntiles + 7) / 8));
+    b.fd_b = FastDiv::make((uint32_t)((b.ntiles + 7) / 8));
   }
-  const size_t smem = (size_t)rb * row_bytes;
-  if (smem > kMaxLds) return hipErrorInvalidConfiguration;  // beyond a workgroup's LDS
-  hipLaunchKernelGGL((k_leaf<Real, L, B, NPAR, MIR, BS>), dim3((unsigned)blocks), dim3(rb * G::SL), smem, s, b);
+  *smem = (size_t)rb * row_bytes;
+  if (*smem > kMaxLds || blocks >= kIdx32) return -1;  // beyond a workgroup's LDS or the grid
+  return blocks;
+}
+
+template <typename Real, int L, int B, int NPAR, bool MIR = false, int BS = 0>
+hipError_t launch_leaf(const PassArgs& a, hipStream_t s) {
+  using G = Geo<Real, L>;
+  PassArgs b = a;
+  size_t smem = 0;
+  const int64_t blocks = prep_leaf<Real, L, B, NPAR, MIR, BS>(b, &smem);
+  if (blocks == 0) return hipSuccess;
+  if (blocks < 0) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL((k_leaf<Real, L, B, NPAR, MIR, BS>), dim3((unsigned)blocks), dim3(b.rb * G::SL), smem, s, b);
   return hipGetLastError();
+}
+
+template <typename Real, int L, int B, int NPAR, bool MIR, int BS>
+hipError_t group_leaf(const PassArgs* tab, int nent, int64_t blocks, int rb, size_t smem, hipStream_t s) {
+  using G = Geo<Real, L>;
+  if (blocks <= 0) return hipSuccess;
+  if (blocks >= kIdx32 || smem > kMaxLds) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL((k_leaf_group<Real, L, B, NPAR, MIR, BS>), dim3((unsigned)blocks), dim3(rb * G::SL), smem, s,
+                     tab, nent);
+  return hipGetLastError();
+}
+
+template <typename Real, int L, int B, bool MIR> AxisOps::LeafGroupRow leaf_group_row() {
+  AxisOps::LeafGroupRow r{};
+  if constexpr (B == 1) {  // a scalar block has no block symmetry to exploit
+    for (int bs = 0; bs < 3; ++bs) {
+      r.prep[bs] = prep_leaf<Real, L, 1, 2, MIR, 0>;
+      r.group[bs] = group_leaf<Real, L, 1, 2, MIR, 0>;
+    }
+  } else {
+    r.prep[0] = prep_leaf<Real, L, B, 2, MIR, 0>;
+    r.prep[1] = prep_leaf<Real, L, B, 2, MIR, 1>;
+    r.prep[2] = prep_leaf<Real, L, B, 2, MIR, 2>;
+    r.group[0] = group_leaf<Real, L, B, 2, MIR, 0>;
+    r.group[1] = group_leaf<Real, L, B, 2, MIR, 1>;
+    r.group[2] = group_leaf<Real, L, B, 2, MIR, 2>;
+  }
+  return r;
 }
 
 template <typename Real, int L, int B> constexpr AxisOps::LeafRow leaf_row_general() {
@@ -850,6 +966,15 @@ template <typename Real, int L> const AxisOps* make_ops() {
       {{}, leaf_row_mirror<Real, L, 1>(), leaf_row_mirror<Real, L, 2>(), leaf_row_mirror<Real, L, 3>(),
        leaf_row_mirror<Real, L, 4>()},
       0,
+      {prep_strided_nt<Real, L, G::NT>, half_tiles_ok<Real, L>() ? prep_strided_nt<Real, L, G::NT / 2> : nullptr},
+      {{group_strided_nt<Real, L, 0, G::NT>,
+        half_tiles_ok<Real, L>() ? group_strided_nt<Real, L, 0, G::NT / 2> : nullptr},
+       {group_strided_nt<Real, L, 1, G::NT>,
+        half_tiles_ok<Real, L>() ? group_strided_nt<Real, L, 1, G::NT / 2> : nullptr}},
+      {{}, leaf_group_row<Real, L, 1, false>(), leaf_group_row<Real, L, 2, false>(),
+       leaf_group_row<Real, L, 3, false>(), leaf_group_row<Real, L, 4, false>()},
+      {{}, leaf_group_row<Real, L, 1, true>(), leaf_group_row<Real, L, 2, true>(),
+       leaf_group_row<Real, L, 3, true>(), leaf_group_row<Real, L, 4, true>()},
   };
   return &ops;
 }

@@ -32,17 +32,27 @@ template <typename C> __device__ __forceinline__ C mk(decltype(C::x) a, decltype
 }
 template <typename C> __device__ __forceinline__ C cadd(C a, C b) { return mk<C>(a.x + b.x, a.y + b.y); }
 template <typename C> __device__ __forceinline__ C csub(C a, C b) { return mk<C>(a.x - b.x, a.y - b.y); }
-template <typename C> __device__ __forceinline__ C cmul(C a, C b) {
-  return mk<C>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-// a * conj(b)
-template <typename C> __device__ __forceinline__ C cmulc(C a, C b) {
-  return mk<C>(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
-}
-template <typename C> __device__ __forceinline__ C cscale(C a, decltype(C::x) s) { return mk<C>(a.x * s, a.y * s); }
+// The library is compiled without implicit contraction (-ffp-contract=off):
+// every fused multiply-add is written out below, so a result's rounding is
+// fixed by the source and never by how the compiler schedules one kernel
+// instantiation against another (single and grouped launches, tile widths
+// and schedules give bit-identical results).
 // fused multiply-add, one rounding
 __device__ __forceinline__ float fmar(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmar(double a, double b, double c) { return __builtin_fma(a, b, c); }
+// a * b: one product rounded, the other fused
+template <typename C> __device__ __forceinline__ C cmul(C a, C b) {
+  return mk<C>(fmar(a.x, b.x, -(a.y * b.y)), fmar(a.x, b.y, a.y * b.x));
+}
+// a * conj(b)
+template <typename C> __device__ __forceinline__ C cmulc(C a, C b) {
+  return mk<C>(fmar(a.x, b.x, a.y * b.y), fmar(a.y, b.x, -(a.x * b.y)));
+}
+template <typename C> __device__ __forceinline__ C cscale(C a, decltype(C::x) s) { return mk<C>(a.x * s, a.y * s); }
+// u + a * s for a real s
+template <typename C> __device__ __forceinline__ C cfmas(C a, decltype(C::x) s, C u) {
+  return mk<C>(fmar(a.x, s, u.x), fmar(a.y, s, u.y));
+}
 // u + a * b, u - a * b and u + a * conj(b) as four fused multiply-adds each
 template <typename C> __device__ __forceinline__ C cfma(C a, C b, C u) {
   return mk<C>(fmar(-a.y, b.y, fmar(a.x, b.x, u.x)), fmar(a.y, b.x, fmar(a.x, b.y, u.y)));
@@ -86,11 +96,11 @@ template <int DIR, typename C> __device__ __forceinline__ void dft3(C* v) {
   C a = v[0];
   C sb = cadd(v[1], v[2]);
   C db = csub(v[1], v[2]);
-  C m = cadd(a, cscale(sb, c3));
-  C r = mul_di<DIR>(cscale(db, s3));
+  C m = cfmas(sb, c3, a);
+  C r = mul_di<DIR>(db);
   v[0] = cadd(a, sb);
-  v[1] = cadd(m, r);
-  v[2] = csub(m, r);
+  v[1] = cfmas(r, s3, m);
+  v[2] = cfmas(r, -s3, m);
 }
 
 template <int DIR, typename C> __device__ __forceinline__ void dft4(C* v) {
@@ -113,10 +123,10 @@ template <int DIR, typename C> __device__ __forceinline__ void dft5(C* v) {
   C a0 = v[0];
   C p1 = cadd(v[1], v[4]), m1 = csub(v[1], v[4]);
   C p2 = cadd(v[2], v[3]), m2 = csub(v[2], v[3]);
-  C e1 = cadd(a0, cadd(cscale(p1, c1), cscale(p2, c2)));
-  C e2 = cadd(a0, cadd(cscale(p1, c2), cscale(p2, c1)));
-  C o1 = mul_di<DIR>(cadd(cscale(m1, s1), cscale(m2, s2)));
-  C o2 = mul_di<DIR>(csub(cscale(m1, s2), cscale(m2, s1)));
+  C e1 = cfmas(p1, c1, cfmas(p2, c2, a0));
+  C e2 = cfmas(p1, c2, cfmas(p2, c1, a0));
+  C o1 = mul_di<DIR>(cfmas(m1, s1, cscale(m2, s2)));
+  C o2 = mul_di<DIR>(cfmas(m1, s2, cscale(m2, -s1)));
   v[0] = cadd(a0, cadd(p1, p2));
   v[1] = cadd(e1, o1);
   v[4] = csub(e1, o1);
@@ -140,12 +150,12 @@ template <int DIR, typename C> __device__ __forceinline__ void dft7(C* v) {
   const C p2 = cadd(v[2], v[5]), m2 = csub(v[2], v[5]);
   const C p3 = cadd(v[3], v[4]), m3 = csub(v[3], v[4]);
   // cos(2 pi jk/7) and sin(2 pi jk/7) for jk mod 7 = 4, 5, 6 are c3, c2, c1 and -s3, -s2, -s1
-  const C e1 = cadd(a0, cadd(cscale(p1, c1), cadd(cscale(p2, c2), cscale(p3, c3))));
-  const C e2 = cadd(a0, cadd(cscale(p1, c2), cadd(cscale(p2, c3), cscale(p3, c1))));
-  const C e3 = cadd(a0, cadd(cscale(p1, c3), cadd(cscale(p2, c1), cscale(p3, c2))));
-  const C o1 = mul_di<DIR>(cadd(cscale(m1, s1), cadd(cscale(m2, s2), cscale(m3, s3))));
-  const C o2 = mul_di<DIR>(csub(cscale(m1, s2), cadd(cscale(m2, s3), cscale(m3, s1))));
-  const C o3 = mul_di<DIR>(cadd(csub(cscale(m1, s3), cscale(m2, s1)), cscale(m3, s2)));
+  const C e1 = cfmas(p1, c1, cfmas(p2, c2, cfmas(p3, c3, a0)));
+  const C e2 = cfmas(p1, c2, cfmas(p2, c3, cfmas(p3, c1, a0)));
+  const C e3 = cfmas(p1, c3, cfmas(p2, c1, cfmas(p3, c2, a0)));
+  const C o1 = mul_di<DIR>(cfmas(m1, s1, cfmas(m2, s2, cscale(m3, s3))));
+  const C o2 = mul_di<DIR>(cfmas(m1, s2, cfmas(m2, -s3, cscale(m3, -s1))));
+  const C o3 = mul_di<DIR>(cfmas(m1, s3, cfmas(m2, -s1, cscale(m3, s2))));
   v[0] = cadd(a0, cadd(p1, cadd(p2, p3)));
   v[1] = cadd(e1, o1);
   v[6] = csub(e1, o1);
@@ -155,22 +165,31 @@ template <int DIR, typename C> __device__ __forceinline__ void dft7(C* v) {
   v[4] = csub(e3, o3);
 }
 
-template <int DIR, typename C> __device__ __forceinline__ void dft8(C* v) {
+// Second layer of a radix-8 DFT from the DFT4s e (even entries) and o (odd
+// entries): o[k] *= W8^k with W8 = exp(DIR 2 pi i / 8); the sqrt(1/2) of
+// k = 1, 3 is fused into the output butterflies.
+template <int DIR, typename C> __device__ __forceinline__ void dft8_tail(C* v, const C* e, const C* o) {
   using R = decltype(C::x);
   const R h = (R)0.70710678118654752440084436210485;  // sqrt(1/2)
+  const C t1 = cadd(o[1], mul_di<DIR>(o[1]));
+  const C t2 = mul_di<DIR>(o[2]);
+  const C t3 = csub(mul_di<DIR>(o[3]), o[3]);
+  v[0] = cadd(e[0], o[0]);
+  v[4] = csub(e[0], o[0]);
+  v[1] = cfmas(t1, h, e[1]);
+  v[5] = cfmas(t1, -h, e[1]);
+  v[2] = cadd(e[2], t2);
+  v[6] = csub(e[2], t2);
+  v[3] = cfmas(t3, h, e[3]);
+  v[7] = cfmas(t3, -h, e[3]);
+}
+
+template <int DIR, typename C> __device__ __forceinline__ void dft8(C* v) {
   C e[4] = {v[0], v[2], v[4], v[6]};
   C o[4] = {v[1], v[3], v[5], v[7]};
   dft4<DIR>(e);
   dft4<DIR>(o);
-  // o[k] *= W8^k, W8 = exp(DIR 2 pi i / 8)
-  o[1] = cscale(cadd(o[1], mul_di<DIR>(o[1])), h);
-  o[2] = mul_di<DIR>(o[2]);
-  o[3] = cscale(csub(mul_di<DIR>(o[3]), o[3]), h);
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    v[k] = cadd(e[k], o[k]);
-    v[k + 4] = csub(e[k], o[k]);
-  }
+  dft8_tail<DIR>(v, e, o);
 }
 
 template <int DIR, typename C> __device__ __forceinline__ void dft16(C* v) {
@@ -247,18 +266,10 @@ template <int R, int DIR, typename C> __device__ __forceinline__ void tw_dft(C* 
     dft4_tail<DIR>(v, y0[0], y1[0], y0[1], y1[1]);
   } else if constexpr (R == 8) {
     // as dft8: e = DFT4 of the even entries, o = DFT4 of the odd ones
-    const Rl h = (Rl)0.70710678118654752440084436210485;  // sqrt(1/2)
     C e[4], o[4];
     dft4_tail<DIR>(e, y0[0], y1[0], y0[2], y1[2]);
     dft4_tail<DIR>(o, y0[1], y1[1], y0[3], y1[3]);
-    o[1] = cscale(cadd(o[1], mul_di<DIR>(o[1])), h);
-    o[2] = mul_di<DIR>(o[2]);
-    o[3] = cscale(csub(mul_di<DIR>(o[3]), o[3]), h);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      v[k] = cadd(e[k], o[k]);
-      v[k + 4] = csub(e[k], o[k]);
-    }
+    dft8_tail<DIR>(v, e, o);
   } else {
     static_assert(R == 16, "twiddled butterfly for radix 2, 4, 8, 16");
     // as dft16: n = 4 n1 + n2; the DFT4 over n1 of group n2 pairs entries

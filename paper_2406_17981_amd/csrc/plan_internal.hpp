@@ -94,6 +94,20 @@ size_t sfft_rt_workspace_elems(const sfft_plan_s* p, int64_t nrhs);
 sfft_status sfft_rt_apply_one(sfft_plan_s* p, const void* x, void* y, int64_t nrhs, void* ws, size_t ws_bytes,
                               hipStream_t st, bool adj = false);
 int sfft_rt_leaf_rbmax(const sfft_plan_s* p);
+// The kernels a leaf launch can use: one launch of its own, and the grouped
+// launch's prep and launch functions (null where the length has none).
+struct LeafSel {
+  sfft::pass_fn single = nullptr;
+  sfft::leaf_prep_fn prep = nullptr;
+  sfft::leaf_group_fn group = nullptr;
+};
+// Arguments of level l's pass over nv vectors (whole vectors, one branch).
+sfft::PassArgs sfft_rt_pass_args(const sfft_plan_s* p, int l, int64_t nv);
+// Leaf arguments over branches 0 .. nq-1 (whole vectors).
+sfft_status sfft_rt_leaf_args(const sfft_plan_s* p, const void* in, void* out, int64_t in_bs, int64_t nq,
+                              int64_t nrhs, sfft::PassArgs* a, LeafSel* sel);
+// Workspace entries of the breadth-first schedule (what grouped batches use).
+size_t sfft_rt_breadth_workspace_elems(const sfft_plan_s* p, int64_t nrhs);
 // drops cached graphs that reference the plan (called before it is freed)
 void sfft_rt_forget_plan(const sfft_plan_s* p);
 

@@ -518,11 +518,15 @@ sfft_status run_pass(const sfft_plan_s* p, int l, int mode, const PassArgs& a, h
 
 // Leaf pass over branches q0 .. q0+nq-1 of levels 1..d-1 (q0 only matters
 // for the symbols: its bits are the branch's parities).
-sfft_status run_leaf(const sfft_plan_s* p, const void* in, void* out, int64_t in_bs, int64_t nq, int64_t q0,
-                     int64_t nrhs, hipStream_t st, bool adj, const Slab& sl) {
+// Leaf launch arguments over branches q0 .. q0+nq-1 of levels 1..d-1 (q0 only
+// matters for the symbols: its bits are the branch's parities) and the
+// kernels that take them (a single launch, and the grouped launch's prep and
+// launch functions where the length has them).
+sfft_status leaf_args(const sfft_plan_s* p, const void* in, void* out, int64_t in_bs, int64_t nq, int64_t q0,
+                      int64_t nrhs, bool adj, const Slab& sl, PassArgs* ap, LeafSel* sel) {
   const int l = p->d - 1;
   const AxisOps* o = p->ops[l];
-  PassArgs a;
+  PassArgs& a = *ap;
   std::memset(&a, 0, sizeof(a));
   a.in = in;
   a.out = out;
@@ -545,8 +549,8 @@ sfft_status run_leaf(const sfft_plan_s* p, const void* in, void* out, int64_t in
     while (rb < nrhs && rb < o->RBMAX) rb *= 2;
   }
   a.rb = rb;
-  sfft::pass_fn f;
   const void* sym = adj ? p->sym_adj : p->sym;
+  *sel = LeafSel{};
   if (p->compressed) {
     a.sym = sym;
     a.sym_bs = 0;
@@ -558,15 +562,30 @@ sfft_status run_leaf(const sfft_plan_s* p, const void* in, void* out, int64_t in
     }
     a.mcomp = p->mcomp;
     for (int k = 0; k < p->ns; ++k) a.odd[k] = adj ? p->odd_adj[k] : p->odd[k];
-    f = o->leaf_mirror[p->b].f[p->bsym];
+    sel->single = o->leaf_mirror[p->b].f[p->bsym];
+    sel->prep = o->leaf_group_mirror[p->b].prep[p->bsym];
+    sel->group = o->leaf_group_mirror[p->b].group[p->bsym];
   } else {
     a.sym = (const char*)sym + (size_t)(q0 * p->sym_bs) * p->esz;
     a.sym_bs = p->sym_bs;
-    f = o->leaf[p->b].f[p->method == SFFT_SPLIT ? 2 : 1][p->bsym];
+    sel->single = o->leaf[p->b].f[p->method == SFFT_SPLIT ? 2 : 1][p->bsym];
+    if (p->method == SFFT_SPLIT) {
+      sel->prep = o->leaf_group[p->b].prep[p->bsym];
+      sel->group = o->leaf_group[p->b].group[p->bsym];
+    }
   }
-  if (!f) return fail(SFFT_UNSUPPORTED, "no leaf kernel for this block size");
+  if (!sel->single) return fail(SFFT_UNSUPPORTED, "no leaf kernel for this block size");
+  return SFFT_OK;
+}
+
+sfft_status run_leaf(const sfft_plan_s* p, const void* in, void* out, int64_t in_bs, int64_t nq, int64_t q0,
+                     int64_t nrhs, hipStream_t st, bool adj, const Slab& sl) {
+  PassArgs a;
+  LeafSel sel;
+  sfft_status s = leaf_args(p, in, out, in_bs, nq, q0, nrhs, adj, sl, &a, &sel);
+  if (s != SFFT_OK) return s;
   ProfScope ps(p, SFFT_KIND_LEAF, st);
-  hipError_t e = f(a, st);
+  hipError_t e = sel.single(a, st);
   if (e != hipSuccess) return hip_fail(e, "leaf launch");
   return SFFT_OK;
 }
@@ -1125,6 +1144,17 @@ sfft_status sfft_rt_apply_one(sfft_plan_s* p, const void* x, void* y, int64_t nr
   return apply_one(p, x, y, nrhs, ws, ws_bytes, st, adj);
 }
 int sfft_rt_leaf_rbmax(const sfft_plan_s* p) { return p->ops[p->d - 1]->RBMAX; }
+PassArgs sfft_rt_pass_args(const sfft_plan_s* p, int l, int64_t nv) { return base_args(p, l, nv, p->L[0]); }
+sfft_status sfft_rt_leaf_args(const sfft_plan_s* p, const void* in, void* out, int64_t in_bs, int64_t nq,
+                              int64_t nrhs, PassArgs* a, LeafSel* sel) {
+  return leaf_args(p, in, out, in_bs, nq, 0, nrhs, false, whole(p), a, sel);
+}
+size_t sfft_rt_breadth_workspace_elems(const sfft_plan_s* p, int64_t nrhs) {
+  const int64_t V = vec_elems(p, nrhs);
+  if (p->method == SFFT_EMBED) return (size_t)((int64_t(1) << p->d) * V);
+  if (p->d == 1) return 0;
+  return (size_t)(((int64_t(1) << p->d) - 2) * V);
+}
 
 // ---------------------------------------------------------------------------
 // C ABI
@@ -1399,7 +1429,7 @@ sfft_status sfft_workspace_size_multi(int nprob, const sfft_plan* plans, const i
   size_t total = 0;
   for (int i = 0; i < nprob; ++i) {
     if (!plans[i] || nrhs[i] < 0) return fail(SFFT_INVALID_ARG, "bad problem entry");
-    if (nrhs[i] > 0) total += sfft_rt_align256(workspace_elems(plans[i], nrhs[i]) * plans[i]->esz);
+    if (nrhs[i] > 0) total += sfft_rt_align256(sfft_rt_breadth_workspace_elems(plans[i], nrhs[i]) * plans[i]->esz);
   }
   *bytes = total;
   return SFFT_OK;

@@ -265,6 +265,11 @@ def apply_multi(plans: Sequence[Plan], xs: Sequence[torch.Tensor], ys: Sequence[
     return ys
 
 
+def batch_last_form() -> Optional[str]:
+    """Graph form the last apply_multi replayed: "chains", "grouped" or None."""
+    return {0: "chains", 1: "grouped"}.get(int(N.lib.sfft_batch_last_form()))
+
+
 def gmres_workspace_size(lo: Plan, hi: Plan, m: int) -> int:
     out = C.c_size_t()
     N.check(N.lib.sfft_gmres_workspace_size(lo.handle, hi.handle, int(m), C.byref(out)),

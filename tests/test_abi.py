@@ -41,6 +41,7 @@ def test_host_only_calls():
         assert N.lib.sfft_length_supported(L) == 0, L
     for L in (16, 40, 48, 64, 80, 96, 128, 160, 192, 256, 384, 512, 768, 1024, 2048):
         assert N.lib.sfft_length_supported(L) == 1, L
+    assert N.lib.sfft_batch_last_form() == -1  # no batch graph replayed in this process
 
 
 def test_argument_validation_without_a_device():

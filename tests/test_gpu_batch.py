@@ -50,7 +50,12 @@ def _plans(sf, probs):
     return plans, xs, ys
 
 
-def test_apply_multi_graph_matches_single_applies_and_oracle(sf):
+@pytest.mark.parametrize("form", ["auto", "chains", "grouped"])
+def test_apply_multi_graph_matches_single_applies_and_oracle(sf, monkeypatch, form):
+    if form == "auto":
+        monkeypatch.delenv("SFFT_BATCH_MODE", raising=False)
+    else:
+        monkeypatch.setenv("SFFT_BATCH_MODE", form)
     probs = _problems()
     plans, xs, ys = _plans(sf, probs)
     ws = torch.empty(max(sf.workspace_size_multi(plans, [x.shape[0] for x in xs]), 1), dtype=torch.uint8,
@@ -117,13 +122,21 @@ def test_autotune_keeps_results_and_uses_cache(sf, tmp_path, monkeypatch):
     plan2.close()
 
 
-def test_batch_workload_matches_oracle(sf, tmp_path, monkeypatch):
+@pytest.mark.parametrize("form", ["auto", "chains", "grouped"])
+def test_batch_workload_matches_oracle(sf, tmp_path, monkeypatch, form):
     """The uneven-grid batch exactly as the benchmark runs it: 48x40x32,
     64x64x32, 96x80x64 and 512x384, each with i.i.d. scalar and 3x3 Green
     blocks, 8 right-hand sides each (64 in all), complex64, every plan
-    autotuned, all problems through one sfft_apply_multi graph. Each problem
-    equals its single apply bit for bit and the FP64 oracle to 1e-5."""
+    autotuned, all problems through one sfft_apply_multi graph in either form
+    (per-problem chains, grouped lanes) or the timed choice. Each problem
+    equals its single apply bit for bit (every fused multiply-add is explicit,
+    so grouped and single kernels round alike) and, for the timed choice, the
+    FP64 oracle to 1e-5."""
     monkeypatch.setenv("SFFT_TUNE_CACHE", str(tmp_path / "tune.jsonl"))
+    if form == "auto":
+        monkeypatch.delenv("SFFT_BATCH_MODE", raising=False)
+    else:
+        monkeypatch.setenv("SFFT_BATCH_MODE", form)
     probs = wl.batch_problems()
     plans, xs, ys = [], [], []
     for pr in probs:
@@ -141,9 +154,12 @@ def test_batch_workload_matches_oracle(sf, tmp_path, monkeypatch):
     for rep in range(2):  # capture, then replay
         sf.apply_multi(plans, xs, ys, workspace=ws)
         torch.cuda.synchronize()
+        got = sf.batch_last_form()
+        print(f"[case] batch form requested {form}, replayed {got}", flush=True)
+        assert got == form if form != "auto" else got in ("chains", "grouped")
         for i, (y, ysingle) in enumerate(zip(ys, singles)):
             assert torch.equal(y, ysingle), (rep, i)
-    for pr, y in zip(probs, ys):
+    for pr, y in zip(probs, ys) if form == "auto" else ():
         want = oracle.embed_matvec(pr["coeffs"], pr["x"])
         err = wl.relative_l2(y.cpu().numpy().astype(np.complex128), want)
         print(f"[case] batch problem n={pr['n']} b={pr['b']} rel_l2={err:.3e}", flush=True)

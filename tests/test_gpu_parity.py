@@ -788,3 +788,28 @@ def test_adjoint_follows_plan_update(sf):
     want = oracle.embed_matvec(oracle.adjoint_coeffs(cb), x)
     assert wl.relative_l2(y.cpu().numpy(), want) <= 1e-12
     plan.close()
+
+
+def test_one_plan_on_two_streams_with_distinct_workspaces(sf):
+    """A plan is immutable after creation, so applies of one plan on two streams
+    at once, each with its own workspace, must give the same bits as
+    applies one after another (both schedules)."""
+    grid, b = (24, 20, 32), 3
+    coeffs = wl.green_coeffs(grid, 0.8)
+    xa = torch.from_numpy(wl.vectors(120, grid, b, 2).astype(np.complex64)).cuda()
+    xb = torch.from_numpy(wl.vectors(121, grid, b, 2).astype(np.complex64)).cuda()
+    for sched in ("depth", "breadth"):
+        plan = sf.Plan(grid, b, torch.from_numpy(coeffs).cuda(), dtype="c64", max_nrhs=2, schedule=sched)
+        ya_ref = plan.apply(xa, workspace=plan.alloc_workspace(2))
+        yb_ref = plan.apply(xb, workspace=plan.alloc_workspace(2))
+        torch.cuda.synchronize()
+        s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+        w1, w2 = plan.alloc_workspace(2), plan.alloc_workspace(2)
+        ya, yb = torch.empty_like(xa), torch.empty_like(xb)
+        torch.cuda.synchronize()
+        for _ in range(20):  # interleaved launches on both streams
+            plan.apply(xa, ya, w1, stream=s1)
+            plan.apply(xb, yb, w2, stream=s2)
+        torch.cuda.synchronize()
+        assert torch.equal(ya, ya_ref) and torch.equal(yb, yb_ref), sched
+        plan.close()
