@@ -111,6 +111,8 @@ def pmc_probe(workload="green64"):
     import torch
     import workloads as wl
     import paper_2406_17981_amd as sf
+    # the counters describe the kernels built from these sources
+    log(f"[pmc-probe] kernel_source_hash {kernel_source_hash()}")
     a = torch.empty(COPY_PROBE_BYTES // 4, dtype=torch.float32, device="cuda").fill_(1.0)
     b = torch.empty_like(a)
     b.copy_(a)
@@ -145,7 +147,7 @@ def pmc_probe(workload="green64"):
     log("pmc probe done")
 
 
-def pmc_summarize(fetch_dir, write_dir, out_path):
+def pmc_summarize(fetch_dir, write_dir, out_path, probe_log):
     """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the leaf kernel, scaled by the
     copy probe's counters, written as JSON for the roofline's traffic field."""
     import csv
@@ -176,7 +178,7 @@ def pmc_summarize(fetch_dir, write_dir, out_path):
     total = None
     if out["fetch"]["leaf_bytes"] is not None and out["write"]["leaf_bytes"] is not None:
         total = out["fetch"]["leaf_bytes"] + out["write"]["leaf_bytes"]
-    rec = dict(kernel="sfft::k_leaf<float, 64, 3, 2, false, 1>", kernel_source_hash=kernel_source_hash(),
+    rec = dict(kernel="sfft::k_leaf<float, 64, 3, 2, false, 1>", kernel_source_hash=probe_source_hash(probe_log),
                bytes_per_launch=total, detail=out,
                command="rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) -- python3 bench.py --pmc-probe")
     with open(out_path, "w") as f:
@@ -223,9 +225,18 @@ LARGE_PMC_KERNELS = {
 }
 
 
-def pmc_summarize_large(fetch_dir, write_dir, out_path):
+def probe_source_hash(probe_log):
+    """Kernel source hash that a --pmc-probe run printed (its stderr log)."""
+    for ln in open(probe_log):
+        if ln.startswith("[pmc-probe] kernel_source_hash "):
+            return ln.split()[-1]
+    raise SystemExit(f"{probe_log}: no kernel_source_hash line from --pmc-probe")
+
+
+def pmc_summarize_large(fetch_dir, write_dir, out_path, probe_log):
     """Per-dispatch FETCH_SIZE / WRITE_SIZE of the 256x256x128 kernels, scaled by
-    the copy probe's counters, against their algorithmic bytes."""
+    the copy probe's counters, against their algorithmic bytes; stamped with the
+    kernel source hash the probe reported."""
     import csv
     import glob
 
@@ -253,7 +264,7 @@ def pmc_summarize_large(fetch_dir, write_dir, out_path):
             out[name] = dict(fetch_bytes=r["fetch"], write_bytes=r["write"], measured_bytes=r["fetch"] + r["write"],
                              algorithmic_bytes=alg, ratio=(r["fetch"] + r["write"]) / alg, launches=r["launches"])
     rec = dict(workload="256x256x128, b=3, 8 right-hand sides, c64, split depth-first", scales=scales,
-               kernel_source_hash=kernel_source_hash(), kernels=out,
+               kernel_source_hash=probe_source_hash(probe_log), kernels=out,
                command="rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) -- python3 bench.py --workload large --pmc-probe")
     with open(out_path, "w") as f:
         json.dump(rec, f, indent=1)
@@ -912,7 +923,8 @@ def main():
                     help="large (default, the headline): 256x256x128, b=3, 8 RHS, split vs embed; "
                          "green64: the 64^3 one-RHS configuration; "
                          "batch: 8 uneven-grid problems, 64 RHS, one graph; serve: the Poisson stream")
-    ap.add_argument("--pmc-summarize", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON"))
+    ap.add_argument("--pmc-summarize", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON", "PROBE_LOG"),
+                    help="PROBE_LOG: stderr of one of the --pmc-probe runs (names the kernel sources measured)")
     ap.add_argument("--prof-summarize", nargs=4, metavar=("RESULTS_DB", "OUT_MD", "TITLE", "COMMAND"),
                     help="write a kernel-statistics table from a rocprofv3 --kernel-trace results database")
     ap.add_argument("--pmc-table", nargs=4, metavar=("PMC_DIR", "OUT_MD", "TITLE", "COMMAND"),

@@ -86,6 +86,9 @@ typedef struct {
   int block_symmetry;      /* 0, or 1 / 2 when t[a,c] = t[c,a] / -t[c,a] at every offset:
                               the symbol then stores the b(b+1)/2 components a <= c */
   size_t adjoint_symbol_bytes; /* device bytes of the T^H symbols (0 until sfft_plan_enable_adjoint) */
+  int tile_mode[8];        /* per level, the strided passes' workgroup width: 0 by rule (128 lanes
+                              below 2048 workgroups, else 256), 1 always 256, 2 always 128 lanes
+                              (set by sfft_plan_autotune; 0 for levels of size 1) */
 } sfft_info;
 
 /* Build a plan and its Fourier-space symbols.
@@ -314,7 +317,10 @@ sfft_status sfft_gmres_solve(sfft_plan lo, sfft_plan hi, const void* chi, const 
  * SFFT_SPLIT with d > 1) and leaf right-hand-side groupings (1, 2, 4, 8 per
  * workgroup, within the kernel's limit) at nrhs right-hand sides on `stream`,
  * and keeps the fastest in the plan (sfft_workspace_size follows the chosen
- * schedule). With use_cache != 0 a result stored for the same device,
+ * schedule); then, level by level, the strided passes' workgroup width (256
+ * or 128 lanes, where the length has both) against the built-in rule,
+ * keeping a fixed width only when it is more than 1% faster
+ * (sfft_info.tile_mode). With use_cache != 0 a result stored for the same device,
  * method, dtype, block size, grid, storage and nrhs in the JSON-lines file
  * named by SFFT_TUNE_CACHE (default $HOME/.cache/sfft_autotune.jsonl) is
  * reused without timing, and new results are appended to it. Allocates and

@@ -66,6 +66,7 @@ struct PassArgs {
   const void* tw;    // 2L entries exp(-i pi m / L)
   int64_t len;       // pencil length L (read by the runtime-length kernels only)
   int use_phase;     // FWD2/INV2: multiply the odd child by Phi / conj(Phi)
+  int tile_mode;     // strided passes: 0 width by rule, 1 full-size, 2 half-size workgroups
   // LEAF only
   const void* sym;   // symbols for branch q at sym + q*sym_bs
   int64_t sym_bs;
@@ -844,7 +845,8 @@ template <typename Real, int L, int MODE> hipError_t launch_strided(const PassAr
   if constexpr (half_tiles_ok<Real, L>()) {
     const int64_t cols = a.outer * a.inner;
     const int64_t blocks = a.nq * ((cols + G::W - 1) / G::W);
-    if (blocks < kHalfTilesBelow) return launch_strided_nt<Real, L, MODE, G::NT / 2>(a, s);
+    if (a.tile_mode == 2 || (a.tile_mode == 0 && blocks < kHalfTilesBelow))
+      return launch_strided_nt<Real, L, MODE, G::NT / 2>(a, s);
   }
   return launch_strided_nt<Real, L, MODE, G::NT>(a, s);
 }

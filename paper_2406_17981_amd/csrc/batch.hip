@@ -447,7 +447,8 @@ std::string tune_key(const sfft_plan_s* p, int64_t nrhs) {
   return k.str();
 }
 
-bool tune_lookup(const std::string& key, int* sched, int* rb) {
+// tiles: one digit per level (the plan's tile_mode), "" when not recorded
+bool tune_lookup(const std::string& key, int* sched, int* rb, std::string* tiles) {
   std::ifstream f(tune_cache_path());
   std::string line;
   bool found = false;
@@ -462,16 +463,21 @@ bool tune_lookup(const std::string& key, int* sched, int* rb) {
     if (s >= SFFT_SCHED_BREADTH && s <= SFFT_SCHED_DEPTH && r >= 0) {
       *sched = s;
       *rb = r;
+      tiles->clear();
+      const size_t pt = line.find("\"tiles\": \"");
+      if (pt != std::string::npos)
+        for (size_t i = pt + 10; i < line.size() && line[i] >= '0' && line[i] <= '2'; ++i) tiles->push_back(line[i]);
       found = true;
     }
   }
   return found;
 }
 
-void tune_store(const std::string& key, int sched, int rb, double us) {
+void tune_store(const std::string& key, int sched, int rb, const std::string& tiles, double us) {
   std::ofstream f(tune_cache_path(), std::ios::app);
   if (!f) return;  // a read-only home leaves tuning per process
-  f << "{\"key\": \"" << key << "\", \"sched\": " << sched << ", \"rb\": " << rb << ", \"us\": " << us << "}\n";
+  f << "{\"key\": \"" << key << "\", \"sched\": " << sched << ", \"rb\": " << rb << ", \"tiles\": \"" << tiles
+    << "\", \"us\": " << us << "}\n";
 }
 
 }  // namespace
@@ -580,6 +586,9 @@ sfft_status sfft_apply_multi(int nprob, const sfft_plan* plans, const void* cons
     key.push_back((uintptr_t)nrhs[i]);
     key.push_back((uintptr_t)plans[i]->sched);
     key.push_back((uintptr_t)plans[i]->rb_pref);
+    uintptr_t tm = 0;
+    for (int l = 0; l < kMaxD; ++l) tm = tm * 3 + (uintptr_t)plans[i]->tile_mode[l];
+    key.push_back(tm);
   }
   const int req = batch_form_request();
   key.push_back((uintptr_t)(req + 1));
@@ -687,9 +696,11 @@ sfft_status sfft_plan_autotune(sfft_plan plan, int64_t nrhs, int use_cache, void
   hipStream_t st = (hipStream_t)stream;
   const std::string key = tune_key(plan, nrhs);
   int sched = 0, rb = 0;
-  if (use_cache && tune_lookup(key, &sched, &rb)) {
+  std::string tiles;
+  if (use_cache && tune_lookup(key, &sched, &rb, &tiles)) {
     if (plan->method == SFFT_SPLIT) plan->sched = sched;
     plan->rb_pref = rb;
+    for (int l = 0; l < plan->d; ++l) plan->tile_mode[l] = l < (int)tiles.size() ? tiles[l] - '0' : 0;
     if (best_us) *best_us = -1.0;
     return SFFT_OK;
   }
@@ -702,6 +713,11 @@ sfft_status sfft_plan_autotune(sfft_plan plan, int64_t nrhs, int use_cache, void
     for (int r = 1; r <= rbmax && (r == 1 || r <= 2 * nrhs - 1); r *= 2) cand.push_back({sc, r});
   const size_t vbytes = (size_t)(nrhs * plan->b * plan->s) * plan->esz;
   const int old_sched = plan->sched, old_rb = plan->rb_pref;
+  int old_tiles[kMaxD];
+  for (int l = 0; l < kMaxD; ++l) {
+    old_tiles[l] = plan->tile_mode[l];
+    plan->tile_mode[l] = 0;  // schedules and groupings are timed with the rule's widths
+  }
   size_t wsmax = 0;
   for (int sc : scheds) {
     plan->sched = sc;
@@ -739,22 +755,28 @@ sfft_status sfft_plan_autotune(sfft_plan plan, int64_t nrhs, int use_cache, void
     *us = 1e3 * ms / reps;
     return SFFT_OK;
   };
+  // one candidate: a warm-up apply, then three trials of `reps` applies
+  auto time_candidate = [&](double* cbest) -> sfft_status {
+    sfft_status r = sfft_rt_apply_one(plan, x, y, nrhs, ws, wsmax, st);  // warm-up
+    double est = 0.0;
+    if (r == SFFT_OK) r = time_reps(1, &est);
+    if (r != SFFT_OK) return r;
+    int reps = est > 0.0 ? (int)(2000.0 / est) : 3;
+    reps = reps < 3 ? 3 : (reps > 200 ? 200 : reps);
+    *cbest = 1e300;
+    for (int trial = 0; trial < 3 && r == SFFT_OK; ++trial) {
+      double us = 0.0;
+      r = time_reps(reps, &us);
+      if (r == SFFT_OK && us < *cbest) *cbest = us;
+    }
+    return r;
+  };
   for (auto& c : cand) {
     if (s != SFFT_OK) break;
     plan->sched = c.first;
     plan->rb_pref = c.second;
-    s = sfft_rt_apply_one(plan, x, y, nrhs, ws, wsmax, st);  // warm-up
-    double est = 0.0;
-    if (s == SFFT_OK) s = time_reps(1, &est);
-    if (s != SFFT_OK) break;
-    int reps = est > 0.0 ? (int)(2000.0 / est) : 3;
-    reps = reps < 3 ? 3 : (reps > 200 ? 200 : reps);
     double cbest = 1e300;
-    for (int trial = 0; trial < 3 && s == SFFT_OK; ++trial) {
-      double us = 0.0;
-      s = time_reps(reps, &us);
-      if (s == SFFT_OK && us < cbest) cbest = us;
-    }
+    s = time_candidate(&cbest);
     if (s != SFFT_OK) break;
     if (cbest < best) {
       best = cbest;
@@ -771,6 +793,29 @@ sfft_status sfft_plan_autotune(sfft_plan plan, int64_t nrhs, int use_cache, void
     br = bdr;
     best = best_depth;
   }
+  // then, level by level, a fixed workgroup width for the strided passes
+  // (levels 1..d-1; the last level is the leaf) against the rule, kept only
+  // when more than 1% faster
+  if (s == SFFT_OK) {
+    plan->sched = bs;
+    plan->rb_pref = br;
+    for (int l = 0; l + 1 < plan->d && s == SFFT_OK; ++l) {
+      if (!plan->ops[l]->strided_prep[1]) continue;  // the length has one width only
+      int keep = 0;
+      double lbest = best;
+      for (int mode = 1; mode <= 2 && s == SFFT_OK; ++mode) {
+        plan->tile_mode[l] = mode;
+        double us = 1e300;
+        s = time_candidate(&us);
+        if (s == SFFT_OK && us < 0.99 * lbest) {
+          lbest = us;
+          keep = mode;
+        }
+      }
+      plan->tile_mode[l] = keep;
+      best = lbest;
+    }
+  }
   (void)hipStreamSynchronize(st);
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
@@ -780,11 +825,14 @@ sfft_status sfft_plan_autotune(sfft_plan plan, int64_t nrhs, int use_cache, void
   if (s != SFFT_OK) {
     plan->sched = old_sched;
     plan->rb_pref = old_rb;
+    for (int l = 0; l < kMaxD; ++l) plan->tile_mode[l] = old_tiles[l];
     return s;
   }
   plan->sched = bs;
   plan->rb_pref = br;
-  if (use_cache) tune_store(key, bs, br, best);
+  std::string tiles_out;
+  for (int l = 0; l < plan->d; ++l) tiles_out.push_back((char)('0' + plan->tile_mode[l]));
+  if (use_cache) tune_store(key, bs, br, tiles_out, best);
   if (best_us) *best_us = best;
   return SFFT_OK;
 }

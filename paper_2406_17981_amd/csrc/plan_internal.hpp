@@ -58,6 +58,7 @@ struct sfft_plan_s {
   uint8_t odd_adj[16] = {0};
   // right-hand sides per leaf workgroup chosen by the autotuner (0: automatic)
   int rb_pref = 0;
+  int tile_mode[kMaxD] = {0};  // strided passes per level: 0 rule, 1 full-size, 2 half-size workgroups
   size_t table_bytes = 0;
   std::mutex pool_mu;
   void* pool = nullptr;

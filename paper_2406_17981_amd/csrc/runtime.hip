@@ -461,6 +461,7 @@ PassArgs base_args(const sfft_plan_s* p, int l, int64_t nv, int64_t len0) {
   a.tw = p->tw[l];
   a.len = p->L[l];
   a.nq = 1;
+  a.tile_mode = p->tile_mode[l];
   return a;
 }
 
@@ -1452,6 +1453,8 @@ sfft_status sfft_plan_info(sfft_plan plan, sfft_info* info) {
   info->workspace_bytes = workspace_elems(plan, plan->max_nrhs) * plan->esz;
   info->vector_elems = plan->b * plan->s;
   info->adjoint_symbol_bytes = plan->sym_adj ? plan->sym_bytes : 0;
+  for (int l = 0, k = 0; l < plan->user_d; ++l)  // levels of size 1 have no pass
+    if (plan->user_n[l] > 1) info->tile_mode[l] = plan->tile_mode[k++];
   return SFFT_OK;
 }
 

@@ -89,7 +89,8 @@ class Plan:
                     schedule=inf.schedule, compressed=inf.compressed, max_nrhs=inf.max_nrhs,
                     symbol_bytes=inf.symbol_bytes, table_bytes=inf.table_bytes,
                     workspace_bytes=inf.workspace_bytes, vector_elems=inf.vector_elems,
-                    block_symmetry=inf.block_symmetry, adjoint_symbol_bytes=inf.adjoint_symbol_bytes)
+                    block_symmetry=inf.block_symmetry, adjoint_symbol_bytes=inf.adjoint_symbol_bytes,
+                    tile_mode=tuple(inf.tile_mode[:inf.d]))
 
     def workspace_size(self, nrhs: int) -> int:
         out = C.c_size_t()

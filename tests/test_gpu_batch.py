@@ -118,8 +118,17 @@ def test_autotune_keeps_results_and_uses_cache(sf, tmp_path, monkeypatch):
     plan2 = sf.Plan(n, b, torch.from_numpy(coeffs).cuda(), dtype="c64", max_nrhs=nrhs)
     assert plan2.autotune(nrhs) == -1.0  # answered from the cache
     assert plan2.info()["schedule"] == plan.info()["schedule"]
+    assert plan2.info()["tile_mode"] == plan.info()["tile_mode"]
+    assert all(m in (0, 1, 2) for m in plan.info()["tile_mode"])
+    # tuned widths and groupings only regroup pencils: bit-identical to an untuned plan
+    plain = sf.Plan(n, b, torch.from_numpy(coeffs).cuda(), dtype="c64", max_nrhs=nrhs,
+                    schedule=["auto", "breadth", "depth"][plan.info()["schedule"]])
+    y0 = plain.apply(torch.from_numpy(x).to(torch.complex64).cuda(), workspace=plain.alloc_workspace(nrhs))
+    torch.cuda.synchronize()
+    assert torch.equal(y, y0)
     plan.close()
     plan2.close()
+    plain.close()
 
 
 @pytest.mark.parametrize("form", ["auto", "chains", "grouped"])
