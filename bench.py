@@ -218,8 +218,9 @@ def prof_summarize(db_path, out_path, title, command):
 LARGE_PMC_KERNELS = {
     "sfft::k_leaf<float, 128, 3, 2, false, 1>": 2 * 1610612736 + 805306368,
     # mirrored symbols: a branch's parities select a quarter of the stored
-    # 6 x 257 x 257 x 129 entries along the outer two levels
-    "sfft::k_leaf<float, 128, 3, 2, true, 1>": 2 * 1610612736 + 6 * 129 * 129 * 129 * 8,
+    # 6 x 257 x 257 x 130 entries along the outer two levels (rows of 128 + 2
+    # entries: lane pairs of the 32-lane, 4-entry leaf)
+    "sfft::k_leaf<float, 128, 3, 2, true, 1>": 2 * 1610612736 + 6 * 129 * 129 * 130 * 8,
     "sfft::k_strided<float, 256, 0, 256>": 3 * 1610612736,
     "sfft::k_strided<float, 256, 1, 256>": 3 * 1610612736,
 }

@@ -89,6 +89,10 @@ typedef struct {
   int tile_mode[8];        /* per level, the strided passes' workgroup width: 0 by rule (128 lanes
                               below 2048 workgroups, else 256), 1 always 256, 2 always 128 lanes
                               (set by sfft_plan_autotune; 0 for levels of size 1) */
+  int64_t mirror_row;      /* mirrored storage: stored entries along the last level (n_d + 1, or
+                              n_d + E/2 where the leaf reads lane pairs, E its entries per lane);
+                              symbol_bytes = components x prod_{l<d}(n_l + 1) x mirror_row x dtype
+                              size. 0 without mirrored storage */
 } sfft_info;
 
 /* Build a plan and its Fourier-space symbols.

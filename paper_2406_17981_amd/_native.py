@@ -39,7 +39,7 @@ class SfftInfo(C.Structure):
         ("method", C.c_int), ("schedule", C.c_int), ("compressed", C.c_int),
         ("max_nrhs", C.c_int64), ("symbol_bytes", C.c_size_t), ("table_bytes", C.c_size_t),
         ("workspace_bytes", C.c_size_t), ("vector_elems", C.c_int64), ("block_symmetry", C.c_int),
-        ("adjoint_symbol_bytes", C.c_size_t), ("tile_mode", C.c_int * 8),
+        ("adjoint_symbol_bytes", C.c_size_t), ("tile_mode", C.c_int * 8), ("mirror_row", C.c_int64),
     ]
 
 

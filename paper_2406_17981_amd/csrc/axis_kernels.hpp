@@ -91,6 +91,7 @@ struct PassArgs {
   int64_t mst[6];    // strides of the stored array
   int64_t mcomp;     // stored entries per component
   uint8_t odd[16];   // bit l of odd[k]: stored component k is odd along level l
+  FastDiv mfd[6];    // divisions by the level sizes mn[l], l < d - 1
   // filled by the launchers: block and column decoding without 64-bit division
   FastDiv fd_a, fd_b;  // strided: tiles per branch, inner; leaf: rhs groups, tile groups of 8
   int idx32;           // every decoded index fits in 32 bits
@@ -528,19 +529,24 @@ __device__ __forceinline__ void leaf_body(const PassArgs& a, uint32_t bid) {
   uint32_t mbits = 0;
   if constexpr (MIR) {
     const int64_t Q = a.q0 + q;
-    int64_t rem = a.pen0 + p0 + (g < nh ? g : 0);
+    // multiply-high divisions by the level sizes (mirrored plans keep every
+    // component under 4 GiB, so pencil indexes fit in 32 bits)
+    uint32_t rem = (uint32_t)(a.pen0 + p0 + (g < nh ? g : 0));
+    uint32_t mb = 0;
     for (int l = a.d - 2; l >= 0; --l) {
-      const int64_t n = a.mn[l];
-      const int64_t j = rem % n;
-      rem /= n;
-      const int pl = (int)((Q >> (a.d - 2 - l)) & 1);
-      int64_t jj = j;
+      const uint32_t n = a.mfd[l].d;
+      const uint32_t qt = a.mfd[l].div(rem);
+      const uint32_t j = rem - qt * n;
+      rem = qt;
+      const uint32_t pl = (uint32_t)((Q >> (a.d - 2 - l)) & 1);
+      uint32_t jj = j;
       if (2 * j + pl > n) {
         jj = pl ? n - 1 - j : n - j;
         mbits |= 1u << l;
       }
-      mbase += (pl * (n / 2 + 1) + jj) * a.mst[l];
+      mb += (pl * (n / 2 + 1) + jj) * (uint32_t)a.mst[l];
     }
+    mbase = mb;
   }
   const int slane = g * T + t;  // lane inside the symbol block
   // mirrored storage: bit k of osign is set when stored component k enters
@@ -575,27 +581,66 @@ __device__ __forceinline__ void leaf_body(const PassArgs& a, uint32_t bid) {
       for (int k = 0; k < NS; ++k) pf[j][k] = *(const C2*)(sym_base(0) + sym_offset(k, 2 * j, slane, E, SL));
   }
   // mirrored storage: the stored entries of group (p, m0) of every component,
-  // with their sign flips (bit k of flip[j])
+  // with their sign flips (bit k of flip[j]). With E a multiple of 4 the
+  // last level's rows are stored in lane pairs (the runtime's mirror
+  // scatter): entries m0, m0 + 1 of a lane are one 16-byte load, from the
+  // lane itself below E/2 and from its mirror lane (pair E - 2 - m0, halves
+  // swapped) above; otherwise one 8-byte load per entry from the plain row.
+  constexpr bool PAIRED = MIR && (E % 4 == 0);
   auto mir_group = [&](int p, int m0, C (&dst)[MSP][NS], uint32_t (&flip)[MSP]) {
-    uint32_t off[MSP];
 #pragma unroll
     for (int j = 0; j < MSP; ++j) {
       const int k = t + T * (m0 + j);
       const bool mir = 2 * k + p > L;
-      off[j] = ((uint32_t)mbase + (uint32_t)(p * (L / 2 + 1) + (mir ? (p ? L - 1 - k : L - k) : k))) *
-               (uint32_t)sizeof(C);
       flip[j] = osign ^ (mir ? lodd : 0u);
     }
+    if constexpr (PAIRED) {
+      const bool upper = 2 * m0 >= E;  // compile-time once unrolled
+      const int W = p ? T : T + 1;
+      const int u = upper ? (p ? T - 1 - t : T - t) : t;
+      const int P = upper ? (E - 2 - m0) / 2 : m0 / 2;
+      const uint32_t off =
+          ((uint32_t)mbase + (uint32_t)((p ? (T + 1) * (E / 2) : 0) + (P * W + u) * 2)) * (uint32_t)sizeof(C);
 #pragma unroll
-    for (int k = 0; k < NS; ++k) {
-      const char* base = (const char*)a.sym + k * a.mcomp * (int64_t)sizeof(C);
+      for (int k = 0; k < NS; ++k) {
+        const C2 v = *(const C2*)((const char*)a.sym + k * a.mcomp * (int64_t)sizeof(C) + off);
+        dst[upper ? 1 : 0][k] = mk<C>(v.x, v.y);
+        dst[upper ? 0 : 1][k] = mk<C>(v.z, v.w);
+      }
+    } else {
+      uint32_t off[MSP];
 #pragma unroll
-      for (int j = 0; j < MSP; ++j) dst[j][k] = *(const C*)(base + off[j]);
+      for (int j = 0; j < MSP; ++j) {
+        const int k = t + T * (m0 + j);
+        const bool mir = 2 * k + p > L;
+        off[j] = ((uint32_t)mbase + (uint32_t)(p * (L / 2 + 1) + (mir ? (p ? L - 1 - k : L - k) : k))) *
+                 (uint32_t)sizeof(C);
+      }
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        const char* base = (const char*)a.sym + k * a.mcomp * (int64_t)sizeof(C);
+#pragma unroll
+        for (int j = 0; j < MSP; ++j) dst[j][k] = *(const C*)(base + off[j]);
+      }
     }
   };
-  C mpf[MSP][NS];
-  uint32_t mpf_flip[MSP];
-  if constexpr (MIR) mir_group(0, 0, mpf, mpf_flip);
+  // mirrored storage requests groups ahead as the general layout does: NPF
+  // of parity 0 before the forward transforms, the first of parity 1 before
+  // parity 0's product (-4% on the length-128 leaf: it then matches the
+  // general one). Only complex64 leaves of length <= 128 with lane pairs
+  // keep their occupancy with the extra registers (complex128, and lengths
+  // 256 to 1024, drop a wavefront per SIMD); the others request one group.
+  constexpr bool MPF = PAIRED && sizeof(Real) == 4 && L <= 128;
+  constexpr int MNPF = MPF ? NPF : 1;
+  constexpr bool MPF1 = MPF && PF1 && NPAR == 2;
+  C mpf[MNPF][MSP][NS];
+  uint32_t mpf_flip[MNPF][MSP];
+  C mpf1[MPF1 ? MSP : 1][NS];
+  uint32_t mpf1_flip[MSP];
+  if constexpr (MIR) {
+#pragma unroll
+    for (int i = 0; i < MNPF; ++i) mir_group(0, i * MSP, mpf[i], mpf_flip[i]);
+  }
   // mulBrn for one child p: w[.][m] <- S_p[., .](m) w[.][m]
   auto block_product = [&](C (&w)[B][E], int p) {
     if constexpr (!MIR && MSP == 2 && NPAR == 2 && PF1) {  // the embedding baseline has one child
@@ -603,6 +648,9 @@ __device__ __forceinline__ void leaf_body(const PassArgs& a, uint32_t bid) {
 #pragma unroll
         for (int k = 0; k < NS; ++k) pf1[k] = *(const C2*)(sym_base(1) + sym_offset(k, 0, slane, E, SL));
       }
+    }
+    if constexpr (MPF1) {
+      if (p == 0) mir_group(1, 0, mpf1, mpf1_flip);
     }
     const C* sp = (const C*)a.sym + q * a.sym_bs + ((int64_t)p * a.sym_ntiles + a.tile0 + tile) * (NS * E * SL);
     constexpr int MS = (E % 2 == 0) ? 2 : 1;  // entries per symbol load
@@ -612,12 +660,19 @@ __device__ __forceinline__ void leaf_body(const PassArgs& a, uint32_t bid) {
       if constexpr (MIR) {
         C raw[MSP][NS];
         uint32_t flip[MSP];
-        if (p == 0 && m0 == 0) {
+        if (p == 0 && m0 < MNPF * MSP) {
 #pragma unroll
           for (int j = 0; j < MSP; ++j) {
-            flip[j] = mpf_flip[j];
+            flip[j] = mpf_flip[m0 / MSP][j];
 #pragma unroll
-            for (int k = 0; k < NS; ++k) raw[j][k] = mpf[j][k];
+            for (int k = 0; k < NS; ++k) raw[j][k] = mpf[m0 / MSP][j][k];
+          }
+        } else if (MPF1 && p == 1 && m0 == 0) {
+#pragma unroll
+          for (int j = 0; j < MSP; ++j) {
+            flip[j] = mpf1_flip[j];
+#pragma unroll
+            for (int k = 0; k < NS; ++k) raw[j][k] = mpf1[MPF1 ? j : 0][k];
           }
         } else {
           mir_group(p, m0, raw, flip);

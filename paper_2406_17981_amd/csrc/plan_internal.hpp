@@ -49,6 +49,10 @@ struct sfft_plan_s {
   // when that component is odd along level l
   int64_t mst[kMaxD] = {0};
   int64_t mcomp = 0;
+  // mirrored storage along the last level: mpair = 1 stores each parity's
+  // half row in lane pairs (see k_scatter_mirror), mrow entries per row
+  int mpair = 0;
+  int64_t mrow = 0;
   int32_t parity[16 * kMaxD] = {0};
   uint8_t odd[16] = {0};
   // symbols of the conjugate transpose T^H (sfft_plan_enable_adjoint): the

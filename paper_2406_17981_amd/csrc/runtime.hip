@@ -180,18 +180,39 @@ __global__ void k_scatter_embed(const double2* __restrict__ full, C* __restrict_
 // Mirrored storage of one FP64 symbol component (Section II.C): stored index
 // s_l in [0, n_l] along every level, s_l < n_l/2+1 holding the even bin
 // 2 s_l of the 2n_l lattice and the rest the odd bins 2 (s_l - n_l/2 - 1) + 1.
+// With lane pairs (paired = 1; the leaf's T lanes hold E entries each, E a
+// multiple of 4) the last level's row is the even part, (T + 1) lanes x E/2
+// entries, then the odd part, T lanes x E/2 entries, each part ordered
+// [e / 2][lane][e % 2]: lane u < T, entry e is index u + T e of that parity's
+// half row, and the extra lane T of the even part repeats indexes T (e + 1).
+// A leaf lane t then reads its entries m, m + 1 (m even) as one pair: its own
+// below E/2, lane T - t (even) or T - 1 - t (odd), pair E - 2 - m, above.
 template <typename C>
 __global__ void k_scatter_mirror(const double2* __restrict__ full, C* __restrict__ sym, int ks, Dims dm,
-                                 double scale, int64_t total) {
+                                 double scale, int64_t total, int paired, int T, int E, int64_t mrow) {
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
     int64_t rem = idx, fidx = 0, fstride = 1;
     for (int l = dm.d - 1; l >= 0; --l) {
       const int64_t n = dm.n[l];
-      const int64_t sl = rem % (n + 1);
-      rem /= n + 1;
-      const int64_t m0 = n / 2 + 1;
-      const int64_t M = sl < m0 ? 2 * sl : 2 * (sl - m0) + 1;
+      int64_t M;
+      if (paired && l == dm.d - 1) {
+        const int64_t pos = rem % mrow;
+        rem /= mrow;
+        const int64_t even_part = (int64_t)(T + 1) * (E / 2);
+        const int par = pos < even_part ? 0 : 1;
+        const int64_t q = par ? pos - even_part : pos;
+        const int64_t W = par ? T : T + 1;
+        const int64_t e = 2 * (q / (2 * W)) + (q % 2);
+        const int64_t u = (q / 2) % W;
+        const int64_t h = (par == 0 && u == T) ? T * (e + 1) : u + T * e;  // index in the half row
+        M = 2 * h + par;
+      } else {
+        const int64_t sl = rem % (n + 1);
+        rem /= n + 1;
+        const int64_t m0 = n / 2 + 1;
+        M = sl < m0 ? 2 * sl : 2 * (sl - m0) + 1;
+      }
       fidx += M * fstride;
       fstride *= 2 * n;
     }
@@ -560,6 +581,7 @@ sfft_status leaf_args(const sfft_plan_s* p, const void* in, void* out, int64_t i
     for (int m = 0; m < p->d; ++m) {
       a.mn[m] = p->n[m];
       a.mst[m] = p->mst[m];
+      if (m + 1 < p->d) a.mfd[m] = sfft::FastDiv::make((uint32_t)p->n[m]);
     }
     a.mcomp = p->mcomp;
     for (int k = 0; k < p->ns; ++k) a.odd[k] = adj ? p->odd_adj[k] : p->odd[k];
@@ -887,10 +909,10 @@ sfft_status build_symbols(sfft_plan_s* p, const double2* coeffs, hipStream_t st)
       const int64_t total = p->mcomp;
       if (p->dtype == SFFT_C64)
         hipLaunchKernelGGL(k_scatter_mirror<float2>, dim3(grid_for(total)), dim3(256), 0, st, tmp, (float2*)p->sym,
-                           ks, dm, scale, total);
+                           ks, dm, scale, total, p->mpair, lo->LT, lo->LE, p->mrow);
       else
         hipLaunchKernelGGL(k_scatter_mirror<double2>, dim3(grid_for(total)), dim3(256), 0, st, tmp,
-                           (double2*)p->sym, ks, dm, scale, total);
+                           (double2*)p->sym, ks, dm, scale, total, p->mpair, lo->LT, lo->LE, p->mrow);
     } else if (p->method == SFFT_SPLIT) {
       const int64_t total = (int64_t(1) << d) * p->ntiles * lo->LE * lo->NTL;
       if (p->dtype == SFFT_C64)
@@ -1245,8 +1267,10 @@ sfft_status sfft_plan_create(sfft_plan* out, int d, const int64_t* n, int b, con
     for (int i = 0; i < b * b * d; ++i)
       if (parity[i] == SFFT_PARITY_NONE)
         return fail(SFFT_UNSUPPORTED, "mirrored storage needs every (component, level) even or odd");
-    double bytes = dtype == SFFT_C64 ? 8 : 16;  // the leaf addresses one component with 32-bit offsets
-    for (int l = 0; l < d; ++l) bytes *= (double)(n[l] + 1);
+    // the leaf addresses one component with 32-bit offsets (a bound: rows of
+    // lane pairs hold up to n/2 - 1 more entries along the last level)
+    double bytes = dtype == SFFT_C64 ? 8 : 16;
+    for (int l = 0; l < d; ++l) bytes *= (double)(l == d - 1 ? n[l] + n[l] / 2 + 1 : n[l] + 1);
     if (bytes >= 4294967296.0)
       return fail(SFFT_UNSUPPORTED, "mirrored storage holds at most 4 GiB per block component");
     sfft_status sp = check_parity((const double2*)coeffs, b, d, n, parity, (hipStream_t)stream);
@@ -1294,10 +1318,15 @@ sfft_status sfft_plan_create(sfft_plan* out, int d, const int64_t* n, int b, con
   }
   if (mirror) {
     p->compressed = 1;
+    // the length-specialised leaves read a lane's entries m and m + 1 as one
+    // 16-byte pair (entries per lane a multiple of 4); the runtime-length
+    // leaves keep the plain half rows
+    p->mpair = (!lo->generic && lo->LE % 4 == 0) ? 1 : 0;
+    p->mrow = p->mpair ? n[d - 1] + lo->LE / 2 : n[d - 1] + 1;
     p->mcomp = 1;
     for (int l = d - 1; l >= 0; --l) {
       p->mst[l] = p->mcomp;
-      p->mcomp *= n[l] + 1;
+      p->mcomp *= l == d - 1 ? p->mrow : n[l] + 1;
     }
     for (int i = 0; i < b * b * d; ++i) p->parity[i] = parity[i];
     for (int k = 0; k < p->ns; ++k)
@@ -1455,6 +1484,7 @@ sfft_status sfft_plan_info(sfft_plan plan, sfft_info* info) {
   info->adjoint_symbol_bytes = plan->sym_adj ? plan->sym_bytes : 0;
   for (int l = 0, k = 0; l < plan->user_d; ++l)  // levels of size 1 have no pass
     if (plan->user_n[l] > 1) info->tile_mode[l] = plan->tile_mode[k++];
+  info->mirror_row = plan->compressed ? plan->mrow : 0;
   return SFFT_OK;
 }
 

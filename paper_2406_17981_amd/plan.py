@@ -90,7 +90,7 @@ class Plan:
                     symbol_bytes=inf.symbol_bytes, table_bytes=inf.table_bytes,
                     workspace_bytes=inf.workspace_bytes, vector_elems=inf.vector_elems,
                     block_symmetry=inf.block_symmetry, adjoint_symbol_bytes=inf.adjoint_symbol_bytes,
-                    tile_mode=tuple(inf.tile_mode[:inf.d]))
+                    tile_mode=tuple(inf.tile_mode[:inf.d]), mirror_row=inf.mirror_row)
 
     def workspace_size(self, nrhs: int) -> int:
         out = C.c_size_t()

@@ -275,7 +275,9 @@ def test_mirrored_symbols_green(sf, grid, dtype):
         esz = 8 if dtype == "c64" else 16
         # Green blocks are symmetric: 6 stored components of 9
         assert info["block_symmetry"] == 1
-        assert info["symbol_bytes"] == 6 * math.prod(v + 1 for v in grid) * esz
+        row = info["mirror_row"]  # n + 1, or n + E/2 with lane pairs
+        assert grid[-1] + 1 <= row <= grid[-1] + max(1, grid[-1] // 2)
+        assert info["symbol_bytes"] == 6 * math.prod(v + 1 for v in grid[:-1]) * row * esz
         assert wl.relative_l2(got, want) <= TOL[dtype], sched
 
 
@@ -392,7 +394,11 @@ def test_green_64_mirrored_full_size(sf, green64, dtype):
     got = _run(sf, coeffs, x, dtype, "split", parity=wl.green_parity(3), info=info)
     err = wl.relative_l2(got, want)
     _say(f"green64 mirrored {dtype} rel_l2={err:.3e} symbol_bytes={info['symbol_bytes']}")
-    assert info["symbol_bytes"] == 6 * 65 ** 3 * (8 if dtype == "c64" else 16)
+    # lane pairs: 64 + E/2 entries per last-level row (E = 8 entries per lane
+    # in the complex64 leaf, 4 in the complex128 one) instead of 65
+    row = 68 if dtype == "c64" else 66
+    assert info["mirror_row"] == row
+    assert info["symbol_bytes"] == 6 * 65 ** 2 * row * (8 if dtype == "c64" else 16)
     assert err <= TOL[dtype]
 
 
