@@ -416,7 +416,7 @@ def bench_large(args):
             ms, leaf = time_plan(plan, x, y, ws, args.steps, args.warmup, profile_leaf=head)
             rel[key] = float(f"{sampled_err(kname):.3e}")
             r = dict(ms_per_apply=round(ms, 4), matvecs_per_s=round(nrhs * 1e3 / ms, 2),
-                     schedule=["auto", "breadth", "depth"][info["schedule"]],
+                     schedule=["auto", "breadth", "depth", "slab"][info["schedule"]],
                      symbol_bytes=info["symbol_bytes"], workspace_bytes=info["workspace_bytes"],
                      model_device_bytes=info["symbol_bytes"] + info["table_bytes"] + info["workspace_bytes"] + 2 * vb,
                      measured_device_bytes=int(held) + 2 * vb)
@@ -588,7 +588,7 @@ def bench_batch(args):
         os.environ["SFFT_BATCH_MODE"] = saved
     line = {"workload": "batch-8-problems-64rhs-c64",
             "problems": [dict(grid=list(pr["n"]), b=pr["b"], nrhs=int(pr["x"].shape[0]),
-                              schedule=["auto", "breadth", "depth"][p.info()["schedule"]], tuned_us=round(t, 1))
+                              schedule=["auto", "breadth", "depth", "slab"][p.info()["schedule"]], tuned_us=round(t, 1))
                          for pr, p, t in zip(probs, plans, tuned)],
             "steps": args.steps, "warmup": args.warmup, "results": res,
             "graph_speedup": round(res["sequential_applies"]["ms_per_batch"] / res["apply_multi_graph"]["ms_per_batch"], 3)}
@@ -800,7 +800,7 @@ def bench_green64(args):
         vbytes = nrhs * b * s * esz
         dev_bytes = info["symbol_bytes"] + info["table_bytes"] + info["workspace_bytes"] + 2 * vbytes
         results[f"{vmethod}_{dtype}"] = dict(
-            matvecs_per_s=nrhs * 1e3 / ms, ms_per_matvec=ms, schedule=["auto", "breadth", "depth"][info["schedule"]],
+            matvecs_per_s=nrhs * 1e3 / ms, ms_per_matvec=ms, schedule=["auto", "breadth", "depth", "slab"][info["schedule"]],
             device_bytes=dev_bytes, symbol_bytes=info["symbol_bytes"],
             workspace_bytes=info["workspace_bytes"], vector_bytes=vbytes,
             block_symmetry=info["block_symmetry"])
@@ -820,7 +820,7 @@ def bench_green64(args):
         ws8 = plan.alloc_workspace(8)
         ms8, _ = time_plan(plan, x8, y8, ws8, max(args.steps // 4, 10), args.warmup)
         results["split_c64_8rhs"] = dict(matvecs_per_s=8e3 / ms8, ms_per_apply=ms8,
-                                         schedule=["auto", "breadth", "depth"][plan.info()["schedule"]])
+                                         schedule=["auto", "breadth", "depth", "slab"][plan.info()["schedule"]])
         plan.close()
         del x8, y8, ws8
         torch.cuda.empty_cache()
@@ -911,7 +911,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=None,
                     help="untimed applies first (default 5 large; 2000 green64, whose applies are "
                          "short and would otherwise run before the GPU clocks ramp up; 5 batch)")
-    ap.add_argument("--schedule", default="auto", choices=["auto", "breadth", "depth"])
+    ap.add_argument("--schedule", default="auto", choices=["auto", "breadth", "depth", "slab"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variants", default="all", choices=["all", "headline"])

@@ -62,7 +62,11 @@ typedef enum {
 typedef enum {
   SFFT_SCHED_AUTO = 0,    /* depth-first (the paper's peak memory); sfft_plan_autotune may pick breadth-first */
   SFFT_SCHED_BREADTH = 1, /* all branches of a level per launch: workspace (2^d - 2) vectors */
-  SFFT_SCHED_DEPTH = 2    /* Algorithm 1's lazy order: workspace (d - 1) vectors, peak (d + 1) with x, y */
+  SFFT_SCHED_DEPTH = 2,   /* Algorithm 1's lazy order: workspace (d - 1) vectors, peak (d + 1) with x, y */
+  SFFT_SCHED_SLAB = 3     /* d >= 3: Algorithm 1's order with levels 2..d over slabs of consecutive
+                             level-1 indices, each slab's grandchildren small enough (about 48 MB
+                             each; SFFT_SLAB_MB overrides) to stay in the memory-side cache between
+                             launches: workspace one vector plus (d - 1) slab vectors; d <= 2 as DEPTH */
 } sfft_schedule;
 
 /* Per-(component, level) symmetry of the generator t, used to store the
@@ -318,7 +322,9 @@ sfft_status sfft_gmres_solve(sfft_plan lo, sfft_plan hi, const void* chi, const 
                              sfft_gmres_info* info);
 
 /* Times the plan's candidate schedules (breadth-first and depth-first for
- * SFFT_SPLIT with d > 1) and leaf right-hand-side groupings (1, 2, 4, 8 per
+ * SFFT_SPLIT with d > 1, and the slab form for d > 2; a low-memory schedule
+ * is kept unless breadth-first is more than 3% faster) and leaf
+ * right-hand-side groupings (1, 2, 4, 8 per
  * workgroup, within the kernel's limit) at nrhs right-hand sides on `stream`,
  * and keeps the fastest in the plan (sfft_workspace_size follows the chosen
  * schedule); then, level by level, the strided passes' workgroup width (256

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsfft.so"
 OK, INVALID_ARG, UNSUPPORTED, OUT_OF_MEMORY, HIP_ERROR = range(5)
 C64, C128 = 0, 1
 SPLIT, EMBED = 0, 1
-SCHED_AUTO, SCHED_BREADTH, SCHED_DEPTH = 0, 1, 2
+SCHED_AUTO, SCHED_BREADTH, SCHED_DEPTH, SCHED_SLAB = 0, 1, 2, 3
 PARITY_NONE, PARITY_EVEN, PARITY_ODD = 0, 1, 2
 
 # every function include/sfft.h declares

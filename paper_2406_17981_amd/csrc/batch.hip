@@ -460,7 +460,7 @@ bool tune_lookup(const std::string& key, int* sched, int* rb, std::string* tiles
     if (ps == std::string::npos || pr == std::string::npos) continue;
     s = std::atoi(line.c_str() + ps + 9);
     r = std::atoi(line.c_str() + pr + 6);
-    if (s >= SFFT_SCHED_BREADTH && s <= SFFT_SCHED_DEPTH && r >= 0) {
+    if (s >= SFFT_SCHED_BREADTH && s <= SFFT_SCHED_SLAB && r >= 0) {
       *sched = s;
       *rb = r;
       tiles->clear();
@@ -706,7 +706,8 @@ sfft_status sfft_plan_autotune(sfft_plan plan, int64_t nrhs, int use_cache, void
   }
   std::vector<std::pair<int, int>> cand;
   std::vector<int> scheds;
-  if (plan->method == SFFT_SPLIT && plan->d > 1) scheds = {SFFT_SCHED_BREADTH, SFFT_SCHED_DEPTH};
+  if (plan->method == SFFT_SPLIT && plan->d > 2) scheds = {SFFT_SCHED_BREADTH, SFFT_SCHED_DEPTH, SFFT_SCHED_SLAB};
+  else if (plan->method == SFFT_SPLIT && plan->d > 1) scheds = {SFFT_SCHED_BREADTH, SFFT_SCHED_DEPTH};
   else scheds = {plan->sched};
   const int rbmax = sfft_rt_leaf_rbmax(plan);
   for (int sc : scheds)
@@ -738,10 +739,11 @@ sfft_status sfft_plan_autotune(sfft_plan plan, int64_t nrhs, int use_cache, void
   if (he != hipSuccess) s = sfft_rt_hip_fail(he, "autotune buffers");
   // each candidate: one warm-up apply, then three trials of `reps` applies
   // (reps sized so a trial lasts about 2 ms, at least 3), keeping the fastest
-  // trial; depth-first (the paper's peak memory) wins unless breadth-first is
-  // more than 3% faster
+  // trial; the faster of the low-memory schedules (depth-first, the paper's
+  // peak memory, and its slab form) wins unless breadth-first is more than 3%
+  // faster
   double best = 1e300, best_depth = 1e300;
-  int bs = old_sched, br = old_rb, bdr = old_rb;
+  int bs = old_sched, br = old_rb, bds = SFFT_SCHED_DEPTH, bdr = old_rb;
   auto time_reps = [&](int reps, double* us) -> sfft_status {
     he = hipEventRecord(e0, st);
     sfft_status r = SFFT_OK;
@@ -783,13 +785,14 @@ sfft_status sfft_plan_autotune(sfft_plan plan, int64_t nrhs, int use_cache, void
       bs = c.first;
       br = c.second;
     }
-    if (c.first == SFFT_SCHED_DEPTH && cbest < best_depth) {
+    if (c.first != SFFT_SCHED_BREADTH && cbest < best_depth) {  // the low-memory schedules
       best_depth = cbest;
+      bds = c.first;
       bdr = c.second;
     }
   }
   if (s == SFFT_OK && bs == SFFT_SCHED_BREADTH && best_depth < 1e300 && best > 0.97 * best_depth) {
-    bs = SFFT_SCHED_DEPTH;
+    bs = bds;
     br = bdr;
     best = best_depth;
   }

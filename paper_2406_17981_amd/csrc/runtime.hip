@@ -447,11 +447,38 @@ namespace {
 
 int64_t vec_elems(const sfft_plan_s* p, int64_t nrhs) { return nrhs * p->b * p->s; }
 
+// Slab schedule: level-1 indices per slab, so that one slab vector (all
+// right-hand sides and components, those level-1 indices) is about the target
+// size (SFFT_SLAB_MB, default 48 MB) and its leaf pencils start on tile
+// boundaries.
+int64_t slab_rows(const sfft_plan_s* p, int64_t nrhs) {
+  double target = 48.0 * (1 << 20);
+  const char* env = std::getenv("SFFT_SLAB_MB");
+  if (env && std::atof(env) > 0) target = std::atof(env) * (1 << 20);
+  const int64_t L0 = p->L[0];
+  const int64_t row = p->s / L0;  // entries of one level-1 index of one vector
+  int64_t cc = (int64_t)(target / ((double)nrhs * p->b * row * p->esz));
+  const int64_t ppr = p->npen / L0, PL = p->ops[p->d - 1]->PL;
+  int64_t gcd = PL, r = ppr;
+  while (r) {
+    const int64_t t = gcd % r;
+    gcd = r;
+    r = t;
+  }
+  const int64_t step = PL / gcd;  // cc * ppr must be a multiple of PL
+  cc = cc < step ? step : cc / step * step;
+  return cc > L0 ? L0 : cc;
+}
+
 size_t workspace_elems(const sfft_plan_s* p, int64_t nrhs) {
   const int64_t V = vec_elems(p, nrhs);
   if (p->method == SFFT_EMBED) return (size_t)((int64_t(1) << p->d) * V);
   if (p->d == 1) return 0;
-  if (p->sched == SFFT_SCHED_DEPTH) return (size_t)((p->d - 1) * V);
+  if (p->sched == SFFT_SCHED_SLAB && p->d >= 3) {
+    const int64_t Vs = V / p->L[0] * slab_rows(p, nrhs);
+    return (size_t)(V + (p->d - 1) * Vs);  // the odd child, then the slab's (d - 1) vectors
+  }
+  if (p->sched == SFFT_SCHED_DEPTH || p->sched == SFFT_SCHED_SLAB) return (size_t)((p->d - 1) * V);
   return (size_t)(((int64_t(1) << p->d) - 2) * V);
 }
 
@@ -638,6 +665,71 @@ sfft_status split_depth(const sfft_plan_s* p, int l, const void* src, void* dst,
   b.out = dst;
   b.use_phase = 1;
   return run_pass(p, l, 1, b, st);
+}
+
+// Slab schedule (d >= 3): level 1 over whole vectors; then, for each child
+// and each slab of cc consecutive level-1 indices, the level-2 forward pass
+// reads the slab straight from the child (one branch per vector, stride one
+// vector) into two compact slab vectors, levels 3..d run depth-first on
+// those (the out-of-core slab walk), and the level-2 inverse pass writes the
+// merged slab back into the child. The slab vectors are small enough to stay
+// in the memory-side cache between these launches, so only the child's read
+// and write and the symbols cross HBM below level 1.
+sfft_status split_slab(const sfft_plan_s* p, const void* x, void* y, int64_t nrhs, char* ws, hipStream_t st,
+                       bool adj) {
+  const int64_t nv = nrhs * p->b;
+  const int64_t V = vec_elems(p, nrhs);
+  const int64_t L0 = p->L[0];
+  const int64_t row = p->s / L0;
+  const int64_t cc = slab_rows(p, nrhs);
+  const int64_t ppr = p->npen / L0;
+  const size_t esz = p->esz;
+  char* odd = ws;
+  char* g0 = ws + (size_t)V * esz;
+  char* g1 = g0 + (size_t)(nv * cc * row) * esz;
+  char* deep = g1 + (size_t)(nv * cc * row) * esz;
+  PassArgs a = base_args(p, 0, nv, L0);
+  a.in = x;
+  a.out = y;
+  a.out1 = odd;
+  a.use_phase = 1;
+  sfft_status s = run_pass(p, 0, 0, a, st);
+  if (s != SFFT_OK) return s;
+  for (int c1 = 0; c1 < 2; ++c1) {
+    char* child = c1 ? odd : (char*)y;
+    for (int64_t j0 = 0; j0 < L0; j0 += cc) {
+      const int64_t c = L0 - j0 < cc ? L0 - j0 : cc;
+      const int64_t Vs = nv * c * row;  // entries of one compact slab vector
+      PassArgs f = base_args(p, 1, 1, c);
+      f.in = child + (size_t)(j0 * row) * esz;
+      f.in_bs = p->s;  // branch q = vector q
+      f.nq = nv;
+      f.out = g0;
+      f.out1 = g1;
+      f.out_bs = c * row;
+      f.use_phase = 1;
+      if ((s = run_pass(p, 1, 0, f, st)) != SFFT_OK) return s;
+      const Slab sl{c, j0 * ppr, c * ppr, 2};
+      if ((s = split_depth(p, 2, g0, g0, 2 * c1, nrhs, deep, st, adj, sl)) != SFFT_OK) return s;
+      if ((s = split_depth(p, 2, g1, g1, 2 * c1 + 1, nrhs, deep, st, adj, sl)) != SFFT_OK) return s;
+      PassArgs v = base_args(p, 1, 1, c);
+      v.in = g0;
+      v.in1 = g1;
+      v.in_bs = c * row;
+      v.nq = nv;
+      v.out = child + (size_t)(j0 * row) * esz;
+      v.out_bs = p->s;
+      v.use_phase = 1;
+      if ((s = run_pass(p, 1, 1, v, st)) != SFFT_OK) return s;
+      (void)Vs;
+    }
+  }
+  PassArgs b = base_args(p, 0, nv, L0);
+  b.in = y;
+  b.in1 = odd;
+  b.out = y;
+  b.use_phase = 1;
+  return run_pass(p, 0, 1, b, st);
 }
 
 // Breadth-first: level l's 2^(l+1) branch vectors live contiguously in
@@ -1032,7 +1124,9 @@ sfft_status apply_one(sfft_plan_s* p, const void* x, void* y, int64_t nrhs, void
   }
   if (adj && !p->sym_adj) return fail(SFFT_INVALID_ARG, "adjoint symbols not built (sfft_plan_enable_adjoint)");
   if (p->method == SFFT_EMBED) return embed_apply(p, x, y, nrhs, (char*)ws, st, adj);
-  if (p->sched == SFFT_SCHED_DEPTH && p->d > 1) return split_depth(p, 0, x, y, 0, nrhs, (char*)ws, st, adj, whole(p));
+  if (p->sched == SFFT_SCHED_SLAB && p->d >= 3) return split_slab(p, x, y, nrhs, (char*)ws, st, adj);
+  if ((p->sched == SFFT_SCHED_DEPTH || p->sched == SFFT_SCHED_SLAB) && p->d > 1)
+    return split_depth(p, 0, x, y, 0, nrhs, (char*)ws, st, adj, whole(p));
   return split_breadth(p, x, y, nrhs, (char*)ws, st, adj);
 }
 
@@ -1214,7 +1308,7 @@ sfft_status sfft_plan_create(sfft_plan* out, int d, const int64_t* n, int b, con
   if (b > 4) return fail(SFFT_INVALID_ARG, "block size must be 1, 2, 3 or 4");
   if (dtype != SFFT_C64 && dtype != SFFT_C128) return fail(SFFT_INVALID_ARG, "bad dtype");
   if (method != SFFT_SPLIT && method != SFFT_EMBED) return fail(SFFT_INVALID_ARG, "bad method");
-  if (schedule < SFFT_SCHED_AUTO || schedule > SFFT_SCHED_DEPTH) return fail(SFFT_INVALID_ARG, "bad schedule");
+  if (schedule < SFFT_SCHED_AUTO || schedule > SFFT_SCHED_SLAB) return fail(SFFT_INVALID_ARG, "bad schedule");
   if (max_nrhs < 1) return fail(SFFT_INVALID_ARG, "max_nrhs must be >= 1");
   for (int l = 0; l < d; ++l)
     if (n[l] < 1) return fail(SFFT_INVALID_ARG, "level sizes must be >= 1");

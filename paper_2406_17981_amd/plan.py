@@ -16,7 +16,7 @@ from . import _native as N
 
 _DTYPES = {"c64": (N.C64, torch.complex64), "c128": (N.C128, torch.complex128)}
 _METHODS = {"split": N.SPLIT, "embed": N.EMBED}
-_SCHEDS = {"auto": N.SCHED_AUTO, "breadth": N.SCHED_BREADTH, "depth": N.SCHED_DEPTH}
+_SCHEDS = {"auto": N.SCHED_AUTO, "breadth": N.SCHED_BREADTH, "depth": N.SCHED_DEPTH, "slab": N.SCHED_SLAB}
 
 
 def _stream_handle(stream) -> int:
@@ -41,7 +41,7 @@ class Plan:
     tensor (b, b, 2n_1-1, ..., 2n_d-1) (host arrays are copied to the device);
     dtype "c64" | "c128"; method "split" | "embed"; parity: optional
     (b, b, d) int array of 0 / 1 (even) / 2 (odd) for mirrored symbol storage;
-    schedule "auto" | "breadth" | "depth".
+    schedule "auto" | "breadth" | "depth" | "slab".
     """
 
     def __init__(self, n: Sequence[int], b: int, coeffs, dtype: str = "c64", method: str = "split",

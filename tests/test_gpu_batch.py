@@ -122,7 +122,7 @@ def test_autotune_keeps_results_and_uses_cache(sf, tmp_path, monkeypatch):
     assert all(m in (0, 1, 2) for m in plan.info()["tile_mode"])
     # tuned widths and groupings only regroup pencils: bit-identical to an untuned plan
     plain = sf.Plan(n, b, torch.from_numpy(coeffs).cuda(), dtype="c64", max_nrhs=nrhs,
-                    schedule=["auto", "breadth", "depth"][plan.info()["schedule"]])
+                    schedule=["auto", "breadth", "depth", "slab"][plan.info()["schedule"]])
     y0 = plain.apply(torch.from_numpy(x).to(torch.complex64).cuda(), workspace=plain.alloc_workspace(nrhs))
     torch.cuda.synchronize()
     assert torch.equal(y, y0)

@@ -62,12 +62,15 @@ SMALL = [
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("grid,b", SMALL)
-def test_split_matches_dense_small(sf, grid, b, dtype):
+def test_split_matches_dense_small(sf, grid, b, dtype, monkeypatch):
+    # slab schedule with the smallest slabs (a few level-1 indices each, the
+    # last one ragged): many slab walks per product
+    monkeypatch.setenv("SFFT_SLAB_MB", "0.000001")
     coeffs = wl.iid_coeffs(7, grid, b)
     x = wl.vectors(8, grid, b, 2)
     want = oracle.dense_matvec(coeffs, x) if math.prod(grid) * b <= 4096 else \
         oracle.embed_matvec(coeffs, x)
-    for sched in ("breadth", "depth"):
+    for sched in ("breadth", "depth", "slab"):
         got = _run(sf, coeffs, x, dtype, "split", sched)
         err = wl.relative_l2(got, want)
         assert err <= TOL[dtype], (sched, err)
@@ -129,13 +132,14 @@ def test_green_64_full_size(sf, green64, dtype, method):
     assert err <= TOL[dtype]
 
 
-def test_multi_rhs_and_depth_schedule(sf):
+def test_multi_rhs_and_depth_schedule(sf, monkeypatch):
+    monkeypatch.setenv("SFFT_SLAB_MB", "0.02")  # slabs of a few level-1 indices at 5 RHS
     grid, b = (12, 10, 16), 3
     coeffs = wl.iid_coeffs(12, grid, b)
     x = wl.vectors(13, grid, b, 5)
     want = oracle.embed_matvec(coeffs, x)
     for dtype in ("c128", "c64"):
-        for sched in ("breadth", "depth"):
+        for sched in ("breadth", "depth", "slab"):
             got = _run(sf, coeffs, x, dtype, "split", sched)
             assert wl.relative_l2(got, want) <= TOL[dtype]
 
@@ -262,13 +266,16 @@ def _odd_scalar_coeffs(n, seed):
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("grid", [(6, 10, 12), (5, 12, 40), (16, 16, 16), (10, 12)])
-def test_mirrored_symbols_green(sf, grid, dtype):
-    """Green blocks with symbols stored mirrored (Section II.C): same product."""
+def test_mirrored_symbols_green(sf, grid, dtype, monkeypatch):
+    """Green blocks with symbols stored mirrored (Section II.C): same product,
+    every schedule (the slab one with slabs of a few level-1 indices: the
+    leaf reads the mirrored rows from a slab's pencil offset)."""
+    monkeypatch.setenv("SFFT_SLAB_MB", "0.000001")
     coeffs = wl.green_coeffs(grid, 0.7)
     x = wl.vectors(21, grid, 3, 2)
     want = oracle.embed_matvec(coeffs, x)
     par = wl.green_parity(len(grid))
-    for sched in ("breadth", "depth"):
+    for sched in ("breadth", "depth", "slab"):
         info = {}
         got = _run(sf, coeffs, x, dtype, "split", sched, parity=par, info=info)
         assert info["compressed"] == 1
