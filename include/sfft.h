@@ -111,7 +111,7 @@ typedef struct {
  *   n         host: d level sizes; each must have built kernels (as must 2 n_l).
  *             A level of size 1 (offset 0 only) is dropped internally; at least
  *             one level must be larger (else SFFT_UNSUPPORTED).
- *   b         block size (1 or 3).
+ *   b         block size, 1 <= b <= 4.
  *   coeffs    device, complex128 (b, b, 2n_1-1, ..., 2n_d-1); read during the
  *             call only (the stream is synchronised before return, the caller
  *             may free it afterwards).
@@ -120,7 +120,8 @@ typedef struct {
  *   parity    host, NULL or b*b*d sfft_parity values [(a*b + c)*d + l]: when
  *             every entry is EVEN or ODD and method is SFFT_SPLIT, the symbol
  *             is stored mirrored (about prod(n_l + 1) per component instead
- *             of 2^d prod(n_l)). The declared symmetry is trusted.
+ *             of 2^d prod(n_l)). The declared symmetry is checked exactly
+ *             against the coefficients (SFFT_INVALID_ARG on a mismatch).
  *   max_nrhs  largest nrhs a later apply may use (sizes sfft_plan_info only).
  *   schedule  sfft_schedule.
  *   stream    hipStream_t for the generation kernels.
@@ -140,8 +141,9 @@ sfft_status sfft_plan_create(sfft_plan* out, int d, const int64_t* n, int b, con
  *   coeffs  device, complex128, the layout of sfft_plan_create; its block
  *           symmetry (every pair t[a,c] = t[c,a], or every pair
  *           t[a,c] = -t[c,a], or neither) must equal the plan's
- *           (sfft_info.block_symmetry), else SFFT_INVALID_ARG and the plan is
- *           unchanged. A mirrored plan trusts the parity it was created with.
+ *           (sfft_info.block_symmetry), and a mirrored plan's coefficients
+ *           must keep the parity it was created with (checked exactly), else
+ *           SFFT_INVALID_ARG and the plan is unchanged.
  *   stream  hipStream_t for the generation kernels, synchronised before
  *           return. Every earlier use of the plan (applies on any stream) must
  *           be ordered before the work on `stream`: the symbols are
@@ -357,6 +359,9 @@ sfft_status sfft_profile_enable(sfft_plan plan, unsigned mask);
 /* Waits for the recorded events of one kind and returns their summed
  * duration in milliseconds and the launch count; reset != 0 clears them. */
 sfft_status sfft_profile_read(sfft_plan plan, int kind, double* total_ms, int64_t* launches, int reset);
+/* Frees the plan and its device memory (hipFree waits for the device work in
+ * flight) and drops the batch graphs that hold it. SFFT_INVALID_ARG for a
+ * null plan. */
 sfft_status sfft_plan_destroy(sfft_plan plan);
 
 const char* sfft_status_string(sfft_status s);

@@ -95,7 +95,38 @@ def build(jobs: int | None = None, verbose: bool = False, incremental: bool = Fa
     if rc != 0:
         raise RuntimeError("link failed:\n" + out)
     os.replace(tmp, LIB)
+    build_host_check(units, jobs, incremental)
     return LIB
+
+
+# Host code of the runtime units instrumented by AddressSanitizer and
+# UndefinedBehaviorSanitizer (-Xarch_host: the device code stays the regular
+# build's), linked with the length kernels into tests/native/sfft_host_check.
+HOST_CHECK = os.path.join(PKG, "sfft_host_check")
+SAN = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+       "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-g"]
+
+
+def build_host_check(units, jobs, incremental=False):
+    asan = os.path.join(BUILD, "asan")
+    os.makedirs(asan, exist_ok=True)
+    driver = os.path.join(ROOT, "tests", "native", "sfft_host_check.cpp")
+    san_units = [(src, os.path.join(asan, os.path.basename(obj))) for src, obj, extra in units
+                 if "kernels_L" not in obj]
+    san_units.append((driver, os.path.join(asan, "sfft_host_check.o")))
+    cmds = [[HIPCC] + FLAGS + SAN + ["-c", src, "-o", obj] for src, obj in san_units
+            if not incremental or _stale(src, obj)]
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        results = list(ex.map(_run, cmds))
+    failed = [(c, r) for c, r in zip(cmds, results) if r[0] != 0]
+    if failed:
+        for c, (rc, out, _) in failed:
+            sys.stderr.write(" ".join(c) + "\n" + out + "\n")
+        raise RuntimeError(f"{len(failed)} sanitizer compile step(s) failed")
+    objs = [obj for _, obj in san_units] + [obj for _, obj, _ in units if "kernels_L" in obj]
+    rc, out, _ = _run([HIPCC, f"--offload-arch={ARCH}"] + SAN + ["-o", HOST_CHECK] + objs)
+    if rc != 0:
+        raise RuntimeError("host check link failed:\n" + out)
 
 
 def main():

@@ -1,0 +1,359 @@
+// Host-side memory and undefined-behaviour check of the library's runtime.
+//
+// Built by paper_2406_17981_amd/build.py with the host code of the runtime
+// units instrumented by AddressSanitizer and UndefinedBehaviorSanitizer (the
+// device code is the regular build's). `sfft_host_check host` runs the calls
+// that need no GPU (argument validation, status strings, length table);
+// `sfft_host_check gpu` drives every entry point of include/sfft.h on a small
+// problem: plan creation in both dtypes and all schedules, applies, the
+// adjoint, the allocation-free and out-of-core forms, batches, the
+// autotuner with a cache file holding malformed lines, plan updates, GMRES,
+// profiling and the error paths. A sanitizer report aborts with a nonzero
+// status; otherwise the results are checked for consistency (the schedules
+// and entry points agree bit for bit) and "host check ok" is printed.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <string>
+#include <vector>
+
+#include "../../include/sfft.h"
+
+namespace {
+
+int g_fail = 0;
+
+void expect(bool ok, const char* what) {
+  if (!ok) {
+    std::fprintf(stderr, "FAILED: %s (last error: %s)\n", what, sfft_last_error());
+    ++g_fail;
+  }
+}
+
+void expect_status(sfft_status got, sfft_status want, const char* what) {
+  if (got != want) {
+    std::fprintf(stderr, "FAILED: %s: %s, expected %s (%s)\n", what, sfft_status_string(got),
+                 sfft_status_string(want), sfft_last_error());
+    ++g_fail;
+  }
+}
+
+#define HIPC(x)                                                                        \
+  do {                                                                                 \
+    hipError_t e_ = (x);                                                               \
+    if (e_ != hipSuccess) {                                                            \
+      std::fprintf(stderr, "HIP error %s at %s:%d\n", hipGetErrorString(e_), __FILE__, \
+                   __LINE__);                                                          \
+      std::exit(2);                                                                    \
+    }                                                                                  \
+  } while (0)
+
+// deterministic pseudo-random numbers (SplitMix64)
+struct Rng {
+  uint64_t s;
+  double next() {
+    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return (double)(z >> 11) / 9007199254740992.0 - 0.5;
+  }
+};
+
+void host_only() {
+  expect(std::strcmp(sfft_status_string(SFFT_OK), "SFFT_OK") == 0, "status string");
+  expect(sfft_length_supported(64) == 1, "length 64 specialised");
+  expect(sfft_length_supported(49) == 2, "length 49 runtime");
+  expect(sfft_length_supported(11) == 0, "length 11 unsupported");
+  expect(sfft_length_supported(-5) == 0, "negative length");
+  sfft_plan h = nullptr;
+  const int64_t n[3] = {16, 16, 16};
+  const void* fake = (const void*)0x1000;
+  expect_status(sfft_plan_create(nullptr, 3, n, 1, fake, SFFT_C64, SFFT_SPLIT, nullptr, 1, 0, nullptr),
+                SFFT_INVALID_ARG, "null out");
+  expect_status(sfft_plan_create(&h, 0, n, 1, fake, SFFT_C64, SFFT_SPLIT, nullptr, 1, 0, nullptr), SFFT_INVALID_ARG,
+                "d = 0");
+  expect_status(sfft_plan_create(&h, 3, n, 5, fake, SFFT_C64, SFFT_SPLIT, nullptr, 1, 0, nullptr), SFFT_INVALID_ARG,
+                "b = 5");
+  expect_status(sfft_plan_create(&h, 3, n, 1, fake, SFFT_C64, SFFT_SPLIT, nullptr, 1, 7, nullptr), SFFT_INVALID_ARG,
+                "bad schedule");
+  const int64_t n11[3] = {16, 11, 16};
+  expect_status(sfft_plan_create(&h, 3, n11, 1, fake, SFFT_C64, SFFT_SPLIT, nullptr, 1, 0, nullptr),
+                SFFT_UNSUPPORTED, "prime 11");
+  size_t bytes = 1;
+  expect_status(sfft_workspace_size(nullptr, 1, &bytes), SFFT_INVALID_ARG, "null plan workspace");
+  expect_status(sfft_apply(nullptr, fake, (void*)0x2000, 1, nullptr, 0, nullptr), SFFT_INVALID_ARG, "null plan apply");
+  expect_status(sfft_workspace_size_multi(1, nullptr, nullptr, &bytes), SFFT_INVALID_ARG, "null multi");
+  expect_status(sfft_apply_multi(0, nullptr, nullptr, nullptr, nullptr, nullptr, 0, nullptr), SFFT_OK, "empty multi");
+  expect_status(sfft_plan_destroy(nullptr), SFFT_INVALID_ARG, "destroy null");
+  expect(sfft_batch_last_form() == -1, "no batch form yet");
+}
+
+struct Problem {
+  std::vector<int64_t> n;
+  int b;
+  int64_t ncoef = 1, s = 1;
+  void* coeffs = nullptr;  // device complex128
+};
+
+Problem make_problem(std::vector<int64_t> n, int b, uint64_t seed) {
+  Problem p;
+  p.n = n;
+  p.b = b;
+  for (int64_t v : n) {
+    p.ncoef *= 2 * v - 1;
+    p.s *= v;
+  }
+  std::vector<std::complex<double>> h((size_t)(b * b * p.ncoef));
+  Rng r{seed};
+  for (auto& z : h) z = {r.next(), r.next()};
+  HIPC(hipMalloc(&p.coeffs, h.size() * sizeof(h[0])));
+  HIPC(hipMemcpy(p.coeffs, h.data(), h.size() * sizeof(h[0]), hipMemcpyHostToDevice));
+  return p;
+}
+
+std::vector<char> download(const void* d, size_t bytes) {
+  std::vector<char> h(bytes);
+  HIPC(hipMemcpy(h.data(), d, bytes, hipMemcpyDeviceToHost));
+  return h;
+}
+
+bool finite_c64(const std::vector<char>& h) {
+  const float* f = (const float*)h.data();
+  for (size_t i = 0; i < h.size() / sizeof(float); ++i)
+    if (!std::isfinite(f[i])) return false;
+  return true;
+}
+
+void gpu_checks() {
+  int ndev = 0;
+  HIPC(hipGetDeviceCount(&ndev));
+  if (ndev < 1) {
+    std::fprintf(stderr, "no GPU\n");
+    std::exit(3);
+  }
+  hipStream_t st;
+  HIPC(hipStreamCreate(&st));
+  const int64_t nrhs = 2;
+  Problem pr = make_problem({12, 10, 16}, 3, 7);
+  const size_t vb = (size_t)(nrhs * pr.b * pr.s) * 8;  // complex64 vectors
+  void *x, *y, *y2;
+  HIPC(hipMalloc(&x, vb));
+  HIPC(hipMalloc(&y, vb));
+  HIPC(hipMalloc(&y2, vb));
+  {
+    std::vector<std::complex<float>> h((size_t)(nrhs * pr.b * pr.s));
+    Rng r{11};
+    for (auto& z : h) z = {(float)r.next(), (float)r.next()};
+    HIPC(hipMemcpy(x, h.data(), vb, hipMemcpyHostToDevice));
+  }
+
+  // every schedule gives the same product bit for bit
+  std::vector<char> ref;
+  sfft_plan plans[3] = {nullptr, nullptr, nullptr};
+  const int scheds[3] = {SFFT_SCHED_DEPTH, SFFT_SCHED_BREADTH, SFFT_SCHED_SLAB};
+  for (int i = 0; i < 3; ++i) {
+    expect_status(sfft_plan_create(&plans[i], 3, pr.n.data(), pr.b, pr.coeffs, SFFT_C64, SFFT_SPLIT, nullptr, nrhs,
+                                   scheds[i], st),
+                  SFFT_OK, "plan create");
+    size_t ws = 0;
+    expect_status(sfft_workspace_size(plans[i], nrhs, &ws), SFFT_OK, "workspace size");
+    void* w = nullptr;
+    if (ws) HIPC(hipMalloc(&w, ws));
+    expect_status(sfft_apply(plans[i], x, y, nrhs, w, ws, st), SFFT_OK, "apply");
+    expect_status(sfft_apply(plans[i], x, y2, nrhs, nullptr, 0, st), SFFT_OK, "apply with the plan's pool");
+    if (ws) expect_status(sfft_apply(plans[i], x, y2, nrhs, w, ws - 1, st), SFFT_INVALID_ARG, "short workspace");
+    expect_status(sfft_apply(plans[i], x, x, nrhs, w, ws, st), SFFT_INVALID_ARG, "x aliases y");
+    HIPC(hipStreamSynchronize(st));
+    const std::vector<char> got = download(y, vb);
+    expect(finite_c64(got), "finite product");
+    if (i == 0) ref = got;
+    else expect(got == ref, "schedules agree");
+    expect(download(y2, vb) == ref, "pool workspace agrees");
+    if (w) HIPC(hipFree(w));
+  }
+  sfft_plan p = plans[0];
+  sfft_info info;
+  expect_status(sfft_plan_info(p, &info), SFFT_OK, "info");
+  expect(info.d == 3 && info.b == 3 && info.schedule == SFFT_SCHED_DEPTH, "info fields");
+
+  // allocation-free form
+  expect_status(sfft_apply_noalloc(p, x, y2, nrhs, st), SFFT_OK, "noalloc");
+  HIPC(hipStreamSynchronize(st));
+  expect(download(y2, vb) == ref, "noalloc agrees");
+
+  // adjoint
+  expect_status(sfft_apply_adjoint(p, x, y2, nrhs, nullptr, 0, st), SFFT_INVALID_ARG, "adjoint before enabling");
+  expect_status(sfft_plan_enable_adjoint(p, st), SFFT_OK, "enable adjoint");
+  expect_status(sfft_apply_adjoint(p, x, y2, nrhs, nullptr, 0, st), SFFT_OK, "adjoint");
+  HIPC(hipStreamSynchronize(st));
+  expect(finite_c64(download(y2, vb)), "finite adjoint");
+
+  // out-of-core form (host vectors)
+  {
+    size_t hws = 0, dws = 0;
+    const size_t budget = 4 * vb;  // below the in-core need: several column and row slabs
+    expect_status(sfft_ooc_sizes(p, nrhs, budget, &hws, &dws), SFFT_OK, "ooc sizes");
+    std::vector<char> xh = download(x, vb), yh(vb), hw(hws);
+    void* dw = nullptr;
+    HIPC(hipMalloc(&dw, dws));
+    expect_status(sfft_apply_ooc(p, xh.data(), yh.data(), nrhs, hw.data(), hws, dw, dws, st), SFFT_OK, "ooc apply");
+    expect(yh == ref, "out-of-core agrees");
+    HIPC(hipFree(dw));
+  }
+
+  // batches: two problems, graph and per-call forms
+  Problem pr2 = make_problem({24, 40}, 1, 9);
+  sfft_plan q = nullptr;
+  expect_status(sfft_plan_create(&q, 2, pr2.n.data(), 1, pr2.coeffs, SFFT_C64, SFFT_SPLIT, nullptr, 1, 0, st), SFFT_OK,
+                "second plan");
+  const size_t vb2 = (size_t)pr2.s * 8;
+  void *x2, *yq;
+  HIPC(hipMalloc(&x2, vb2));
+  HIPC(hipMalloc(&yq, vb2));
+  HIPC(hipMemsetAsync(x2, 0x3c, vb2, st));
+  {
+    sfft_plan ps[2] = {p, q};
+    const void* xs[2] = {x, x2};
+    void* ys[2] = {y2, yq};
+    const int64_t nr[2] = {nrhs, 1};
+    size_t mb = 0;
+    expect_status(sfft_workspace_size_multi(2, ps, nr, &mb), SFFT_OK, "multi size");
+    void* mw = nullptr;
+    HIPC(hipMalloc(&mw, mb));
+    for (int rep = 0; rep < 2; ++rep) {
+      expect_status(sfft_apply_multi(2, ps, xs, ys, nr, mw, mb, st), SFFT_OK, "apply multi");
+      HIPC(hipStreamSynchronize(st));
+      expect(download(y2, vb) == ref, "multi agrees");
+    }
+    expect(sfft_batch_last_form() == 0 || sfft_batch_last_form() == 1, "batch form");
+    void* ys_alias[2] = {y2, (void*)x2};
+    expect_status(sfft_apply_multi(2, ps, xs, ys_alias, nr, mw, mb, st), SFFT_INVALID_ARG, "multi aliasing");
+    size_t w0 = 0, w1 = 0;
+    sfft_workspace_size(p, nrhs, &w0);
+    sfft_workspace_size(q, 1, &w1);
+    void *e0 = nullptr, *e1 = nullptr;
+    HIPC(hipMalloc(&e0, w0 ? w0 : 1));
+    HIPC(hipMalloc(&e1, w1 ? w1 : 1));
+    void* wss[2] = {e0, e1};
+    const size_t wsb[2] = {w0, w1};
+    sfft_status each[2];
+    expect_status(sfft_apply_each(2, ps, xs, ys, nr, wss, wsb, st, each), SFFT_OK, "apply each");
+    HIPC(hipStreamSynchronize(st));
+    expect(each[0] == SFFT_OK && each[1] == SFFT_OK, "each status");
+    expect(download(y2, vb) == ref, "each agrees");
+    HIPC(hipFree(e0));
+    HIPC(hipFree(e1));
+    HIPC(hipFree(mw));
+  }
+
+  // autotuner with a cache holding malformed lines for this plan's key
+  {
+    const char* path = "/tmp/sfft_host_check_tune.jsonl";
+    setenv("SFFT_TUNE_CACHE", path, 1);
+    hipDeviceProp_t prop;
+    HIPC(hipGetDeviceProperties(&prop, 0));
+    const std::string key = std::string(prop.gcnArchName) + "|split|c64|b3|12x10x16|nrhs2|mirror0";
+    std::ofstream f(path, std::ios::trunc);
+    f << "not json at all\n";
+    f << "{\"key\": \"" << key << "\", \"sched\": \n";
+    f << "{\"key\": \"" << key << "\", \"sched\": 99, \"rb\": 2}\n";
+    f << "{\"key\": \"" << key << "\", \"sched\": 2, \"rb\": 4, \"tiles\": \"0122222222222222222222\", \"us\": 1}\n";
+    f << "{\"key\": \"" << key << "\", \"sched\": 3, \"rb\": 2, \"tiles\": \"1x\"}\n";
+    f.close();
+    double us = 0;
+    expect_status(sfft_plan_autotune(p, nrhs, 1, st, &us), SFFT_OK, "autotune from cache");
+    expect(us == -1.0, "cache answered");
+    expect_status(sfft_plan_info(p, &info), SFFT_OK, "info after tune");
+    expect(info.schedule == SFFT_SCHED_SLAB, "cached schedule");
+    expect_status(sfft_plan_autotune(p, nrhs, 0, st, &us), SFFT_OK, "autotune timed");
+    expect(us > 0, "timed autotune");
+    expect_status(sfft_apply(p, x, y2, nrhs, nullptr, 0, st), SFFT_OK, "apply after tune");
+    HIPC(hipStreamSynchronize(st));
+    expect(download(y2, vb) == ref, "tuned plan agrees");
+    std::remove(path);
+  }
+
+  // update with the same coefficients keeps the product; other block symmetry is refused
+  expect_status(sfft_plan_update(p, pr.coeffs, st), SFFT_OK, "update");
+  expect_status(sfft_apply(p, x, y2, nrhs, nullptr, 0, st), SFFT_OK, "apply after update");
+  HIPC(hipStreamSynchronize(st));
+  expect(download(y2, vb) == ref, "update agrees");
+
+  // profiling hooks
+  expect_status(sfft_profile_enable(p, 0xF), SFFT_OK, "profile enable");
+  expect_status(sfft_apply(p, x, y2, nrhs, nullptr, 0, st), SFFT_OK, "profiled apply");
+  HIPC(hipStreamSynchronize(st));
+  double ms = 0;
+  int64_t launches = 0;
+  expect_status(sfft_profile_read(p, 1, &ms, &launches, 1), SFFT_OK, "profile read");
+  expect(launches > 0 && ms > 0, "leaf launches profiled");
+  expect_status(sfft_profile_enable(p, 0), SFFT_OK, "profile off");
+
+  // GMRES with complex64 products and FP64 residuals
+  {
+    sfft_plan lo = nullptr, hi = nullptr;
+    Problem g = make_problem({8, 6, 10}, 3, 13);
+    expect_status(sfft_plan_create(&lo, 3, g.n.data(), 3, g.coeffs, SFFT_C64, SFFT_SPLIT, nullptr, 1, 0, st), SFFT_OK,
+                  "gmres lo");
+    expect_status(sfft_plan_create(&hi, 3, g.n.data(), 3, g.coeffs, SFFT_C128, SFFT_SPLIT, nullptr, 1, 0, st),
+                  SFFT_OK, "gmres hi");
+    const size_t gb = (size_t)(3 * g.s) * 16;
+    std::vector<std::complex<double>> chi_h((size_t)(3 * g.s), {0.002, 0.0}), rhs_h((size_t)(3 * g.s));
+    Rng r{17};
+    for (auto& z : rhs_h) z = {r.next(), r.next()};
+    void *chi, *rhs, *xs;
+    HIPC(hipMalloc(&chi, gb));
+    HIPC(hipMalloc(&rhs, gb));
+    HIPC(hipMalloc(&xs, gb));
+    HIPC(hipMemcpy(chi, chi_h.data(), gb, hipMemcpyHostToDevice));
+    HIPC(hipMemcpy(rhs, rhs_h.data(), gb, hipMemcpyHostToDevice));
+    HIPC(hipMemset(xs, 0, gb));
+    size_t wb = 0;
+    expect_status(sfft_gmres_workspace_size(lo, hi, 10, &wb), SFFT_OK, "gmres size");
+    void* gw = nullptr;
+    HIPC(hipMalloc(&gw, wb));
+    sfft_gmres_info gi;
+    expect_status(sfft_gmres_solve(lo, hi, chi, rhs, xs, 10, 20, 1e-8, gw, wb, st, &gi), SFFT_OK, "gmres");
+    expect(gi.converged == 1 && gi.rel_residual <= 1e-8, "gmres converged");
+    expect_status(sfft_gmres_solve(lo, hi, chi, rhs, xs, 10, 20, 1e-8, gw, wb - 1, st, &gi), SFFT_INVALID_ARG,
+                  "gmres short workspace");
+    HIPC(hipFree(gw));
+    HIPC(hipFree(chi));
+    HIPC(hipFree(rhs));
+    HIPC(hipFree(xs));
+    HIPC(hipFree(g.coeffs));
+    sfft_plan_destroy(lo);
+    sfft_plan_destroy(hi);
+  }
+
+  for (auto pl : plans) expect_status(sfft_plan_destroy(pl), SFFT_OK, "destroy");
+  expect_status(sfft_plan_destroy(q), SFFT_OK, "destroy second");
+  HIPC(hipFree(x));
+  HIPC(hipFree(y));
+  HIPC(hipFree(y2));
+  HIPC(hipFree(x2));
+  HIPC(hipFree(yq));
+  HIPC(hipFree(pr.coeffs));
+  HIPC(hipFree(pr2.coeffs));
+  HIPC(hipStreamDestroy(st));
+}
+
+}  // namespace
+
+int main(int argc, char** argv) {
+  const std::string mode = argc > 1 ? argv[1] : "host";
+  host_only();
+  if (mode == "gpu") gpu_checks();
+  if (g_fail) {
+    std::fprintf(stderr, "%d check(s) failed\n", g_fail);
+    return 1;
+  }
+  std::printf("host check ok (%s)\n", mode.c_str());
+  return 0;
+}
