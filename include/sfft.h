@@ -193,11 +193,15 @@ sfft_status sfft_apply_noalloc(sfft_plan plan, const void* x, void* y, int64_t n
  *      2..d depth-first there (the plan's symbols stay on the device), back;
  *   3. column slabs of both children to the device, level-1 inverse pass and
  *      merge, y back to the host.
- * The device holds the plan and slabs only. Results equal sfft_apply's
- * depth-first product bit for bit (same kernels, same per-pencil work).
+ * The device holds the plan and slabs only. When the budget holds two slab
+ * buffers, consecutive slabs alternate between them on `stream` and an
+ * internal stream, so one slab's copies overlap the other's kernels. Results
+ * equal sfft_apply's depth-first product bit for bit (same kernels, same
+ * per-pencil work).
  *   x_host, y_host  host (nrhs, b, n...) of the plan dtype, preferably pinned
  *                   (hipHostMalloc) so the copies run asynchronously.
- *   host_ws         host, 2 * nrhs * b * prod(n) entries: the two children.
+ *   host_ws         host, 2 * nrhs * b * prod(n) entries: the two children
+ *                   (pinned too, preferably).
  *   device_ws       device, its size is the budget: sfft_ooc_sizes tells the
  *                   bytes a budget actually uses (SFFT_INVALID_ARG when one
  *                   slab does not fit).

@@ -1147,10 +1147,37 @@ struct OocGeom {
   int64_t nv, inner, rowlen;  // vectors, columns per level-1 index, entries per (vector, j_1)
   int64_t w;                  // columns per slab of steps 1 and 3
   int64_t c;                  // level-1 indices per slab of step 2
-  size_t dev_bytes;           // device workspace used
+  size_t dev_bytes;           // device workspace used (all buffers)
+  int nbuf;                   // slab buffers: 2 when the budget holds two (copies overlap kernels)
+  size_t buf_bytes;           // bytes of one buffer
 };
 
+sfft_status ooc_geometry_one(const sfft_plan_s* p, int64_t nrhs, size_t budget, OocGeom* g);
+
+// Two slab buffers when they fit, so one slab's copies overlap the other's
+// kernels; else one buffer. A buffer takes half the budget, at most an eighth
+// of the vectors' bytes (but 64 MiB at least): with several slabs per step the
+// copies and kernels keep overlapping (at 256x256x128 with 8 right-hand sides,
+// 194 ms per product with 0.4 GB buffers, 242 ms with 3.2 GB ones).
 sfft_status ooc_geometry(const sfft_plan_s* p, int64_t nrhs, size_t budget, OocGeom* g) {
+  const size_t vbytes = (size_t)vec_elems(p, nrhs) * p->esz;
+  const size_t cap = vbytes / 8 > ((size_t)64 << 20) ? vbytes / 8 : ((size_t)64 << 20);
+  size_t half = budget / 2 < cap ? budget / 2 : cap;
+  half = half / 256 * 256;  // each buffer 256-byte aligned inside the budget
+  if (half > 0 && ooc_geometry_one(p, nrhs, half, g) == SFFT_OK) {
+    g->nbuf = 2;
+    g->buf_bytes = (g->dev_bytes + 255) / 256 * 256;
+    g->dev_bytes = 2 * g->buf_bytes;
+    return SFFT_OK;
+  }
+  sfft_status s = ooc_geometry_one(p, nrhs, budget, g);
+  if (s != SFFT_OK) return s;
+  g->nbuf = 1;
+  g->buf_bytes = g->dev_bytes;
+  return SFFT_OK;
+}
+
+sfft_status ooc_geometry_one(const sfft_plan_s* p, int64_t nrhs, size_t budget, OocGeom* g) {
   if (p->method != SFFT_SPLIT) return fail(SFFT_UNSUPPORTED, "out-of-core apply needs a split plan");
   if (p->d < 2) return fail(SFFT_UNSUPPORTED, "out-of-core apply needs at least two levels");
   const int64_t esz = (int64_t)p->esz;
@@ -1192,15 +1219,45 @@ sfft_status apply_ooc(sfft_plan_s* p, const void* xh, void* yh, int64_t nrhs, vo
   const int64_t L0 = p->L[0];
   const size_t V = (size_t)g.nv * p->s;  // entries of all nrhs vectors
   char* child[2] = {(char*)host_ws, (char*)host_ws + V * esz};
-  char* dev = (char*)dev_ws;
-  sfft_status s;
+  // slabs alternate between the buffers and streams: slab i uses buffer
+  // i % nbuf on `st` (even i) or a second stream (odd i); a step's slabs are
+  // independent, so the next slab's copies run beside this one's kernels, and
+  // both streams join before the next step reads what this one wrote
+  hipStream_t ss[2] = {st, nullptr};
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  if (g.nbuf == 2) {
+    HIP_TRY(hipStreamCreateWithFlags(&ss[1], hipStreamNonBlocking), "out-of-core stream");
+    hipError_t e = hipEventCreateWithFlags(&ev[0], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev[1], hipEventDisableTiming);
+    if (e != hipSuccess) {
+      for (auto x : ev)
+        if (x) (void)hipEventDestroy(x);
+      (void)hipStreamDestroy(ss[1]);
+      return hip_fail(e, "out-of-core events");
+    }
+  }
+  auto fork = [&]() -> hipError_t {  // the second stream waits for st's work so far
+    if (g.nbuf < 2) return hipSuccess;
+    hipError_t e = hipEventRecord(ev[0], st);
+    return e == hipSuccess ? hipStreamWaitEvent(ss[1], ev[0], 0) : e;
+  };
+  auto join = [&]() -> hipError_t {  // st waits for the second stream's slabs
+    if (g.nbuf < 2) return hipSuccess;
+    hipError_t e = hipEventRecord(ev[1], ss[1]);
+    return e == hipSuccess ? hipStreamWaitEvent(st, ev[1], 0) : e;
+  };
+  sfft_status s = SFFT_OK;
   // steps 1 and 3: column slabs [i0, i0 + w) of every (vector, level-1 index) row
   auto column_pass = [&](int mode) -> sfft_status {
     const size_t slab = (size_t)g.nv * L0 * g.w;
-    char* A = dev;
-    char* B = dev + slab * esz;
-    char* Cc = dev + 2 * slab * esz;
-    for (int64_t i0 = 0; i0 < g.inner; i0 += g.w) {
+    int64_t k = 0;
+    for (int64_t i0 = 0; i0 < g.inner; i0 += g.w, ++k) {
+      const int b = (int)(k % g.nbuf);
+      hipStream_t sk = ss[b];
+      char* dev = (char*)dev_ws + (size_t)b * g.buf_bytes;
+      char* A = dev;
+      char* B = dev + slab * esz;
+      char* Cc = dev + 2 * slab * esz;
       const int64_t ww = g.inner - i0 < g.w ? g.inner - i0 : g.w;
       const size_t hp = (size_t)g.inner * esz, dp = (size_t)ww * esz, wid = (size_t)ww * esz;
       const size_t rows = (size_t)g.nv * L0;
@@ -1209,44 +1266,72 @@ sfft_status apply_ooc(sfft_plan_s* p, const void* xh, void* yh, int64_t nrhs, vo
       a.nq = 1;
       a.use_phase = 1;
       if (mode == 0) {
-        HIP_TRY(copy2d(A, dp, (const char*)xh + i0 * esz, hp, wid, rows, hipMemcpyHostToDevice, st), "x slab");
+        HIP_TRY(copy2d(A, dp, (const char*)xh + i0 * esz, hp, wid, rows, hipMemcpyHostToDevice, sk), "x slab");
         a.in = A;
         a.out = B;
         a.out1 = Cc;
-        if ((s = run_pass(p, 0, 0, a, st)) != SFFT_OK) return s;
-        HIP_TRY(copy2d(child[0] + i0 * esz, hp, B, dp, wid, rows, hipMemcpyDeviceToHost, st), "even slab");
-        HIP_TRY(copy2d(child[1] + i0 * esz, hp, Cc, dp, wid, rows, hipMemcpyDeviceToHost, st), "odd slab");
+        if ((s = run_pass(p, 0, 0, a, sk)) != SFFT_OK) return s;
+        HIP_TRY(copy2d(child[0] + i0 * esz, hp, B, dp, wid, rows, hipMemcpyDeviceToHost, sk), "even slab");
+        HIP_TRY(copy2d(child[1] + i0 * esz, hp, Cc, dp, wid, rows, hipMemcpyDeviceToHost, sk), "odd slab");
       } else {
-        HIP_TRY(copy2d(A, dp, child[0] + i0 * esz, hp, wid, rows, hipMemcpyHostToDevice, st), "even slab");
-        HIP_TRY(copy2d(B, dp, child[1] + i0 * esz, hp, wid, rows, hipMemcpyHostToDevice, st), "odd slab");
+        HIP_TRY(copy2d(A, dp, child[0] + i0 * esz, hp, wid, rows, hipMemcpyHostToDevice, sk), "even slab");
+        HIP_TRY(copy2d(B, dp, child[1] + i0 * esz, hp, wid, rows, hipMemcpyHostToDevice, sk), "odd slab");
         a.in = A;
         a.in1 = B;
         a.out = Cc;
-        if ((s = run_pass(p, 0, 1, a, st)) != SFFT_OK) return s;
-        HIP_TRY(copy2d((char*)yh + i0 * esz, hp, Cc, dp, wid, rows, hipMemcpyDeviceToHost, st), "y slab");
+        if ((s = run_pass(p, 0, 1, a, sk)) != SFFT_OK) return s;
+        HIP_TRY(copy2d((char*)yh + i0 * esz, hp, Cc, dp, wid, rows, hipMemcpyDeviceToHost, sk), "y slab");
       }
     }
     return SFFT_OK;
   };
-  if ((s = column_pass(0)) != SFFT_OK) return s;
   // step 2: row slabs of each child through levels 2..d
-  const int64_t pen_per_row = p->npen / L0;
-  for (int c1 = 0; c1 < 2; ++c1) {
-    for (int64_t j0 = 0; j0 < L0; j0 += g.c) {
-      const int64_t cc = L0 - j0 < g.c ? L0 - j0 : g.c;
-      const size_t hp = (size_t)p->s * esz, wid = (size_t)cc * g.rowlen * esz;
-      char* S = dev;
-      char* ws = dev + (size_t)g.nv * cc * g.rowlen * esz;
-      HIP_TRY(copy2d(S, wid, child[c1] + (size_t)j0 * g.rowlen * esz, hp, wid, g.nv, hipMemcpyHostToDevice, st),
-              "child slab in");
-      const Slab sl{cc, j0 * pen_per_row, cc * pen_per_row, 1};
-      if ((s = split_depth(p, 1, S, S, c1, nrhs, ws, st, false, sl)) != SFFT_OK) return s;
-      HIP_TRY(copy2d(child[c1] + (size_t)j0 * g.rowlen * esz, hp, S, wid, wid, g.nv, hipMemcpyDeviceToHost, st),
-              "child slab out");
+  auto row_pass = [&]() -> sfft_status {
+    const int64_t pen_per_row = p->npen / L0;
+    int64_t k = 0;
+    for (int c1 = 0; c1 < 2; ++c1) {
+      for (int64_t j0 = 0; j0 < L0; j0 += g.c, ++k) {
+        const int b = (int)(k % g.nbuf);
+        hipStream_t sk = ss[b];
+        char* dev = (char*)dev_ws + (size_t)b * g.buf_bytes;
+        const int64_t cc = L0 - j0 < g.c ? L0 - j0 : g.c;
+        const size_t hp = (size_t)p->s * esz, wid = (size_t)cc * g.rowlen * esz;
+        char* S = dev;
+        char* ws = dev + (size_t)g.nv * cc * g.rowlen * esz;
+        HIP_TRY(copy2d(S, wid, child[c1] + (size_t)j0 * g.rowlen * esz, hp, wid, g.nv, hipMemcpyHostToDevice, sk),
+                "child slab in");
+        const Slab sl{cc, j0 * pen_per_row, cc * pen_per_row, 1};
+        if ((s = split_depth(p, 1, S, S, c1, nrhs, ws, sk, false, sl)) != SFFT_OK) return s;
+        HIP_TRY(copy2d(child[c1] + (size_t)j0 * g.rowlen * esz, hp, S, wid, wid, g.nv, hipMemcpyDeviceToHost, sk),
+                "child slab out");
+      }
     }
+    return SFFT_OK;
+  };
+  auto run = [&]() -> sfft_status {
+    HIP_TRY(fork(), "out-of-core fork");
+    if ((s = column_pass(0)) != SFFT_OK) return s;
+    HIP_TRY(join(), "out-of-core join");
+    HIP_TRY(fork(), "out-of-core fork");
+    if ((s = row_pass()) != SFFT_OK) return s;
+    HIP_TRY(join(), "out-of-core join");
+    HIP_TRY(fork(), "out-of-core fork");
+    if ((s = column_pass(1)) != SFFT_OK) return s;
+    HIP_TRY(join(), "out-of-core join");
+    return SFFT_OK;
+  };
+  s = run();
+  // both streams drain before the buffers, events and stream go away
+  hipError_t e = hipStreamSynchronize(st);
+  if (ss[1]) {
+    const hipError_t e1 = hipStreamSynchronize(ss[1]);
+    if (e == hipSuccess) e = e1;
+    (void)hipStreamDestroy(ss[1]);
   }
-  if ((s = column_pass(1)) != SFFT_OK) return s;
-  HIP_TRY(hipStreamSynchronize(st), "out-of-core apply");
+  for (auto x : ev)
+    if (x) (void)hipEventDestroy(x);
+  if (s != SFFT_OK) return s;
+  if (e != hipSuccess) return hip_fail(e, "out-of-core apply");
   return SFFT_OK;
 }
 
