@@ -137,7 +137,8 @@ def pmc_probe(workload="green64"):
             log(f"pmc probe: {'mirrored' if parity is not None else 'general'} symbols done")
         return
     coeffs, x_host = wl.green_64(1)
-    plan = sf.Plan(wl.GREEN_64["n"], 3, torch.from_numpy(coeffs).cuda(), dtype="c64", method="split")
+    plan = sf.Plan(wl.GREEN_64["n"], 3, torch.from_numpy(coeffs).cuda(), dtype="c64", method="split",
+                   schedule="breadth")  # the 64^3 workload's schedule
     x = torch.from_numpy(x_host).to(torch.complex64).cuda()
     y = torch.empty_like(x)
     ws = plan.alloc_workspace(1)
@@ -766,6 +767,10 @@ def bench_green64(args):
     s = math.prod(n)
     d = len(n)
 
+    # breadth-first by default here: at 64^3 with one right-hand side it is the
+    # autotuner's choice (fewer, larger launches), and the counters in
+    # profiles/leaf_pmc_traffic.* are taken on it
+    sched64 = "breadth" if args.schedule == "auto" else args.schedule
     results = {}
     outputs = {}
     variants = [("split", "c64"), ("split", "c128"), ("embed", "c64"), ("embed", "c128"),
@@ -784,7 +789,7 @@ def bench_green64(args):
         if vmethod == "split_all9":
             os.environ["SFFT_NO_BLOCK_SYMMETRY"] = "1"
         plan = sf.Plan(n, b, coeffs_d, dtype=dtype, method=method, max_nrhs=nrhs,
-                       schedule=args.schedule, parity=parity)
+                       schedule=sched64, parity=parity)
         os.environ.pop("SFFT_NO_BLOCK_SYMMETRY", None)
         info = plan.info()
         x = torch.from_numpy(x_host).to(tdt).cuda()
@@ -815,7 +820,7 @@ def bench_green64(args):
         # context: the same operator on 8 right-hand sides per apply (the leaf
         # fetches each symbol block once for the right-hand sides of a workgroup)
         x8 = torch.from_numpy(wl.vectors(203, n, b, 8).astype(np.complex64)).cuda()
-        plan = sf.Plan(n, b, coeffs_d, dtype="c64", method="split", max_nrhs=8, schedule=args.schedule)
+        plan = sf.Plan(n, b, coeffs_d, dtype="c64", method="split", max_nrhs=8, schedule=sched64)
         y8 = torch.empty_like(x8)
         ws8 = plan.alloc_workspace(8)
         ms8, _ = time_plan(plan, x8, y8, ws8, max(args.steps // 4, 10), args.warmup)
@@ -827,8 +832,10 @@ def bench_green64(args):
 
     (leaf_ms, leaf_cnt), info, vbytes, ms = headline_leaf
     leaf_avg_s = leaf_ms / max(leaf_cnt, 1) * 1e-3
-    nbr = 2 ** (d - 1)  # leaf launch: every branch prefix of levels 1..d-1
-    leaf_alg_bytes = 2 * nbr * vbytes + info["symbol_bytes"]
+    # a breadth-first leaf launch takes every branch prefix of levels 1..d-1,
+    # a depth-first one a single branch (and the symbols of that branch)
+    nbr = 2 ** (d - 1) if info["schedule"] == 1 else 1
+    leaf_alg_bytes = 2 * nbr * vbytes + info["symbol_bytes"] * nbr // 2 ** (d - 1)
     achieved = leaf_alg_bytes / leaf_avg_s / 1e9
     leaf_kernel = f"sfft::k_leaf<float, 64, 3, 2, false, {info['block_symmetry']}>"
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
