@@ -429,6 +429,7 @@ def bench_large(args):
             if head:
                 headline = dict(ms=ms, leaf=leaf, info=info)
                 y_c64 = y.clone()
+                r["device_shares"] = time_shares(plan, x, y, nrhs, max(10, args.steps // 2))
             results[key] = r
             log(f"[{key}] {ms:.3f} ms per apply ({r['matvecs_per_s']:.0f} matvecs/s), "
                 f"sampled rel L2 {rel[key]:.2e}, device bytes {r['measured_device_bytes'] / 1e9:.2f} GB")
@@ -671,6 +672,35 @@ def time_plan(plan, x, y, ws, steps, warmup, profile_leaf=False):
     t1 = time.perf_counter()
     leaf = plan.profile_read("leaf", reset=True) if profile_leaf else None
     return (t1 - t0) * 1e3 / steps, leaf
+
+
+def time_shares(plan, x, y, nrhs, reps):
+    """One device's share of the product when it is split over 2^k devices by
+    branch (Plan.apply_subtree, k = 1 and 2; the shares sum to T x): mean time
+    per share (ms, wall clock over reps calls after two warm-up calls) for the
+    first and the last branch prefix, and the share's workspace. The
+    cross-device sum of the shares is not part of it."""
+    import torch
+    out = {"note": "ms per share of all right-hand sides (apply_subtree); k levels split across 2^k devices; "
+                   "the sum-reduce across devices is not included"}
+    for k in (1, 2):
+        nb = plan.workspace_size_subtree(k, nrhs)
+        ws = torch.empty(nb, dtype=torch.uint8, device="cuda") if nb else None
+        times = []
+        for prefix in (0, (1 << k) - 1):
+            for _ in range(2):
+                plan.apply_subtree(k, prefix, x, y, workspace=ws)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                plan.apply_subtree(k, prefix, x, y, workspace=ws)
+            torch.cuda.synchronize()
+            times.append(round((time.perf_counter() - t0) * 1e3 / reps, 4))
+        out[f"k{k}"] = {"ms_per_share": {"prefix_0": times[0], f"prefix_{(1 << k) - 1}": times[1]},
+                        "workspace_bytes": nb}
+        log(f"[shares] k={k}: {times[0]:.3f} / {times[1]:.3f} ms per share (first / last prefix)")
+        del ws
+    return out
 
 
 def apply_latencies(plan, x, y, ws, reps, scrub_bytes=0, pct=(10, 50, 90)):

@@ -212,6 +212,26 @@ sfft_status sfft_ooc_sizes(sfft_plan plan, int64_t nrhs, size_t device_budget, s
 sfft_status sfft_apply_ooc(sfft_plan plan, const void* x_host, void* y_host, int64_t nrhs, void* host_ws,
                            size_t host_ws_bytes, void* device_ws, size_t device_ws_bytes, void* stream);
 
+/* One device's share of a product split over 2^k devices by branch. After
+ * the splits of levels 1..k the 2^k branches are independent (Section II's
+ * opening remarks on several devices: by linearity a branch may run on to a
+ * chosen termination point instead of merging): the share of branch `prefix`
+ * forms, along each level
+ * l <= k, only the child whose parity is bit l-1 of prefix, runs the subtree
+ * below level k depth-first, and merges back along levels k..1 with that child
+ * alone. The 2^k shares of one x sum to T x (one sum-reduce of y across
+ * devices). k = 0 is the whole depth-first product.
+ *   k          0 <= k <= d - 1 (the plan's d, levels of size 1 dropped).
+ *   prefix     < 2^k; bit l-1 is the parity along level l.
+ *   x, y       device (nrhs, b, n...) of the plan dtype; y must not overlap x.
+ *   workspace  device, at least sfft_workspace_size_subtree bytes
+ *              ((d - 1 - k) vectors), caller owned, not NULL when that is > 0.
+ * Split plans only (SFFT_UNSUPPORTED for the embedding baseline); general and
+ * mirrored symbols. Asynchronous on `stream`; allocates nothing. */
+sfft_status sfft_workspace_size_subtree(sfft_plan plan, int k, int64_t nrhs, size_t* bytes);
+sfft_status sfft_apply_subtree(sfft_plan plan, int k, uint32_t prefix, const void* x, void* y, int64_t nrhs,
+                               void* workspace, size_t ws_bytes, void* stream);
+
 /* The conjugate transpose, y = T^H x: T^H is block Toeplitz with generator
  * t^H(r) = t(-r)^H, whose embedded symbol is the conjugate transpose of T's at
  * every bin (Section II's embedding with the generator reversed), so the

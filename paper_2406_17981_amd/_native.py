@@ -29,6 +29,7 @@ EXPORTS = [
     "sfft_plan_autotune", "sfft_arnoldi_scratch_size", "sfft_arnoldi_step_multi", "sfft_plan_update",
     "sfft_plan_enable_adjoint", "sfft_apply_adjoint", "sfft_gmres_workspace_size", "sfft_gmres_solve",
     "sfft_apply_noalloc", "sfft_apply_each", "sfft_ooc_sizes", "sfft_apply_ooc", "sfft_batch_last_form",
+    "sfft_workspace_size_subtree", "sfft_apply_subtree",
 ]
 KIND_FORWARD, KIND_LEAF, KIND_INVERSE, KIND_COPY = range(4)
 
@@ -82,6 +83,8 @@ def _load():
     lib.sfft_plan_enable_adjoint.argtypes = [vp, vp]
     lib.sfft_apply_adjoint.argtypes = [vp, vp, vp, i64, vp, sz, vp]
     lib.sfft_apply_noalloc.argtypes = [vp, vp, vp, i64, vp]
+    lib.sfft_workspace_size_subtree.argtypes = [vp, C.c_int, i64, C.POINTER(sz)]
+    lib.sfft_apply_subtree.argtypes = [vp, C.c_int, C.c_uint32, vp, vp, i64, vp, sz, vp]
     lib.sfft_ooc_sizes.argtypes = [vp, i64, sz, C.POINTER(sz), C.POINTER(sz)]
     lib.sfft_apply_ooc.argtypes = [vp, vp, vp, i64, vp, sz, vp, sz, vp]
     lib.sfft_apply_each.argtypes = [C.c_int, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), P64, C.POINTER(vp),

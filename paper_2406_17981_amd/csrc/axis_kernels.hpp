@@ -12,6 +12,8 @@
 //   INV2  (Algorithm 1 iFFT_l + mrgBrn fused, unnormalised, the 1/2 and 1/L
 //         factors live in the symbols):
 //         out = iFFT_L(in) + conj(Phi) .* iFFT_L(in1)      (in1 may be absent)
+//         or, with in_odd set and no in1, out = conj(Phi) .* iFFT_L(in)
+//         (one device's share of a product split over devices by branch)
 //   LEAF  (innermost level: FFT, mulBrn, iFFT and the last merge fused):
 //         out[a] = sum_p conj(Phi)^p .* iFFT_L( sum_c S_p[a, c] .* FFT_L(Phi^p .* in[c]) )
 //         with p over {0, 1} (split) or {0} (embedding baseline).
@@ -66,6 +68,7 @@ struct PassArgs {
   const void* tw;    // 2L entries exp(-i pi m / L)
   int64_t len;       // pencil length L (read by the runtime-length kernels only)
   int use_phase;     // FWD2/INV2: multiply the odd child by Phi / conj(Phi)
+  int in_odd;        // INV2 without in1: in is the odd child (out = conj(Phi) .* iFFT(in))
   int tile_mode;     // strided passes: 0 width by rule, 1 full-size, 2 half-size workgroups
   // LEAF only
   const void* sym;   // symbols for branch q at sym + q*sym_bs
@@ -314,6 +317,9 @@ __device__ __forceinline__ void strided_body(const PassArgs& a, uint32_t bid) {
       fft_pencil<+1, Sh>(w, lp, W, t, lt);
 #pragma unroll
       for (int m = 0; m < E; ++m) h[m] = cadd(h[m], a.use_phase ? cmulc(w[m], phase(m)) : w[m]);
+    } else if (a.in_odd) {
+#pragma unroll
+      for (int m = 0; m < E; ++m) h[m] = cmulc(h[m], phase(m));
     }
     if (act) {
       C* out = (C*)a.out + q * a.out_bs + base;
@@ -440,6 +446,9 @@ __global__ void __launch_bounds__(256) k_contig(PassArgs a) {
       fft_pencil<+1, Sh, G::WS>(w, lp, 1, t, lt);
 #pragma unroll
       for (int m = 0; m < E; ++m) h[m] = cadd(h[m], a.use_phase ? cmulc(w[m], phase(m)) : w[m]);
+    } else if (a.in_odd) {
+#pragma unroll
+      for (int m = 0; m < E; ++m) h[m] = cmulc(h[m], phase(m));
     }
     store_home<C, L, T, E, P, NT>((C*)a.out + q * a.out_bs + p0 * L, lds, h, g, t, nh, tid);
   }

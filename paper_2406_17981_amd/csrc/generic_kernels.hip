@@ -110,7 +110,8 @@ __device__ C* gen_fft(C* a, C* b, const GenPlan& g, int L, int ncols, const C* t
 // axis (outer, L, inner) as in the length-specialised passes.
 //   MODE 0 (FWD2): out1 = FFT(Phi .* in) first (out1 must not alias in), then
 //                  out = FFT(in) (out may alias in).
-//   MODE 1 (INV2): out = iFFT(in) + conj(Phi) .* iFFT(in1)  (in1 may be absent).
+//   MODE 1 (INV2): out = iFFT(in) + conj(Phi) .* iFFT(in1)  (in1 may be absent;
+//                  without it, in_odd makes out = conj(Phi) .* iFFT(in)).
 template <typename Real, int MODE>
 __global__ void __launch_bounds__(256) k_gen_pass(PassArgs a, GenPlan g) {
   using C = cx<Real>;
@@ -184,6 +185,9 @@ __global__ void __launch_bounds__(256) k_gen_pass(PassArgs a, GenPlan g) {
         const int k = idx % L;
         r1[idx] = cadd(r1[idx], a.use_phase ? cmulc(r2[idx], tw[k]) : r2[idx]);
       }
+      __syncthreads();
+    } else if (a.in_odd) {
+      for (int idx = threadIdx.x; idx < W * L; idx += blockDim.x) r1[idx] = cmulc(r1[idx], tw[idx % L]);
       __syncthreads();
     }
     store((C*)a.out + q * a.out_bs, r1);

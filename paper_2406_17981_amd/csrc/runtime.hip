@@ -667,6 +667,39 @@ sfft_status split_depth(const sfft_plan_s* p, int l, const void* src, void* dst,
   return run_pass(p, l, 1, b, st);
 }
 
+// One device's share when the product is split over 2^k devices by branch
+// (after the splits of levels 1..k the branches are independent; Section II
+// remarks that by linearity a branch may run on to a chosen termination
+// point): along levels l < k only the child whose parity is bit l of prefix is
+// formed and, on the way back, merged alone (the even child's inverse, or
+// conj(Phi) times the odd child's); the subtree below level k runs
+// depth-first with its odd children in workspace vectors 0 .. d-2-k. The
+// 2^k shares sum to T x.
+sfft_status split_prefix(const sfft_plan_s* p, int l, int k, uint32_t prefix, const void* src, void* dst,
+                         int64_t q, int64_t nrhs, char* ws, hipStream_t st) {
+  if (l == k) return split_depth(p, l, src, dst, q, nrhs, ws, st, false, Slab{p->L[0], 0, p->npen, k});
+  const int par = (int)((prefix >> l) & 1u);
+  const int64_t nv = nrhs * p->b;
+  PassArgs a = base_args(p, l, nv, p->L[0]);
+  a.in = src;
+  a.out = par ? nullptr : dst;
+  a.out1 = par ? dst : nullptr;
+  a.use_phase = 1;
+  sfft_status s = run_pass(p, l, 0, a, st);
+  if (s != SFFT_OK) return s;
+  if ((s = split_prefix(p, l + 1, k, prefix, dst, dst, 2 * q + par, nrhs, ws, st)) != SFFT_OK) return s;
+  PassArgs b = base_args(p, l, nv, p->L[0]);
+  b.in = dst;
+  b.out = dst;
+  b.use_phase = 1;
+  b.in_odd = par;
+  return run_pass(p, l, 1, b, st);
+}
+
+size_t subtree_workspace_elems(const sfft_plan_s* p, int k, int64_t nrhs) {
+  return (size_t)((p->d - 1 - k) * vec_elems(p, nrhs));
+}
+
 // Slab schedule (d >= 3): level 1 over whole vectors; then, for each child
 // and each slab of cc consecutive level-1 indices, the level-2 forward pass
 // reads the slab straight from the child (one branch per vector, stride one
@@ -1613,6 +1646,34 @@ sfft_status sfft_apply_ooc(sfft_plan plan, const void* x_host, void* y_host, int
       ranges_overlap(host_ws, 2 * vb, y_host, vb))
     return fail(SFFT_INVALID_ARG, "x, y and the host workspace must not overlap");
   return apply_ooc(plan, x_host, y_host, nrhs, host_ws, device_ws, g, (hipStream_t)stream);
+}
+
+sfft_status sfft_workspace_size_subtree(sfft_plan plan, int k, int64_t nrhs, size_t* bytes) {
+  if (!plan || !bytes || nrhs < 0) return fail(SFFT_INVALID_ARG, "null plan/bytes or nrhs < 0");
+  if (k < 0 || k > plan->d - 1) return fail(SFFT_INVALID_ARG, "k must lie in [0, d - 1]");
+  *bytes = subtree_workspace_elems(plan, k, nrhs) * plan->esz;
+  return SFFT_OK;
+}
+
+sfft_status sfft_apply_subtree(sfft_plan plan, int k, uint32_t prefix, const void* x, void* y, int64_t nrhs,
+                               void* workspace, size_t ws_bytes, void* stream) {
+  if (!plan) return fail(SFFT_INVALID_ARG, "null plan");
+  if (plan->method != SFFT_SPLIT) return fail(SFFT_UNSUPPORTED, "subtree shares need a split plan");
+  if (k < 0 || k > plan->d - 1) return fail(SFFT_INVALID_ARG, "k must lie in [0, d - 1]");
+  if (k < 32 && (prefix >> k) != 0) return fail(SFFT_INVALID_ARG, "prefix must be below 2^k");
+  if (nrhs < 0) return fail(SFFT_INVALID_ARG, "nrhs must be >= 0");
+  if (nrhs == 0) return SFFT_OK;
+  if (!x || !y) return fail(SFFT_INVALID_ARG, "x and y must be non-null device pointers");
+  const size_t vbytes = (size_t)vec_elems(plan, nrhs) * plan->esz;
+  if (ranges_overlap(x, vbytes, y, vbytes)) return fail(SFFT_INVALID_ARG, "y must not overlap x");
+  const size_t need = subtree_workspace_elems(plan, k, nrhs) * plan->esz;
+  if (need > 0) {
+    if (!workspace || ws_bytes < need)
+      return fail(SFFT_INVALID_ARG, "workspace too small: need " + std::to_string(need) + " bytes");
+    if (ranges_overlap(workspace, need, x, vbytes) || ranges_overlap(workspace, need, y, vbytes))
+      return fail(SFFT_INVALID_ARG, "workspace overlaps x or y");
+  }
+  return split_prefix(plan, 0, k, prefix, x, y, 0, nrhs, (char*)workspace, (hipStream_t)stream);
 }
 
 sfft_status sfft_plan_enable_adjoint(sfft_plan plan, void* stream) {

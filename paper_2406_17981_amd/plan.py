@@ -136,6 +136,45 @@ class Plan:
 
     __call__ = apply
 
+    def workspace_size_subtree(self, k: int, nrhs: int) -> int:
+        out = C.c_size_t()
+        N.check(N.lib.sfft_workspace_size_subtree(self.handle, int(k), int(nrhs), C.byref(out)),
+                "sfft_workspace_size_subtree")
+        return int(out.value)
+
+    def apply_subtree(self, k: int, prefix: int, x: torch.Tensor, y: Optional[torch.Tensor] = None,
+                      workspace: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """One device's share of T x split over 2^k devices by branch: the
+        contribution of the branches whose parities along levels 1..k are the
+        bits of prefix (bit l-1 for level l; levels of size 1 do not count).
+        The 2^k shares sum to T x. workspace: workspace_size_subtree(k, nrhs)
+        bytes (allocated here when omitted)."""
+        _require_device(x, "x", self.torch_dtype)
+        squeeze = x.dim() == self.d + 1
+        xs = x.unsqueeze(0) if squeeze else x
+        if tuple(xs.shape[1:]) != (self.b,) + self.n:
+            raise ValueError(f"x shape {tuple(x.shape)} does not match b={self.b}, n={self.n}")
+        nrhs = xs.shape[0]
+        if y is None:
+            y = torch.empty_like(xs)
+        else:
+            _require_device(y, "y", self.torch_dtype)
+            if y.numel() != xs.numel():
+                raise ValueError("y has the wrong size")
+        if workspace is None:
+            nb = self.workspace_size_subtree(k, nrhs)
+            workspace = torch.empty(nb, dtype=torch.uint8, device="cuda") if nb else None
+        ws_ptr, ws_bytes = None, 0
+        if workspace is not None:
+            if not workspace.is_cuda or not workspace.is_contiguous():
+                raise ValueError("workspace must be a contiguous device tensor")
+            ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
+        st = N.lib.sfft_apply_subtree(self.handle, int(k), int(prefix), C.c_void_p(xs.data_ptr()),
+                                      C.c_void_p(y.data_ptr()), nrhs, C.c_void_p(ws_ptr) if ws_ptr else None,
+                                      ws_bytes, C.c_void_p(_stream_handle(stream)))
+        N.check(st, "sfft_apply_subtree")
+        return y.view(x.shape) if squeeze else y
+
     def ooc_sizes(self, nrhs: int, device_budget: int):
         """(host workspace bytes, device workspace bytes) of apply_ooc for a
         device budget (sfft_ooc_sizes)."""

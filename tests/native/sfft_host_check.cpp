@@ -91,6 +91,9 @@ void host_only() {
   expect_status(sfft_workspace_size_multi(1, nullptr, nullptr, &bytes), SFFT_INVALID_ARG, "null multi");
   expect_status(sfft_apply_multi(0, nullptr, nullptr, nullptr, nullptr, nullptr, 0, nullptr), SFFT_OK, "empty multi");
   expect_status(sfft_plan_destroy(nullptr), SFFT_INVALID_ARG, "destroy null");
+  expect_status(sfft_workspace_size_subtree(nullptr, 1, 1, &bytes), SFFT_INVALID_ARG, "null plan share size");
+  expect_status(sfft_apply_subtree(nullptr, 1, 0, fake, (void*)0x2000, 1, nullptr, 0, nullptr), SFFT_INVALID_ARG,
+                "null plan share");
   expect(sfft_batch_last_form() == -1, "no batch form yet");
 }
 
@@ -193,6 +196,29 @@ void gpu_checks() {
   expect_status(sfft_apply_adjoint(p, x, y2, nrhs, nullptr, 0, st), SFFT_OK, "adjoint");
   HIPC(hipStreamSynchronize(st));
   expect(finite_c64(download(y2, vb)), "finite adjoint");
+
+  // one device's share of a two-way split by branch: the shares sum to the product
+  {
+    size_t sw = 0;
+    expect_status(sfft_workspace_size_subtree(p, 1, nrhs, &sw), SFFT_OK, "share workspace size");
+    expect_status(sfft_workspace_size_subtree(p, 3, nrhs, &sw), SFFT_INVALID_ARG, "share k beyond d - 1");
+    expect_status(sfft_workspace_size_subtree(p, 1, nrhs, &sw), SFFT_OK, "share workspace size");
+    void* w = nullptr;
+    if (sw) HIPC(hipMalloc(&w, sw));
+    expect_status(sfft_apply_subtree(p, 1, 2, x, y2, nrhs, w, sw, st), SFFT_INVALID_ARG, "share prefix >= 2^k");
+    if (sw) expect_status(sfft_apply_subtree(p, 1, 0, x, y2, nrhs, w, sw - 1, st), SFFT_INVALID_ARG, "share short ws");
+    expect_status(sfft_apply_subtree(p, 1, 0, x, y2, nrhs, w, sw, st), SFFT_OK, "share 0");
+    HIPC(hipStreamSynchronize(st));
+    std::vector<char> s0 = download(y2, vb);
+    expect_status(sfft_apply_subtree(p, 1, 1, x, y2, nrhs, w, sw, st), SFFT_OK, "share 1");
+    HIPC(hipStreamSynchronize(st));
+    std::vector<char> s1 = download(y2, vb);
+    auto* a0 = reinterpret_cast<std::complex<float>*>(s0.data());
+    const auto* a1 = reinterpret_cast<const std::complex<float>*>(s1.data());
+    for (size_t i = 0; i < vb / sizeof(std::complex<float>); ++i) a0[i] += a1[i];
+    expect(s0 == ref, "shares sum to the product");
+    if (w) HIPC(hipFree(w));
+  }
 
   // out-of-core form (host vectors)
   {

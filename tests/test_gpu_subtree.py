@@ -1,0 +1,145 @@
+"""GPU: one device's share of a product split over 2^k devices by branch
+(sfft_apply_subtree). After the splits of levels 1..k the 2^k branches are
+independent (Section II's opening remarks: by linearity a branch may run on to
+a chosen termination point instead of merging), so the 2^k shares of one x
+must sum to T x. Checked against the FP64 oracle (complex128 <= 1e-12,
+complex64 <= 1e-5 relative L2), and for k = 1 against the whole depth-first
+product bit for bit (the two level-1 merges then add the same two rounded
+terms)."""
+
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"c128": 1e-12, "c64": 1e-5}
+NP = {"c128": np.complex128, "c64": np.complex64}
+
+
+@pytest.fixture(scope="module")
+def sf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2406_17981_amd as sf
+    return sf
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def _shares(plan, xd, k):
+    """All 2^k shares of T x, each with a workspace of exactly the reported size."""
+    nrhs = xd.shape[0]
+    out = []
+    for prefix in range(1 << k):
+        nb = plan.workspace_size_subtree(k, nrhs)
+        ws = torch.empty(nb, dtype=torch.uint8, device="cuda") if nb else None
+        out.append(plan.apply_subtree(k, prefix, xd, workspace=ws))
+    torch.cuda.synchronize()
+    return out
+
+
+CASES = [
+    # (grid, b, coefficient kind, mirrored); grids with ragged pass tiles,
+    # runtime-length levels (7, 9, 14, 15) and d = 2..4
+    ((10, 12), 3, "green", False),
+    ((6, 10, 12), 1, "iid", False),
+    ((8, 6, 10), 3, "green", True),
+    ((14, 9), 3, "green", False),
+    ((7, 15, 4), 1, "iid", False),
+    ((4, 3, 2, 5), 3, "iid", False),
+    ((16, 16, 16), 3, "green", True),
+]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("grid,b,kind,mirrored", CASES)
+def test_shares_sum_to_the_product(sf, grid, b, kind, mirrored, dtype):
+    d = len(grid)
+    coeffs = wl.green_coeffs(grid, 0.9) if kind == "green" else wl.iid_coeffs(31, grid, b)
+    parity = wl.green_parity(d) if mirrored else None
+    x = wl.vectors(32, grid, b, 2)
+    want = oracle.embed_matvec(coeffs, x)
+    plan = sf.Plan(grid, b, torch.from_numpy(coeffs).cuda(), dtype=dtype, max_nrhs=2, schedule="depth",
+                   parity=parity)
+    xd = torch.from_numpy(x.astype(NP[dtype])).cuda()
+    full = plan.apply(xd, workspace=plan.alloc_workspace(2))
+    torch.cuda.synchronize()
+    for k in range(d):
+        _say(f"grid={grid} b={b} kind={kind} mirrored={mirrored} dtype={dtype} k={k}")
+        shares = _shares(plan, xd, k)
+        total = shares[0].clone()
+        for sh in shares[1:]:
+            total += sh
+        err = wl.relative_l2(total.cpu().numpy().astype(np.complex128), want)
+        assert err <= TOL[dtype], (k, err)
+        if k <= 1:
+            assert torch.equal(total, full), k
+        # every share is a proper part: none is zero, none is the whole product
+        if k >= 1:
+            for sh in shares:
+                assert torch.linalg.vector_norm(sh) > 0
+    plan.close()
+
+
+def test_share_of_the_large_grid_sampled(sf):
+    """256x256x128, 3x3 Green k = 1.3, 8 right-hand sides, complex64: the four
+    k = 2 shares sum to the stored FP64 oracle values at the sampled points."""
+    import os
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", "large_256_rows.npz"))
+    n, nrhs = (256, 256, 128), 8
+    _say("large grid, k = 2 shares")
+    x = torch.from_numpy(wl.vectors(502, n, 3, nrhs).astype(np.complex64)).cuda()
+    cd = wl.green_coeffs_device(n, 1.3)
+    plan = sf.Plan(n, 3, cd, dtype="c64", max_nrhs=nrhs, schedule="depth")
+    del cd
+    idx = torch.from_numpy(np.ravel_multi_index(g["points"].T, n)).cuda()
+    total = None
+    ws = torch.empty(plan.workspace_size_subtree(2, nrhs), dtype=torch.uint8, device="cuda")
+    y = torch.empty_like(x)
+    for prefix in range(4):
+        plan.apply_subtree(2, prefix, x, y, workspace=ws)
+        part = y.reshape(nrhs, 3, -1)[:, :, idx].to(torch.complex128)
+        total = part if total is None else total + part
+    torch.cuda.synchronize()
+    err = wl.relative_l2(total.cpu().numpy(), g["green"])
+    assert err <= 1e-5, err
+    plan.close()
+
+
+def test_share_rejects_bad_arguments(sf):
+    grid, b = (6, 10, 12), 1
+    coeffs = wl.iid_coeffs(33, grid, b)
+    cd = torch.from_numpy(coeffs).cuda()
+    plan = sf.Plan(grid, b, cd, dtype="c64", max_nrhs=1)
+    x = torch.from_numpy(wl.vectors(34, grid, b, 1).astype(np.complex64)).cuda()
+    ws = torch.empty(plan.workspace_size_subtree(1, 1), dtype=torch.uint8, device="cuda")
+    _say("share argument checks")
+    with pytest.raises(sf.SfftError):
+        plan.apply_subtree(3, 0, x)  # k beyond d - 1
+    with pytest.raises(sf.SfftError):
+        plan.apply_subtree(-1, 0, x)
+    with pytest.raises(sf.SfftError):
+        plan.apply_subtree(1, 2, x, workspace=ws)  # prefix >= 2^k
+    with pytest.raises(sf.SfftError):
+        plan.apply_subtree(1, 0, x, workspace=ws[:-256])  # workspace too small
+    with pytest.raises(sf.SfftError):
+        plan.apply_subtree(1, 0, x, x, workspace=ws)  # y aliases x
+    assert plan.workspace_size_subtree(2, 1) == 0  # the leaf level: no workspace
+    assert plan.workspace_size_subtree(1, 3) == 3 * plan.workspace_size_subtree(1, 1)
+    # an empty batch touches nothing
+    empty = torch.empty((0, b) + grid, dtype=torch.complex64, device="cuda")
+    plan.apply_subtree(1, 1, empty, workspace=ws)
+    plan.close()
+    emb = sf.Plan(grid, b, cd, dtype="c64", method="embed", max_nrhs=1)
+    with pytest.raises(sf.SfftError):
+        emb.apply_subtree(1, 0, x, workspace=ws)
+    emb.close()
