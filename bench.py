@@ -989,7 +989,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU split of the branch tree is a design note, not a measured path.",
+              "one device's share of a branch-split product is timed on one GPU instead (device_shares).",
               file=sys.stderr)
         sys.exit(2)
 
