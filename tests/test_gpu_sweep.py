@@ -5,8 +5,10 @@ length-specialised and runtime-length kernels (odd and even, with prime
 factors 2, 3, 5, 7), the block size (1..4), general or mirrored symbol
 storage (a random even/odd pattern per component and level), the dtype, the
 number of right-hand sides and the schedule; it compares the product with
-the oracle's embedding (complex128 <= 1e-12, complex64 <= 1e-5 relative L2)
-and checks that the 2^k per-device shares for a random k sum to it."""
+the oracle's embedding (complex128 <= 1e-12, complex64 <= 1e-5 relative L2),
+checks that the 2^k per-device shares for a random k sum to it and the
+adjoint against the oracle's product with t^H(r) = t(-r)^H. Random sets of
+these problems then run as batches in every graph form."""
 
 import math
 import sys
@@ -86,4 +88,61 @@ def test_sweep_case(sf, i, monkeypatch):
     torch.cuda.synchronize()
     err = wl.relative_l2(total.cpu().numpy().astype(np.complex128), want)
     assert err <= TOL[c["dtype"]], ("shares", k, err)
+    # the adjoint from the same symbols: generator t^H(r) = t(-r)^H
+    plan.enable_adjoint()
+    yh = plan.apply(xd, workspace=plan.alloc_workspace(c["nrhs"]), adjoint=True)
+    torch.cuda.synchronize()
+    err = wl.relative_l2(yh.cpu().numpy().astype(np.complex128),
+                         oracle.embed_matvec(oracle.adjoint_coeffs(coeffs), x))
+    assert err <= TOL[c["dtype"]], ("adjoint", err)
     plan.close()
+
+
+NBATCH = 12
+
+
+@pytest.mark.parametrize("j", range(NBATCH))
+def test_sweep_batch(sf, j, monkeypatch):
+    """A random set of 2 to 6 of the sweep's problems in one sfft_apply_multi
+    call, in each graph form (the library's timed choice, per-problem chains,
+    grouped lanes), replayed three times: every output equals the problem's
+    own apply bit for bit."""
+    rng = np.random.default_rng(9000 + j)
+    picks = [int(v) for v in rng.choice(NCASE, size=int(rng.integers(2, 7)), replace=False)]
+    print(f"[case] batch sweep {j}: cases {picks}", flush=True)
+    monkeypatch.setenv("SFFT_SLAB_MB", "0.001")
+    plans, xs, singles = [], [], []
+    for i in picks:
+        c = _draw(i)
+        grid, b, d = c["grid"], c["b"], len(c["grid"])
+        par = None
+        if c["mirrored"]:
+            par = np.random.default_rng(c["seed"]).integers(1, 3, (b, b, d)).astype(np.int32)
+            coeffs = wl.parity_coeffs(c["seed"], grid, b, par)
+        else:
+            coeffs = wl.iid_coeffs(c["seed"], grid, b)
+        plan = sf.Plan(grid, b, torch.from_numpy(coeffs).cuda(), dtype=c["dtype"], max_nrhs=c["nrhs"],
+                       schedule=c["sched"], parity=par)
+        x = torch.from_numpy(wl.vectors(c["seed"] + 1, grid, b, c["nrhs"]).astype(NP[c["dtype"]])).cuda()
+        plans.append(plan)
+        xs.append(x)
+        singles.append(plan.apply(x, workspace=plan.alloc_workspace(c["nrhs"])))
+    torch.cuda.synchronize()
+    ws = torch.empty(max(sf.workspace_size_multi(plans, [x.shape[0] for x in xs]), 1), dtype=torch.uint8,
+                     device="cuda")
+    for form in ("auto", "chains", "grouped"):
+        if form == "auto":
+            monkeypatch.delenv("SFFT_BATCH_MODE", raising=False)
+        else:
+            monkeypatch.setenv("SFFT_BATCH_MODE", form)
+        ys = [torch.zeros_like(x) for x in xs]
+        for rep in range(3):
+            for y in ys:
+                y.zero_()
+            torch.cuda.synchronize()
+            sf.apply_multi(plans, xs, ys, workspace=ws)
+            torch.cuda.synchronize()
+            for i, (y, ysingle) in enumerate(zip(ys, singles)):
+                assert torch.equal(y, ysingle), (form, rep, picks[i])
+    for p in plans:
+        p.close()
