@@ -187,6 +187,11 @@ def pmc_summarize(fetch_dir, write_dir, out_path, probe_log):
     print(json.dumps(rec))
 
 
+PROF_ROWS = 40  # kernel rows in a statistics table (the rest summed in one row)
+VGPR_NOTE = ("VGPRs as rocprofv3 reports them, in units of two registers: the code objects' own counts "
+             "(`.amdhsa_next_free_vgpr`) are twice these, e.g. 136 for `k_leaf<float, 128, 3, 2, false, 1>`.")
+
+
 def prof_summarize(db_path, out_path, title, command):
     """Kernel statistics from a rocprofv3 results database (--kernel-trace):
     launches, mean / min / max duration per kernel and workgroup count, with
@@ -199,14 +204,19 @@ def prof_summarize(db_path, out_path, title, command):
         "order by sum(duration) desc").fetchall()
     total = sum(r[6] for r in rows)
     lines = [f"# {title}", "", "Command (repository root, one MI355X):", "```", command, "```", "",
+             VGPR_NOTE, "",
              "| kernel | workgroups | launches | mean (us) | min (us) | max (us) | share of kernel time | VGPRs | LDS (B) |",
              "|---|---:|---:|---:|---:|---:|---:|---:|---:|"]
-    for name, wg, cnt, avg, mn, mx, tot, vgpr, lds in rows:
+    for name, wg, cnt, avg, mn, mx, tot, vgpr, lds in rows[:PROF_ROWS]:
         short = name.replace("(sfft::PassArgs)", "").replace("void ", "")
         if len(short) > 90:
             short = short[:87] + "..."
         lines.append(f"| `{short}` | {wg} | {cnt} | {avg / 1e3:.1f} | {mn / 1e3:.1f} | {mx / 1e3:.1f} | "
                      f"{100.0 * tot / total:.1f}% | {vgpr} | {lds} |")
+    if len(rows) > PROF_ROWS:
+        rest = rows[PROF_ROWS:]
+        lines.append(f"| {len(rest)} further kernels | | {sum(r[2] for r in rest)} | | | | "
+                     f"{100.0 * sum(r[6] for r in rest) / total:.1f}% | | |")
     with open(out_path, "w") as f:
         f.write("\n".join(lines) + "\n")
     print(f"wrote {out_path}")
