@@ -189,7 +189,8 @@ def pmc_summarize(fetch_dir, write_dir, out_path, probe_log):
 
 PROF_ROWS = 40  # kernel rows in a statistics table (the rest summed in one row)
 VGPR_NOTE = ("VGPRs as rocprofv3 reports them, in units of two registers: the code objects' own counts "
-             "(`.amdhsa_next_free_vgpr`) are twice these, e.g. 136 for `k_leaf<float, 128, 3, 2, false, 1>`.")
+             "(`.amdhsa_next_free_vgpr`, rounded up to a multiple of 8) are twice these, e.g. 136 for "
+             "`k_leaf<float, 128, 3, 2, false, 1>`.")
 
 
 def prof_summarize(db_path, out_path, title, command):
