@@ -25,7 +25,7 @@ constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
 // Work per thread (measured on one MI355X; one two-pass step of a 3 x 128^3
 // complex64 chain with 30 basis vectors): 4 entries and one basis vector per
-// sweep keep the streaming kernels small (about 70 VGPRs) and took 1.44 ms,
+// sweep keep the streaming kernels small (54-60 VGPRs) and took 1.44 ms,
 // against 1.59 ms (2 vectors), 2.07 ms (4 vectors) and 3.31 ms (4 vectors of
 // 8 entries)
 constexpr int kPer = 4;                 // entries per thread of a chunk
