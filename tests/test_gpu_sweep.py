@@ -80,7 +80,7 @@ def test_sweep_case(sf, i, monkeypatch):
     assert err <= TOL[c["dtype"]], ("apply", err)
     # the per-device shares of a 2^k-way split by branch (k below the plan's
     # levels; levels of size 1 are not drawn)
-    k = min(c["k"], plan.info()["d"] - 1)
+    k = min(c["k"], sum(v > 1 for v in grid) - 1)
     total = None
     for prefix in range(1 << k):
         sh = plan.apply_subtree(k, prefix, xd)
