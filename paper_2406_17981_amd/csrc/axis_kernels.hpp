@@ -189,6 +189,18 @@ template <typename Real, int L> struct Geo {
   // product and merge (fewer VALU instructions, longer dependence chains);
   // shorter leaves, bound by latency, keep independent products and adds
   static constexpr bool LFMA = L >= 128;
+  // LDS swizzle of the leaf's lockstep rows (fft_engine.hpp, lswz): the
+  // complex64 length-128 leaf (32 lanes x 4 entries) had about 40% of its
+  // LDS-active cycles in bank conflicts on the radix-4 exchanges; the
+  // swizzle takes the leaf from about 1110 to 1010 us at 256x256x128
+  // (general and mirrored symbols) without changing its occupancy. Other
+  // lengths keep plain rows (no gain measured at length 64)
+  static constexpr int LSWZ = (sizeof(Real) == 4 && L == 128 && LWS) ? 1 : 0;
+  // mirrored 3x3 block-symmetric leaves of that length need 194 VGPRs with
+  // the swizzle unless held to 3 wavefronts per SIMD (164, no spills)
+  template <int B, bool MIR, int BS> static constexpr int leaf_waves() {
+    return (MIR && B == 3 && BS != 0 && LSWZ) ? 3 : 1;
+  }
 };
 
 // Stored block components. BS = 0: all B*B components, index a*B + c.
@@ -735,8 +747,10 @@ __device__ __forceinline__ void leaf_body(const PassArgs& a, uint32_t bid) {
     }
   };
 
-  // all children x components transformed together (one LDS row each)
+  // all children x components transformed together (one LDS row each);
+  // the swizzled rows only up to 3x3 blocks (b = 4 mirrored leaves would spill)
   constexpr int NP = NPAR * B;
+  constexpr int SWZ = (G::LSWZ && B <= 3) ? 1 : 0;
   C h[NP][E];
   // split phases Phi[t + T m] = Phi[t] Phi[T m]: one per-lane value and E
   // lane-uniform table entries, so the merge needs no second per-lane fetch
@@ -760,7 +774,7 @@ __device__ __forceinline__ void leaf_body(const PassArgs& a, uint32_t bid) {
       for (int m = 0; m < E; ++m) h[c][m] = x[c][m];
   }
   if constexpr (NROW == NP) {
-    fft_pencils<-1, Sh, G::LWS, NP, G::LFMA>(h, lp, LP, 1, t, lt);
+    fft_pencils<-1, Sh, G::LWS, NP, G::LFMA, SWZ>(h, lp, LP, 1, t, lt);
   } else {
 #pragma unroll
     for (int c = 0; c < NP; ++c) fft_pencil<-1, Sh, G::LWS, G::LFMA>(h[c], lp, 1, t, lt);
@@ -768,7 +782,7 @@ __device__ __forceinline__ void leaf_body(const PassArgs& a, uint32_t bid) {
   block_product(*reinterpret_cast<C(*)[B][E]>(&h[0]), 0);
   if constexpr (NPAR == 2) block_product(*reinterpret_cast<C(*)[B][E]>(&h[B]), 1);
   if constexpr (NROW == NP) {
-    fft_pencils<+1, Sh, G::LWS, NP, G::LFMA>(h, lp, LP, 1, t, lt);
+    fft_pencils<+1, Sh, G::LWS, NP, G::LFMA, SWZ>(h, lp, LP, 1, t, lt);
   } else {
 #pragma unroll
     for (int c = 0; c < NP; ++c) fft_pencil<+1, Sh, G::LWS, G::LFMA>(h[c], lp, 1, t, lt);
@@ -797,12 +811,14 @@ __device__ __forceinline__ void leaf_body(const PassArgs& a, uint32_t bid) {
 }
 
 template <typename Real, int L, int B, int NPAR, bool MIR, int BS>
-__global__ void __launch_bounds__((Geo<Real, L>::RBMAX * Geo<Real, L>::SL)) k_leaf(PassArgs a) {
+__global__ void __launch_bounds__((Geo<Real, L>::RBMAX * Geo<Real, L>::SL))
+    __attribute__((amdgpu_waves_per_eu(Geo<Real, L>::template leaf_waves<B, MIR, BS>()))) k_leaf(PassArgs a) {
   leaf_body<Real, L, B, NPAR, MIR, BS>(a, blockIdx.x);
 }
 
 template <typename Real, int L, int B, int NPAR, bool MIR, int BS>
 __global__ void __launch_bounds__((Geo<Real, L>::RBMAX * Geo<Real, L>::SL))
+    __attribute__((amdgpu_waves_per_eu(Geo<Real, L>::template leaf_waves<B, MIR, BS>() == 3 && BS == 1 ? 3 : 1)))
     k_leaf_group(const PassArgs* __restrict__ tab, int nent) {
   const int e = find_entry(tab, nent, blockIdx.x);
   leaf_body<Real, L, B, NPAR, MIR, BS>(tab[e], blockIdx.x - tab[e].blk_begin);

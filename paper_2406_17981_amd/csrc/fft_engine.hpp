@@ -524,11 +524,23 @@ __device__ __forceinline__ void fft_pencil(C (&home)[Sh::E], C* lds, int kst, in
   fft_stage<C, Sh, DIR, 0, WS, FMA>(home, lds, kst, t, lt);
 }
 
+// LDS index of entry i of a pencil row under swizzle SWZ. 0: none. 1: bits
+// 4-5 of i XOR-ed into bits 0-1 and 2-3 (a permutation inside every block of
+// 16 entries, so rows of a multiple of 16 entries stay in place). For rows of
+// 32-lane pencils with 4 entries per lane (length 128 with radices 4, 4, 2,
+// 4) it moves the stride-4 writes of the first exchange (entries 4t + q) and
+// the blocked writes of the second ((t / 4) 16 + t % 4 + 4q) onto distinct
+// banks within each 16 lanes, while the unit-stride reads stay conflict free.
+template <int SWZ> __device__ __forceinline__ int lswz(int i) {
+  if constexpr (SWZ == 1) return i ^ (((i >> 4) & 3) * 5);
+  else return i;
+}
+
 // NP pencils of one lane advanced stage by stage together: pencil p's LDS row
 // is lds + p * pstride. Every exchange fences once for all NP pencils, and the
 // NP independent butterfly chains give the scheduler work to overlap with
 // LDS and memory latency.
-template <typename C, typename Sh, int DIR, int s, bool WS, int NP, bool FMA>
+template <typename C, typename Sh, int DIR, int s, bool WS, int NP, bool FMA, int SWZ>
 __device__ __forceinline__ void fft_stage_multi(C (&home)[NP][Sh::E], C* lds, int pstride, int kst, int t,
                                                 const LaneTw<C, Sh>& lt) {
   constexpr int L = Sh::L, T = Sh::T, S = Sh::S;
@@ -544,7 +556,7 @@ __device__ __forceinline__ void fft_stage_multi(C (&home)[NP][Sh::E], C* lds, in
 #pragma unroll
     for (int p = 0; p < NP; ++p)
 #pragma unroll
-      for (int m = 0; m < Sh::E; ++m) lds[p * pstride + (t + T * m) * kst] = home[p][m];
+      for (int m = 0; m < Sh::E; ++m) lds[p * pstride + lswz<SWZ>(t + T * m) * kst] = home[p][m];
     xsync<WS>();
   }
 
@@ -558,7 +570,7 @@ __device__ __forceinline__ void fft_stage_multi(C (&home)[NP][Sh::E], C* lds, in
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           if constexpr (FIRST_REG) v[p][u][r] = home[p][u + r * (NB / T)];
-          else v[p][u][r] = lds[p * pstride + (j + r * NB) * kst];
+          else v[p][u][r] = lds[p * pstride + lswz<SWZ>(j + r * NB) * kst];
         }
         if constexpr (FMA && s > 0 && (R == 2 || R == 4 || R == 8 || R == 16)) {
           C w[R - 1];
@@ -597,7 +609,7 @@ __device__ __forceinline__ void fft_stage_multi(C (&home)[NP][Sh::E], C* lds, in
           const int k = j % Ns;
           const int base = (j / Ns) * Ns * R + k;
 #pragma unroll
-          for (int q = 0; q < R; ++q) lds[p * pstride + (base + q * Ns) * kst] = v[p][u][q];
+          for (int q = 0; q < R; ++q) lds[p * pstride + lswz<SWZ>(base + q * Ns) * kst] = v[p][u][q];
         }
       }
     xsync<WS>();
@@ -605,20 +617,22 @@ __device__ __forceinline__ void fft_stage_multi(C (&home)[NP][Sh::E], C* lds, in
 #pragma unroll
       for (int p = 0; p < NP; ++p)
 #pragma unroll
-        for (int m = 0; m < Sh::E; ++m) home[p][m] = lds[p * pstride + (t + T * m) * kst];
+        for (int m = 0; m < Sh::E; ++m) home[p][m] = lds[p * pstride + lswz<SWZ>(t + T * m) * kst];
       xsync<WS>();
     }
   }
-  if constexpr (s + 1 < S) fft_stage_multi<C, Sh, DIR, s + 1, WS, NP, FMA>(home, lds, pstride, kst, t, lt);
+  if constexpr (s + 1 < S) fft_stage_multi<C, Sh, DIR, s + 1, WS, NP, FMA, SWZ>(home, lds, pstride, kst, t, lt);
 }
 
-// Unnormalised DFTs of NP pencils of the same lane (DIR = -1 forward, +1 inverse).
-template <int DIR, typename Sh, bool WS, int NP, bool FMA = false, typename C>
+// Unnormalised DFTs of NP pencils of the same lane (DIR = -1 forward, +1 inverse),
+// their LDS rows indexed through lswz<SWZ>.
+template <int DIR, typename Sh, bool WS, int NP, bool FMA = false, int SWZ = 0, typename C>
 __device__ __forceinline__ void fft_pencils(C (&home)[NP][Sh::E], C* lds, int pstride, int kst, int t,
                                             const LaneTw<C, Sh>& lt) {
   static_assert(shape_ok<Sh>(), "bad radix plan");
   static_assert(!WS || (64 % Sh::T) == 0, "wave sync needs whole pencils per wavefront");
-  fft_stage_multi<C, Sh, DIR, 0, WS, NP, FMA>(home, lds, pstride, kst, t, lt);
+  static_assert(SWZ == 0 || Sh::L % 16 == 0, "the swizzle permutes blocks of 16 entries");
+  fft_stage_multi<C, Sh, DIR, 0, WS, NP, FMA, SWZ>(home, lds, pstride, kst, t, lt);
 }
 
 }  // namespace sfft
