@@ -44,7 +44,7 @@ typedef enum {
   SFFT_OK = 0,
   SFFT_INVALID_ARG = 1,   /* null pointer, d < 1, n_l < 1, b not in {1..4}, bad enum, x aliases y,
                              short workspace, declared parity not held by the coefficients */
-  SFFT_UNSUPPORTED = 2,   /* level size with a prime factor outside {2, 3, 5, 7}, d > 6 */
+  SFFT_UNSUPPORTED = 2,   /* level size with a prime factor outside {2, 3, 5, 7}, more than 6 levels */
   SFFT_OUT_OF_MEMORY = 3, /* device allocation failed */
   SFFT_HIP_ERROR = 4      /* a HIP runtime call or kernel launch failed */
 } sfft_status;
@@ -108,9 +108,19 @@ typedef struct {
  *
  *   out       host: receives the plan handle (NULL on failure).
  *   d         levels, 1 <= d <= 6.
- *   n         host: d level sizes; each must have built kernels (as must 2 n_l).
- *             A level of size 1 (offset 0 only) is dropped internally; at least
- *             one level must be larger (else SFFT_UNSUPPORTED).
+ *   n         host: d level sizes with no prime factor above 7. A level of
+ *             size 1 (offset 0 only) is dropped internally; at least one level
+ *             must be larger (else SFFT_UNSUPPORTED). A level above 2048 is
+ *             carried as two or more plan levels of at most 2048 each (the
+ *             multilevel structure of the introduction: a Toeplitz level of
+ *             size f_1 f_2 is a two-level Toeplitz operator with generator
+ *             t(r_1 f_2 + r_2)); the coefficients are gathered into that
+ *             generator on the device (scratch of b*b*prod(2f_q - 1) complex128
+ *             entries during the call), the vectors keep their layout, and
+ *             sfft_apply_subtree's k and the schedules count plan levels.
+ *             SFFT_UNSUPPORTED if the plan levels number more than 6, or with
+ *             a parity mask on a split plan (mirrored storage needs level
+ *             sizes up to 2048).
  *   b         block size, 1 <= b <= 4.
  *   coeffs    device, complex128 (b, b, 2n_1-1, ..., 2n_d-1); read during the
  *             call only (the stream is synchronised before return, the caller

@@ -14,6 +14,28 @@
 
 constexpr int kMaxD = 6;
 
+// Longest level a pencil kernel takes; a longer level is carried as several
+// plan levels (below).
+constexpr int64_t kMaxLevel = 2048;
+
+// Gather of the caller's coefficients into the generator of the plan's levels
+// when a level of size n = f_1 ... f_m (C order, so index i = sum_k i_k w_k
+// with w_k = f_{k+1} ... f_m) is carried as m levels: entry (i - j) of a
+// Toeplitz level is t(sum_k (i_k - j_k) w_k), an m-level Toeplitz operator
+// whose generator at offsets (r_1, ..., r_m), |r_k| < f_k, is t(sum_k r_k w_k)
+// (|sum_k r_k w_k| < n, so every offset is in the caller's array). The
+// vectors keep their memory layout. Plan level q with offset index
+// i_q (offset i_q - f_q + 1) reads the caller's array at
+// cbase + sum_q i_q mult[q] within each block component.
+struct Regather {
+  int dq = 0;
+  int64_t ext[kMaxD] = {0};   // 2 f_q - 1 offsets per plan level
+  int64_t mult[kMaxD] = {0};  // caller-array stride per unit of i_q
+  int64_t cbase = 0;          // caller-array offset of i = 0 (within a component)
+  int64_t ncoef_in = 0;       // entries per block component: caller's array
+  int64_t ncoef_out = 0;      // and the plan's generator
+};
+
 // A plan: level sizes, block size, dtype, method, schedule, FP64-generated
 // symbols in the compute dtype and per-level twiddle tables (device memory
 // owned by the plan), plus an optional workspace pool and profiling events.
@@ -22,6 +44,12 @@ struct sfft_plan_s {
   int64_t n[kMaxD] = {0};
   int user_d = 0;               // the caller's levels (size-1 levels are dropped from d, n)
   int64_t user_n[kMaxD] = {0};
+  // levels longer than kMaxLevel split into several plan levels: the gather
+  // of the caller's coefficients (creation and update), and the first plan
+  // level of each caller level of size > 1
+  bool regather = false;
+  Regather rg;
+  int eff_first[kMaxD] = {0};
   int b = 1;
   int dtype = SFFT_C64;
   int method = SFFT_SPLIT;

@@ -116,6 +116,24 @@ __global__ void k_embed_generator(const double2* __restrict__ coeffs, double2* _
   }
 }
 
+// Generator of a plan whose long levels are carried as several levels: plan
+// entry (component ab, offset indices i_q) = caller entry
+// ab * ncoef_in + cbase + sum_q i_q mult[q] (Regather).
+__global__ void k_regather(const double2* __restrict__ src, double2* __restrict__ dst, Regather g,
+                           int64_t total) {
+  for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < total;
+       o += (int64_t)gridDim.x * blockDim.x) {
+    int64_t rem = o % g.ncoef_out;
+    int64_t at = (o / g.ncoef_out) * g.ncoef_in + g.cbase;
+    for (int q = g.dq - 1; q >= 0; --q) {
+      const int64_t i = rem % g.ext[q];
+      rem /= g.ext[q];
+      at += i * g.mult[q];
+    }
+    dst[o] = src[at];
+  }
+}
+
 // Parity de-interleave of one FP64 symbol component into the leaf layout of
 // the split plan: [Q][p][tile][k][m][lane] with Q the branch prefix over
 // levels 1..d-1 (level 1 most significant), p the last level's bit and k
@@ -914,6 +932,57 @@ void tmp_free(void* p, hipStream_t st) {
   if (pools_supported()) (void)hipFreeAsync(p, st);
   else (void)hipFree(p);
 }
+
+// The caller's coefficients gathered into the generator of the plan's levels
+// (Regather), in stream-ordered scratch the caller frees with tmp_free.
+sfft_status regather_coeffs(const Regather& g, int b, const void* coeffs, hipStream_t st, double2** out) {
+  *out = nullptr;
+  const int64_t total = (int64_t)b * b * g.ncoef_out;
+  void* dst = nullptr;
+  HIP_TRY(tmp_alloc(&dst, (size_t)total * sizeof(double2), st), "coefficient gather scratch allocation");
+  hipLaunchKernelGGL(k_regather, dim3(grid_for(total)), dim3(256), 0, st, (const double2*)coeffs, (double2*)dst,
+                     g, total);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    tmp_free(dst, st);
+    return hip_fail(e, "coefficient gather launch");
+  }
+  *out = (double2*)dst;
+  return SFFT_OK;
+}
+
+// Plan levels (outer to inner) that carry one caller level of size n: n
+// itself up to kMaxLevel; otherwise a factor pair, both at most kMaxLevel,
+// preferring factors with length-specialised kernels (for the compute dtype
+// and for the FP64 symbol generator's 2f points), then the most balanced
+// pair; beyond kMaxLevel^2 the largest factor up to kMaxLevel comes off
+// first. n has no prime factor above 7, so such factors exist.
+std::vector<int64_t> level_factors(int64_t n, int dtype, int method) {
+  auto special = [&](int64_t f) {
+    const AxisOps* o = find_ops(dtype, method == SFFT_SPLIT ? f : 2 * f);
+    const AxisOps* g = find_ops(SFFT_C128, 2 * f);
+    return (o && !o->generic ? 1 : 0) + (g && !g->generic ? 1 : 0);
+  };
+  std::vector<int64_t> f;
+  while (n > kMaxLevel) {
+    int64_t best = 0, best_score = -1;
+    for (int64_t a = 2; a <= kMaxLevel && a < n; ++a) {
+      if (n % a) continue;
+      const int64_t c = n / a;
+      const int64_t score = c <= kMaxLevel ? ((int64_t)1 << 40) + (int64_t)(special(a) + special(c)) * ((int64_t)1 << 32) +
+                                                 std::min(a, c)
+                                           : a;
+      if (score > best_score) {
+        best_score = score;
+        best = a;
+      }
+    }
+    f.push_back(best);
+    n /= best;
+  }
+  f.push_back(n);
+  return f;
+}
 sfft_status make_table(int dtype, int64_t L, void** out, size_t* bytes, hipStream_t st, bool transient = false) {
   const size_t esz = dtype == SFFT_C64 ? 8 : 16;
   const size_t nb = (size_t)(2 * L) * esz;
@@ -1462,8 +1531,58 @@ sfft_status sfft_plan_create(sfft_plan* out, int d, const int64_t* n, int b, con
     if (r != 1)
       return fail(SFFT_UNSUPPORTED, "level size " + std::to_string(n[l]) + " has the prime factor " +
                                         std::to_string(r) + " (only 2, 3, 5 and 7 are supported)");
-    if (n[l] > 2048)
-      return fail(SFFT_UNSUPPORTED, "level size " + std::to_string(n[l]) + " above 2048");
+  }
+  // levels longer than kMaxLevel: carried as several plan levels (Regather)
+  int64_t n_plan[kMaxD];
+  int eff_first[kMaxD] = {0};
+  Regather rg;
+  bool regather = false;
+  {
+    int dq = 0;
+    int64_t wq[kMaxD], cstride[kMaxD];
+    int grp[kMaxD];
+    for (int e = 0; e < d; ++e) {
+      const std::vector<int64_t> f = level_factors(n[e], dtype, method);
+      if (f.size() > 1) regather = true;
+      if (dq + (int)f.size() > kMaxD)
+        return fail(SFFT_UNSUPPORTED, "levels above " + std::to_string(kMaxLevel) +
+                                          " are carried as several levels; that makes more than 6");
+      eff_first[e] = dq;
+      int64_t w = 1;
+      for (int k = (int)f.size() - 1; k >= 0; --k) {
+        n_plan[dq + k] = f[k];
+        wq[dq + k] = w;
+        grp[dq + k] = e;
+        w *= f[k];
+      }
+      dq += (int)f.size();
+    }
+    if (regather) {
+      if (parity && method == SFFT_SPLIT)
+        return fail(SFFT_UNSUPPORTED, "mirrored storage needs every level size <= " + std::to_string(kMaxLevel));
+      int64_t st_in = 1;
+      for (int e = d - 1; e >= 0; --e) {
+        cstride[e] = st_in;
+        st_in *= 2 * n[e] - 1;
+      }
+      rg.dq = dq;
+      rg.ncoef_in = st_in;
+      rg.ncoef_out = 1;
+      rg.cbase = 0;
+      for (int e = 0; e < d; ++e) rg.cbase += (n[e] - 1) * cstride[e];
+      for (int q = 0; q < dq; ++q) {
+        rg.ext[q] = 2 * n_plan[q] - 1;
+        rg.mult[q] = wq[q] * cstride[grp[q]];
+        rg.cbase -= (n_plan[q] - 1) * rg.mult[q];
+        rg.ncoef_out *= rg.ext[q];
+      }
+      d = dq;
+      n = n_plan;
+    }
+  }
+  for (int l = 0; l < d; ++l) {
+    if (n[l] > kMaxLevel)
+      return fail(SFFT_UNSUPPORTED, "level size " + std::to_string(n[l]) + " above " + std::to_string(kMaxLevel));
     // the FP64 symbol generator transforms 2 n_l points along level l
     if (!find_ops(SFFT_C128, 2 * n[l]) || !generic_fits(find_ops(SFFT_C128, 2 * n[l]), SFFT_C128, b, 1, false, false))
       return fail(SFFT_UNSUPPORTED, "no kernels for length " + std::to_string(2 * n[l]));
@@ -1495,6 +1614,9 @@ sfft_status sfft_plan_create(sfft_plan* out, int d, const int64_t* n, int b, con
   p->d = d;
   p->user_d = user_d;
   for (int l = 0; l < user_d; ++l) p->user_n[l] = user_n[l];
+  p->regather = regather;
+  p->rg = rg;
+  for (int e = 0; e < kMaxD; ++e) p->eff_first[e] = eff_first[e];
   p->b = b;
   p->dtype = dtype;
   p->method = method;
@@ -1516,6 +1638,22 @@ sfft_status sfft_plan_create(sfft_plan* out, int d, const int64_t* n, int b, con
   for (int l = 0; l < d - 1; ++l) p->npen *= p->L[l];
   p->ntiles = (p->npen + lo->PL - 1) / lo->PL;
   const int npar = method == SFFT_SPLIT ? 2 : 1;
+  // the generator of the plan's levels (the caller's array unless a long
+  // level is carried as several); the gathered copy is freed in stream order
+  double2* gathered = nullptr;
+  if (regather) {
+    sfft_status sg = regather_coeffs(rg, b, coeffs, st, &gathered);
+    if (sg != SFFT_OK) {
+      delete p;
+      return sg;
+    }
+    coeffs = gathered;
+  }
+  struct GatherFree {
+    double2* g;
+    hipStream_t st;
+    ~GatherFree() { tmp_free(g, st); }
+  } gather_free{gathered, st};
   {
     int64_t ncoef = 1;
     for (int l = 0; l < d; ++l) ncoef *= 2 * n[l] - 1;
@@ -1570,6 +1708,17 @@ sfft_status sfft_plan_create(sfft_plan* out, int d, const int64_t* n, int b, con
 sfft_status sfft_plan_update(sfft_plan plan, const void* coeffs, void* stream) {
   if (!plan || !coeffs) return fail(SFFT_INVALID_ARG, "null argument");
   hipStream_t st = (hipStream_t)stream;
+  double2* gathered = nullptr;
+  if (plan->regather) {
+    sfft_status sg = regather_coeffs(plan->rg, plan->b, coeffs, st, &gathered);
+    if (sg != SFFT_OK) return sg;
+    coeffs = gathered;
+  }
+  struct GatherFree {
+    double2* g;
+    hipStream_t st;
+    ~GatherFree() { tmp_free(g, st); }
+  } gather_free{gathered, st};
   int64_t ncoef = 1;
   for (int l = 0; l < plan->d; ++l) ncoef *= 2 * plan->n[l] - 1;
   int bsym = 0;
@@ -1722,8 +1871,8 @@ sfft_status sfft_plan_info(sfft_plan plan, sfft_info* info) {
   info->workspace_bytes = workspace_elems(plan, plan->max_nrhs) * plan->esz;
   info->vector_elems = plan->b * plan->s;
   info->adjoint_symbol_bytes = plan->sym_adj ? plan->sym_bytes : 0;
-  for (int l = 0, k = 0; l < plan->user_d; ++l)  // levels of size 1 have no pass
-    if (plan->user_n[l] > 1) info->tile_mode[l] = plan->tile_mode[k++];
+  for (int l = 0, e = 0; l < plan->user_d; ++l)  // levels of size 1 have no pass
+    if (plan->user_n[l] > 1) info->tile_mode[l] = plan->tile_mode[plan->eff_first[e++]];
   info->mirror_row = plan->compressed ? plan->mrow : 0;
   return SFFT_OK;
 }

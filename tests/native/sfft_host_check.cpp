@@ -85,6 +85,9 @@ void host_only() {
   const int64_t n11[3] = {16, 11, 16};
   expect_status(sfft_plan_create(&h, 3, n11, 1, fake, SFFT_C64, SFFT_SPLIT, nullptr, 1, 0, nullptr),
                 SFFT_UNSUPPORTED, "prime 11");
+  const int64_t n7[6] = {4096, 2, 2, 2, 2, 2};  // the 4096 level needs two plan levels: 7 in all
+  expect_status(sfft_plan_create(&h, 6, n7, 1, fake, SFFT_C64, SFFT_SPLIT, nullptr, 1, 0, nullptr),
+                SFFT_UNSUPPORTED, "more than six plan levels");
   size_t bytes = 1;
   expect_status(sfft_workspace_size(nullptr, 1, &bytes), SFFT_INVALID_ARG, "null plan workspace");
   expect_status(sfft_apply(nullptr, fake, (void*)0x2000, 1, nullptr, 0, nullptr), SFFT_INVALID_ARG, "null plan apply");
@@ -179,6 +182,28 @@ void gpu_checks() {
     else expect(got == ref, "schedules agree");
     expect(download(y2, vb) == ref, "pool workspace agrees");
     if (w) HIPC(hipFree(w));
+  }
+  {  // a level above 2048, carried as two plan levels (gathered coefficients), create, update, apply
+    Problem lp = make_problem({3072}, 2, 9);
+    const size_t lvb = (size_t)(lp.b * lp.s) * 8;
+    void *lx, *ly;
+    HIPC(hipMalloc(&lx, lvb));
+    HIPC(hipMalloc(&ly, lvb));
+    HIPC(hipMemset(lx, 0, lvb));
+    sfft_plan lh = nullptr;
+    expect_status(sfft_plan_create(&lh, 1, lp.n.data(), lp.b, lp.coeffs, SFFT_C64, SFFT_SPLIT, nullptr, 1,
+                                   SFFT_SCHED_DEPTH, st),
+                  SFFT_OK, "long-level plan create");
+    expect_status(sfft_plan_update(lh, lp.coeffs, st), SFFT_OK, "long-level plan update");
+    expect_status(sfft_apply(lh, lx, ly, 1, nullptr, 0, st), SFFT_OK, "long-level apply");
+    sfft_info li;
+    expect_status(sfft_plan_info(lh, &li), SFFT_OK, "long-level info");
+    expect(li.d == 1 && li.n[0] == 3072, "long-level info reports the caller's level");
+    HIPC(hipStreamSynchronize(st));
+    expect_status(sfft_plan_destroy(lh), SFFT_OK, "long-level destroy");
+    HIPC(hipFree(lx));
+    HIPC(hipFree(ly));
+    HIPC(hipFree(lp.coeffs));
   }
   sfft_plan p = plans[0];
   sfft_info info;

@@ -1,0 +1,129 @@
+"""GPU parity of plans with levels above 2048 (carried as several plan levels
+of at most 2048 each, the caller's coefficients gathered into the multilevel
+generator t(sum_k r_k w_k) on the device) against the FP64 oracle's
+embedding of the caller's own one-level generator.
+
+Tolerances (relative L2 over all entries): complex128 <= 1e-12, complex64
+<= 1e-5, both against the FP64 oracle."""
+
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"c128": 1e-12, "c64": 1e-5}
+NP = {"c128": np.complex128, "c64": np.complex64}
+
+
+@pytest.fixture(scope="module")
+def sf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2406_17981_amd as sf
+    return sf
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def _apply(sf, coeffs, x, dtype, method="split", schedule="auto"):
+    n = oracle.grid_of(coeffs)
+    b = coeffs.shape[0]
+    _say(f"long levels n={n} b={b} {dtype} {method} {schedule} nrhs={x.shape[0]}")
+    plan = sf.Plan(n, b, torch.from_numpy(coeffs).cuda(), dtype=dtype, method=method,
+                   max_nrhs=x.shape[0], schedule=schedule)
+    info = plan.info()
+    assert info["d"] == len(n) and tuple(info["n"][:len(n)]) == n
+    y = plan.apply(torch.from_numpy(x.astype(NP[dtype])).cuda(), workspace=plan.alloc_workspace(x.shape[0]))
+    torch.cuda.synchronize()
+    plan.close()
+    return y.cpu().numpy().astype(np.complex128)
+
+
+CASES = [
+    # (grid, b, dtype, method, schedule)
+    ((4096,), 1, "c128", "split", "depth"),     # 64 x 64
+    ((4096,), 1, "c64", "split", "breadth"),
+    ((4096,), 2, "c128", "embed", "auto"),
+    ((5000,), 3, "c64", "split", "depth"),      # a runtime-length leaf
+    ((3072, 6), 2, "c128", "split", "depth"),   # first level split, three plan levels
+    ((3072, 6), 2, "c64", "split", "slab"),
+    ((6, 2187), 1, "c128", "split", "breadth"),  # last level split (3^7)
+    ((10, 2500), 1, "c64", "split", "depth"),
+]
+
+
+@pytest.mark.parametrize("grid, b, dtype, method, schedule", CASES)
+def test_long_levels_match_oracle(sf, grid, b, dtype, method, schedule):
+    coeffs = wl.iid_coeffs(611, grid, b)
+    x = wl.vectors(612, grid, b, 2)
+    got = _apply(sf, coeffs, x, dtype, method, schedule)
+    err = wl.relative_l2(got, oracle.embed_matvec(coeffs, x))
+    _say(f"rel_l2={err:.3e}")
+    assert err <= TOL[dtype], err
+
+
+def test_level_of_four_million_points_splits_twice(sf):
+    """n = 2^23: 2048 comes off first, the remaining 4096 splits again (three
+    plan levels), complex64 Green-like decaying coefficients."""
+    n = (1 << 23,)
+    r = np.arange(-(n[0] - 1), n[0])
+    rng = np.random.default_rng(613)
+    coeffs = ((rng.standard_normal(r.size) + 1j * rng.standard_normal(r.size)) / (1.0 + np.abs(r)))[None, None]
+    x = wl.vectors(614, n, 1, 1)
+    got = _apply(sf, coeffs, x, "c64", "split", "depth")
+    err = wl.relative_l2(got, oracle.embed_matvec(coeffs, x))
+    _say(f"rel_l2={err:.3e}")
+    assert err <= TOL["c64"], err
+
+
+def test_long_level_adjoint_update_and_shares(sf):
+    """The adjoint, a plan update and the per-device shares (k counts plan
+    levels: 3072 x 6 is three) on a plan whose first level is split."""
+    grid, b = (3072, 6), 2
+    c0 = wl.iid_coeffs(621, grid, b)
+    c1 = wl.iid_coeffs(622, grid, b)
+    x = wl.vectors(623, grid, b, 2)
+    plan = sf.Plan(grid, b, torch.from_numpy(c0).cuda(), dtype="c128", max_nrhs=2, schedule="depth")
+    xd = torch.from_numpy(x).cuda()
+    ws = plan.alloc_workspace(2)
+    plan.update(torch.from_numpy(c1).cuda())
+    plan.enable_adjoint()
+    y = plan.apply(xd, workspace=ws).cpu().numpy()
+    yh = plan.apply(xd, workspace=ws, adjoint=True).cpu().numpy()
+    want = oracle.embed_matvec(c1, x)
+    assert wl.relative_l2(y, want) <= TOL["c128"]
+    assert wl.relative_l2(yh, oracle.embed_matvec(oracle.adjoint_coeffs(c1), x)) <= TOL["c128"]
+    for k in (1, 2):
+        tot = sum(plan.apply_subtree(k, p, xd).cpu().numpy() for p in range(1 << k))
+        err = wl.relative_l2(tot, want)
+        _say(f"shares k={k} rel_l2={err:.3e}")
+        assert err <= TOL["c128"], (k, err)
+    plan.close()
+
+
+def test_long_level_refusals(sf):
+    """Mirrored storage needs levels up to 2048; more than six plan levels and
+    prime factors above 7 stay unsupported."""
+    par = np.full((1, 1, 1), 1, dtype=np.int32)  # even
+    n = (4096,)
+    r = np.arange(-(n[0] - 1), n[0])
+    even = (1.0 / (1.0 + np.abs(r)))[None, None].astype(np.complex128)
+    with pytest.raises(sf.SfftError, match="UNSUPPORTED"):
+        sf.Plan(n, 1, torch.from_numpy(even).cuda(), dtype="c64", parity=par)
+    # the same mask on the embedding baseline is not used: that plan builds
+    p = sf.Plan(n, 1, torch.from_numpy(even).cuda(), dtype="c64", method="embed", parity=par)
+    p.close()
+    grid = (4096, 2, 2, 2, 2, 2)
+    with pytest.raises(sf.SfftError, match="UNSUPPORTED"):
+        sf.Plan(grid, 1, torch.zeros(wl.coeff_shape(grid, 1), dtype=torch.complex128, device="cuda"))
+    with pytest.raises(sf.SfftError, match="UNSUPPORTED"):
+        sf.Plan((4099,), 1, torch.zeros((1, 1, 8197), dtype=torch.complex128, device="cuda"))

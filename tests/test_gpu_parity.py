@@ -720,9 +720,10 @@ def test_runtime_length_levels_mirrored(sf, grid, dtype):
 
 
 def test_unsupported_level_sizes(sf):
-    """Prime factors outside {2, 3, 5, 7} and sizes above 2048 are refused
-    before any device work, naming the size."""
-    for grid in ((11,), (8, 22), (4096,)):
+    """Prime factors outside {2, 3, 5, 7} are refused before any device work,
+    naming the size (levels above 2048 are carried as several plan levels:
+    tests/test_gpu_long_levels.py)."""
+    for grid in ((11,), (8, 22), (4099,)):
         coeffs = torch.zeros((1, 1) + tuple(2 * v - 1 for v in grid), dtype=torch.complex128, device="cuda")
         with pytest.raises(sf.SfftError, match="UNSUPPORTED"):
             sf.Plan(grid, 1, coeffs, dtype="c64")
