@@ -132,10 +132,15 @@ sfft_status layout(const sfft_plan_s* lo, const sfft_plan_s* hi, int m, Layout* 
 sfft_status check_pair(const sfft_plan_s* lo, const sfft_plan_s* hi, int m) {
   if (!lo || !hi) return sfft_rt_fail(SFFT_INVALID_ARG, "plans must be non-null");
   if (hi->dtype != SFFT_C128) return sfft_rt_fail(SFFT_INVALID_ARG, "the residual plan must be complex128");
-  if (lo->b != hi->b || lo->s != hi->s || lo->d != hi->d)
+  if (lo->b != hi->b || lo->s != hi->s)
     return sfft_rt_fail(SFFT_INVALID_ARG, "the two plans must describe the same grid and block size");
-  for (int l = 0; l < lo->d; ++l)
-    if (lo->n[l] != hi->n[l]) return sfft_rt_fail(SFFT_INVALID_ARG, "the two plans must have the same grid");
+  // the caller's levels of size > 1 (a plan may carry a long level as several)
+  std::vector<int64_t> glo, ghi;
+  for (int l = 0; l < lo->user_d; ++l)
+    if (lo->user_n[l] > 1) glo.push_back(lo->user_n[l]);
+  for (int l = 0; l < hi->user_d; ++l)
+    if (hi->user_n[l] > 1) ghi.push_back(hi->user_n[l]);
+  if (glo != ghi) return sfft_rt_fail(SFFT_INVALID_ARG, "the two plans must have the same grid");
   if (m < 1 || m > kGmresMaxM) return sfft_rt_fail(SFFT_INVALID_ARG, "m must be in 1..64");
   return SFFT_OK;
 }

@@ -89,3 +89,29 @@ def test_gmres_trivial_cases(sf):
         sf.gmres_solve(lo, hi, zero, rhs, workspace=torch.empty(16, dtype=torch.uint8, device="cuda"))
     for p in (hi, lo, other):
         p.close()
+
+
+def test_gmres_on_a_long_level(sf):
+    """A one-level 4096-point problem (carried as two plan levels in both
+    plans) with a decaying scalar kernel and chi = 0.1 on a window: the
+    complex64 / complex128 plan pair is accepted and the oracle's A x confirms
+    the residual."""
+    n, b = (4096,), 1
+    r = np.arange(-(n[0] - 1), n[0])
+    coeffs = (np.exp(0.9j * np.abs(r)) / (1.0 + np.abs(r)))[None, None].astype(np.complex128)
+    chi = np.zeros((b,) + n, dtype=np.complex128)
+    chi[:, 1000:3000] = 0.1
+    rhs = wl.vectors(505, n, b, 1)[0]
+    cd = torch.from_numpy(coeffs).cuda()
+    hi = sf.Plan(n, b, cd, dtype="c128")
+    lo = sf.Plan(n, b, cd, dtype="c64")
+    print(f"[case] gmres long level n={n}", flush=True)
+    x, info = sf.gmres_solve(lo, hi, torch.from_numpy(chi).cuda(), torch.from_numpy(rhs).cuda(), m=30,
+                             max_cycles=40, tol=1e-9)
+    torch.cuda.synchronize()
+    print(f"[case] gmres info {info}", flush=True)
+    assert info["converged"] and info["rel_residual"] <= 1e-9
+    res = _oracle_residual(coeffs, chi, rhs, x.cpu().numpy())
+    assert res <= 1.05e-9 + 1e-14, res
+    hi.close()
+    lo.close()
