@@ -300,7 +300,9 @@ def cpu_model() -> str:
 def cpu_baseline_large(coeffs, x_host, budget_s):
     """The FP64 oracle (circulant embedding, symbol transformed once before the
     timed loop) on one right-hand side of the 256x256x128 workload, with
-    scipy.fft using all host cores and then one core."""
+    scipy.fft using all host cores and then one core; then the oracle's split
+    product (the sum over parity branches) once with all cores."""
+    import numpy as np
     import oracle
     import oracle.toeplitz as OT
     cores = len(os.sched_getaffinity(0))
@@ -323,14 +325,24 @@ def cpu_baseline_large(coeffs, x_host, budget_s):
         wall = time.perf_counter() - t0
         runs[workers] = dict(matvecs_per_s=round(reps / wall, 5), reps=reps, wall_s=round(wall, 2))
         log(f"[cpu] workers={workers}: {reps} matvecs in {wall:.1f} s")
+    # the oracle's split product (sum over the 2^d parity branches) on the same
+    # right-hand side and symbol, all cores: the CPU side of split vs embed
+    OT.set_workers(cores)
+    t0 = time.perf_counter()
+    ys = oracle.split_branch_sum_with_symbol(C, x_host[:1])
+    t_split = time.perf_counter() - t0
+    split = dict(matvecs_per_s=round(1.0 / t_split, 5), reps=1, wall_s=round(t_split, 2),
+                 rel_l2_vs_embed=float(f"{float(np.linalg.norm(ys - ref) / np.linalg.norm(ref)):.3e}"))
+    log(f"[cpu] split branch sum, workers={cores}: 1 matvec in {t_split:.1f} s")
     OT.set_workers(None)
-    del C
+    del C, ys
     best = runs[cores]
     return ref, dict(value=best["matvecs_per_s"], unit="matvecs/s", cores=cores, kind="oracle",
                      sample=f"{best['reps']} FP64 matvecs (1 right-hand side each) of the same 256x256x128 "
                             f"b=3 Green workload through oracle.embed_matvec_with_symbol, symbol transformed "
                             f"once beforehand ({t_sym:.1f} s, not timed); scipy.fft workers={cores}",
-                     cpu_model=cpu_model(), per_workers={str(k): v for k, v in runs.items()})
+                     cpu_model=cpu_model(), per_workers={str(k): v for k, v in runs.items()},
+                     split_branch_sum=split)
 
 
 def pmc_counters_table(pmc_dir, out_path, title, command):
@@ -492,7 +504,7 @@ def bench_large(args):
 
     cpu = None
     if not args.no_cpu_baseline:
-        log(f"CPU oracle baseline (~{args.cpu_seconds:.0f} s with all cores, then one rep on one core)")
+        log(f"CPU oracle baseline (~{args.cpu_seconds:.0f} s with all cores, then one rep on one core, then one split rep)")
         ref, cpu = cpu_baseline_large(coeffs, x_host, args.cpu_seconds)
         rel["green_split_depth_full_rhs0_vs_cpu_oracle"] = float(
             f"{wl.relative_l2(y_c64[:1].cpu().numpy().astype(np.complex128), ref):.3e}")
