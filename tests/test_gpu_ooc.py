@@ -79,3 +79,32 @@ def test_out_of_core_refusals(sf):
         one.ooc_sizes(1, 1 << 20)
     for p in (plan, emb, one):
         p.close()
+
+
+@pytest.mark.parametrize("grid,b", [((4096,), 1), ((3072, 6), 2)])
+def test_out_of_core_with_a_long_level(sf, grid, b):
+    """A level above 2048 is carried as two plan levels, so even a one-level
+    grid has the level-1 split the out-of-core product works on."""
+    coeffs = wl.iid_coeffs(114, grid, b)
+    x = wl.vectors(115, grid, b, 2)
+    print(f"[case] ooc long level n={grid} b={b}", flush=True)
+    plan = sf.Plan(grid, b, torch.from_numpy(coeffs).cuda(), dtype="c128", max_nrhs=2, schedule="depth")
+    xd = torch.from_numpy(x).cuda()
+    y_in = plan.apply(xd, workspace=plan.alloc_workspace(2)).cpu()
+    xh = torch.from_numpy(x).pin_memory()
+    vb = xd.numel() * xd.element_size()
+    ran = 0
+    for budget in (vb // 2, vb, 4 * vb):
+        try:
+            _, used = plan.ooc_sizes(2, budget)
+        except sf.SfftError as e:
+            assert "budget too small" in str(e) and budget < 4 * vb
+            continue
+        assert used <= budget
+        ran += 1
+        y = plan.apply_ooc(xh, device_budget=budget)
+        torch.cuda.synchronize()
+        assert torch.equal(y, y_in), budget
+    assert ran >= 1
+    assert wl.relative_l2(y_in.numpy(), oracle.embed_matvec(coeffs, x)) <= TOL["c128"]
+    plan.close()
