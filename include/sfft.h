@@ -97,6 +97,15 @@ typedef struct {
                               n_d + E/2 where the leaf reads lane pairs, E its entries per lane);
                               symbol_bytes = components x prod_{l<d}(n_l + 1) x mirror_row x dtype
                               size. 0 without mirrored storage */
+  int plan_d;              /* levels the plan runs: d without its levels of size 1, a level above
+                              2048 counted as the two or more levels that carry it */
+  int64_t plan_n[8];       /* their sizes, outermost first */
+  int64_t pencil_len[8];   /* per plan level, the transform length (n_l split, 2 n_l embedding) */
+  int radix[8][8];         /* per plan level, the radices of its pass kernels, outermost stage
+                              first, 0-terminated */
+  int leaf_radix[8];       /* the radices of the leaf kernel (innermost plan level), 0-terminated */
+  size_t peak_bytes;       /* device bytes of one apply at max_nrhs, as modelled: symbols (and
+                              adjoint symbols when enabled), twiddle tables, workspace, x and y */
 } sfft_info;
 
 /* Build a plan and its Fourier-space symbols.

@@ -41,6 +41,8 @@ class SfftInfo(C.Structure):
         ("max_nrhs", C.c_int64), ("symbol_bytes", C.c_size_t), ("table_bytes", C.c_size_t),
         ("workspace_bytes", C.c_size_t), ("vector_elems", C.c_int64), ("block_symmetry", C.c_int),
         ("adjoint_symbol_bytes", C.c_size_t), ("tile_mode", C.c_int * 8), ("mirror_row", C.c_int64),
+        ("plan_d", C.c_int), ("plan_n", C.c_int64 * 8), ("pencil_len", C.c_int64 * 8),
+        ("radix", (C.c_int * 8) * 8), ("leaf_radix", C.c_int * 8), ("peak_bytes", C.c_size_t),
     ]
 
 

@@ -430,3 +430,14 @@ extern "C" const sfft::AxisOps* sfft_ops_generic(int dtype, int64_t L) {
   cache.emplace(key, std::move(ops));
   return p;
 }
+
+// Radices of the runtime-length kernels for pencil length L (passes and leaf
+// alike), outermost stage first; returns how many (at most 8), 0 when L has
+// no such kernels.
+extern "C" int sfft_radix_generic(int64_t L, int* rads) {
+  sfft::GenPlan g;
+  if (!sfft::factor(L, &g)) return 0;
+  int n = 0;
+  for (int i = 0; i < g.nst && n < 8; ++i) rads[n++] = g.rad[i];
+  return n;
+}

@@ -31,6 +31,10 @@ using sfft::PassArgs;
 #include "lengths.def"
 #undef SFFT_X
 extern "C" const AxisOps* sfft_ops_generic(int dtype, int64_t L);
+#define SFFT_X(L) extern "C" int sfft_radix_##L(int, int, int*);
+#include "lengths.def"
+#undef SFFT_X
+extern "C" int sfft_radix_generic(int64_t L, int* rads);
 
 namespace {
 
@@ -43,6 +47,20 @@ const AxisOps* find_ops(int dtype, int64_t L) {
 #undef SFFT_X
     default:
       return sfft_ops_generic(dtype, L);  // runtime-length kernels, or null
+  }
+}
+
+// Radices of the kernels for pencil length L (passes, or the leaf), outermost
+// stage first, into rads[0..7]; returns how many.
+int find_radix(int dtype, int64_t L, bool leaf, int* rads) {
+  switch (L) {
+#define SFFT_X(LL) \
+  case LL:         \
+    return sfft_radix_##LL(dtype, leaf ? 1 : 0, rads);
+#include "lengths.def"
+#undef SFFT_X
+    default:
+      return sfft_radix_generic(L, rads);
   }
 }
 
@@ -1874,6 +1892,15 @@ sfft_status sfft_plan_info(sfft_plan plan, sfft_info* info) {
   for (int l = 0, e = 0; l < plan->user_d; ++l)  // levels of size 1 have no pass
     if (plan->user_n[l] > 1) info->tile_mode[l] = plan->tile_mode[plan->eff_first[e++]];
   info->mirror_row = plan->compressed ? plan->mrow : 0;
+  info->plan_d = plan->d;
+  for (int l = 0; l < plan->d; ++l) {
+    info->plan_n[l] = plan->n[l];
+    info->pencil_len[l] = plan->L[l];
+    find_radix(plan->dtype, plan->L[l], false, info->radix[l]);
+  }
+  find_radix(plan->dtype, plan->L[plan->d - 1], true, info->leaf_radix);
+  info->peak_bytes = plan->sym_bytes + info->adjoint_symbol_bytes + plan->table_bytes + info->workspace_bytes +
+                     2 * (size_t)(plan->max_nrhs * plan->b * plan->s) * plan->esz;
   return SFFT_OK;
 }
 

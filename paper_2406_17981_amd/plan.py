@@ -90,7 +90,10 @@ class Plan:
                     symbol_bytes=inf.symbol_bytes, table_bytes=inf.table_bytes,
                     workspace_bytes=inf.workspace_bytes, vector_elems=inf.vector_elems,
                     block_symmetry=inf.block_symmetry, adjoint_symbol_bytes=inf.adjoint_symbol_bytes,
-                    tile_mode=tuple(inf.tile_mode[:inf.d]), mirror_row=inf.mirror_row)
+                    tile_mode=tuple(inf.tile_mode[:inf.d]), mirror_row=inf.mirror_row,
+                    plan_n=tuple(inf.plan_n[:inf.plan_d]), pencil_len=tuple(inf.pencil_len[:inf.plan_d]),
+                    radix=tuple(tuple(r for r in inf.radix[l] if r) for l in range(inf.plan_d)),
+                    leaf_radix=tuple(r for r in inf.leaf_radix if r), peak_bytes=inf.peak_bytes)
 
     def workspace_size(self, nrhs: int) -> int:
         out = C.c_size_t()

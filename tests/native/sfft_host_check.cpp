@@ -199,6 +199,10 @@ void gpu_checks() {
     sfft_info li;
     expect_status(sfft_plan_info(lh, &li), SFFT_OK, "long-level info");
     expect(li.d == 1 && li.n[0] == 3072, "long-level info reports the caller's level");
+    expect(li.plan_d == 2 && li.plan_n[0] * li.plan_n[1] == 3072, "long level carried as two plan levels");
+    int64_t rp = 1;
+    for (int i = 0; i < 8 && li.leaf_radix[i]; ++i) rp *= li.leaf_radix[i];
+    expect(rp == li.pencil_len[1], "leaf radices multiply to the leaf length");
     HIPC(hipStreamSynchronize(st));
     expect_status(sfft_plan_destroy(lh), SFFT_OK, "long-level destroy");
     HIPC(hipFree(lx));

@@ -105,3 +105,25 @@ def test_arnoldi_scratch_and_validation_without_a_device():
     assert N.lib.sfft_arnoldi_step_multi(2, jobs, N.C64, fake, need, None) == N.INVALID_ARG
     assert b"Arnoldi job" in N.lib.sfft_last_error()
     assert N.lib.sfft_arnoldi_step_multi(0, None, N.C64, None, 0, None) == N.OK               # empty step
+
+
+def test_info_struct_layout_matches_the_header(tmp_path):
+    """The ctypes mirror of sfft_info has the C struct's size and field offsets
+    (compiled from include/sfft.h with the host C compiler)."""
+    import shutil
+    import subprocess
+    from paper_2406_17981_amd import _native as N
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    fields = [f for f, _ in N.SfftInfo._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text("#include <stddef.h>\n#include <stdio.h>\n#include \"sfft.h\"\nint main(void) {\n"
+                   + "  printf(\"%zu\\n\", sizeof(sfft_info));\n"
+                   + "".join(f"  printf(\"%zu\\n\", offsetof(sfft_info, {f}));\n" for f in fields)
+                   + "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", f"-I{os.path.join(ROOT, 'include')}", str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    assert got[0] == ctypes.sizeof(N.SfftInfo)
+    assert got[1:] == [getattr(N.SfftInfo, f).offset for f in fields]

@@ -42,6 +42,15 @@ def _apply(sf, coeffs, x, dtype, method="split", schedule="auto"):
                    max_nrhs=x.shape[0], schedule=schedule)
     info = plan.info()
     assert info["d"] == len(n) and tuple(info["n"][:len(n)]) == n
+    assert int(np.prod(info["plan_n"])) == int(np.prod(n)) and max(info["plan_n"]) <= 2048
+    assert len(info["plan_n"]) > len(n)
+    scale = 1 if method == "split" else 2
+    assert info["pencil_len"] == tuple(scale * v for v in info["plan_n"])
+    for rads, length in zip(info["radix"], info["pencil_len"]):
+        assert int(np.prod(rads)) == length, (rads, length)
+    assert int(np.prod(info["leaf_radix"])) == info["pencil_len"][-1]
+    vb = x.shape[0] * b * int(np.prod(n)) * (8 if dtype == "c64" else 16)
+    assert info["peak_bytes"] == info["symbol_bytes"] + info["table_bytes"] + info["workspace_bytes"] + 2 * vb
     y = plan.apply(torch.from_numpy(x.astype(NP[dtype])).cuda(), workspace=plan.alloc_workspace(x.shape[0]))
     torch.cuda.synchronize()
     plan.close()
