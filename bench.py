@@ -16,7 +16,7 @@ circulant embedding on the same GPU with measured device memory, and the FP64
 CPU oracle timed on the host cores.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
-    python bench.py --workload green64|batch|serve   (the other configurations)
+    python bench.py --workload green64|batch|serve|gmres   (the other configurations)
 """
 
 from __future__ import annotations
@@ -620,6 +620,61 @@ def bench_batch(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_gmres(args):
+    """Krylov solve: (I - diag(chi) T) x = b by restarted GMRES(40) to a
+    relative residual of 1e-8, on a 96^3 grid with 3x3 Green blocks (k = 0.7),
+    chi = 0.05 (1 + 0.5i) on a ball of radius 12 cells (about 7,200 points);
+    Krylov steps with complex64 products (mirrored symbols), true residuals and
+    the refinement in FP64 with a complex128 plan. Time to solution (plans
+    built beforehand), products per second, and the FP64 oracle's residual of
+    the returned x on the host."""
+    import numpy as np
+    import torch
+    import oracle
+    import workloads as wl
+    import paper_2406_17981_amd as sf
+    if not torch.cuda.is_available():
+        log("no GPU visible")
+        sys.exit(1)
+    n, b, tol, m = (96, 96, 96), 3, 1e-8, 40
+    coeffs = wl.green_coeffs(n, 0.7)
+    idx = np.indices(n)
+    r2 = sum((idx[l] - n[l] / 2) ** 2 for l in range(3))
+    chi = np.zeros((b,) + n, dtype=np.complex128)
+    chi[:, r2 <= 12 * 12] = 0.05 * (1 + 0.5j)
+    rhs = wl.vectors(506, n, b, 1)[0]
+    cd = torch.from_numpy(coeffs).cuda()
+    hi = sf.Plan(n, b, cd, dtype="c128", schedule="depth")
+    lo = sf.Plan(n, b, cd, dtype="c64", parity=wl.green_parity(3), schedule="depth")
+    chi_d, rhs_d = torch.from_numpy(chi).cuda(), torch.from_numpy(rhs).cuda()
+    ws = torch.empty(sf.gmres_workspace_size(lo, hi, m), dtype=torch.uint8, device="cuda")
+    sf.gmres_solve(lo, hi, chi_d, rhs_d, m=m, max_cycles=1, tol=1e-1, workspace=ws)  # warm-up
+    torch.cuda.synchronize()
+    runs = []
+    for _ in range(max(1, min(args.steps, 5))):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, info = sf.gmres_solve(lo, hi, chi_d, rhs_d, m=m, max_cycles=60, tol=tol, workspace=ws)
+        torch.cuda.synchronize()
+        runs.append((time.perf_counter() - t0, info))
+        log(f"[gmres] {runs[-1][0] * 1e3:.1f} ms, {info}")
+    wall, info = min(runs, key=lambda r: r[0])
+    xh = x.cpu().numpy()
+    ax = xh - chi * oracle.embed_matvec(coeffs, xh[None])[0]
+    res = float(np.linalg.norm((rhs - ax).ravel()) / np.linalg.norm(rhs.ravel()))
+    log(f"[gmres] oracle residual {res:.3e}")
+    prods = info["matvecs"] + info["fp64_matvecs"]
+    line = {"workload": "gmres-green-96^3-b3-k0.7-chi-ball12", "m": m, "tol": tol,
+            "ms_to_solution": round(wall * 1e3, 3), "runs_ms": [round(r[0] * 1e3, 3) for r in runs],
+            "cycles": info["cycles"], "c64_matvecs": info["matvecs"], "fp64_matvecs": info["fp64_matvecs"],
+            "matvecs_per_s": round(prods / wall, 1), "converged": info["converged"],
+            "rel_residual": info["rel_residual"], "oracle_rel_residual": float(f"{res:.3e}"),
+            "chi_points": int((chi[0] != 0).sum())}
+    lo.close()
+    hi.close()
+    print(json.dumps(line), flush=True)
+
+
 def bench_serve(args):
     """Serving: Poisson arrivals (mean 200 req/s, seed 401), half d=2 grids
     {128..1024}^2 and half d=3 {32..128}^3, 3x3 Green kernels with k ~ U[0.5,1.5],
@@ -980,10 +1035,11 @@ def main():
     ap.add_argument("--single-requests", type=int, default=None,
                     help="serve: requests for the FP64 path (default: the same stream)")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serve: HBM budget")
-    ap.add_argument("--workload", default="large", choices=["large", "green64", "batch", "serve"],
+    ap.add_argument("--workload", default="large", choices=["large", "green64", "batch", "serve", "gmres"],
                     help="large (default, the headline): 256x256x128, b=3, 8 RHS, split vs embed; "
                          "green64: the 64^3 one-RHS configuration; "
-                         "batch: 8 uneven-grid problems, 64 RHS, one graph; serve: the Poisson stream")
+                         "batch: 8 uneven-grid problems, 64 RHS, one graph; serve: the Poisson stream; "
+                         "gmres: restarted GMRES on I - chi T, 96^3 Green blocks")
     ap.add_argument("--pmc-summarize", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON", "PROBE_LOG"),
                     help="PROBE_LOG: stderr of one of the --pmc-probe runs (names the kernel sources measured)")
     ap.add_argument("--prof-summarize", nargs=4, metavar=("RESULTS_DB", "OUT_MD", "TITLE", "COMMAND"),
@@ -991,7 +1047,7 @@ def main():
     ap.add_argument("--pmc-table", nargs=4, metavar=("PMC_DIR", "OUT_MD", "TITLE", "COMMAND"),
                     help="write the leaf kernels' counters of a rocprofv3 --pmc run (CSV) as a table")
     args = ap.parse_args()
-    steps_default, warmup_default = {"large": (20, 5), "batch": (50, 5), "green64": (1000, 2000)}.get(
+    steps_default, warmup_default = {"large": (20, 5), "batch": (50, 5), "green64": (1000, 2000), "gmres": (3, 1)}.get(
         args.workload, (1, 0))
     if args.steps is None:
         args.steps = steps_default
@@ -1016,7 +1072,8 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    {"large": bench_large, "green64": bench_green64, "batch": bench_batch, "serve": bench_serve}[args.workload](args)
+    {"large": bench_large, "green64": bench_green64, "batch": bench_batch, "serve": bench_serve,
+     "gmres": bench_gmres}[args.workload](args)
 
 
 if __name__ == "__main__":
