@@ -22,6 +22,8 @@
 #include <string>
 #include <vector>
 
+#include <unistd.h>
+
 #include "../../include/sfft.h"
 
 namespace {
@@ -405,10 +407,14 @@ int main(int argc, char** argv) {
   const std::string mode = argc > 1 ? argv[1] : "host";
   host_only();
   if (mode == "gpu") gpu_checks();
-  if (g_fail) {
-    std::fprintf(stderr, "%d check(s) failed\n", g_fail);
-    return 1;
-  }
-  std::printf("host check ok (%s)\n", mode.c_str());
-  return 0;
+  if (g_fail) std::fprintf(stderr, "%d check(s) failed\n", g_fail);
+  else std::printf("host check ok (%s)\n", mode.c_str());
+  std::fflush(stdout);
+  std::fflush(stderr);
+  // End without the HIP and HSA runtimes' exit-time finalizers: under
+  // AddressSanitizer their frees can fail the sanitizer's device-allocator
+  // check once the runtime is marked unloaded (an abort inside __cxa_finalize
+  // after every check here has passed). Every stream has been synchronised
+  // and leak detection is off for this program, so nothing is skipped.
+  _exit(g_fail ? 1 : 0);
 }
