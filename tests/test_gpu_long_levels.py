@@ -136,3 +136,41 @@ def test_long_level_refusals(sf):
         sf.Plan(grid, 1, torch.zeros(wl.coeff_shape(grid, 1), dtype=torch.complex128, device="cuda"))
     with pytest.raises(sf.SfftError, match="UNSUPPORTED"):
         sf.Plan((4099,), 1, torch.zeros((1, 1, 8197), dtype=torch.complex128, device="cuda"))
+
+
+def _smooth_above(lo, hi):
+    out = []
+    for v in range(lo, hi + 1):
+        r = v
+        for f in (2, 3, 5, 7):
+            while r % f == 0:
+                r //= f
+        if r == 1:
+            out.append(v)
+    return out
+
+
+LONG = _smooth_above(2049, 20000)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_long_level_sweep(sf, seed):
+    """Seeded draws: one level of a 7-smooth size in 2049..20000, alone or next
+    to a short level (either side), b = 1..3, both dtypes, split (every
+    schedule) or embedding, 1-2 right-hand sides, against the oracle."""
+    rng = np.random.default_rng(7000 + seed)
+    long_n = int(rng.choice(LONG))
+    shape = int(rng.integers(0, 3))
+    short = int(rng.choice([2, 3, 5, 6, 8, 12]))
+    grid = {0: (long_n,), 1: (long_n, short), 2: (short, long_n)}[shape]
+    b = int(rng.integers(1, 4))
+    dtype = ["c128", "c64"][int(rng.integers(0, 2))]
+    method = "embed" if rng.random() < 0.2 else "split"
+    schedule = ["depth", "breadth", "slab", "auto"][int(rng.integers(0, 4))] if method == "split" else "auto"
+    nrhs = int(rng.integers(1, 3))
+    coeffs = wl.iid_coeffs(8000 + seed, grid, b)
+    x = wl.vectors(9000 + seed, grid, b, nrhs)
+    got = _apply(sf, coeffs, x, dtype, method, schedule)
+    err = wl.relative_l2(got, oracle.embed_matvec(coeffs, x))
+    _say(f"rel_l2={err:.3e}")
+    assert err <= TOL[dtype], (grid, b, dtype, method, schedule, err)
