@@ -25,9 +25,11 @@ constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
 // Work per thread (measured on one MI355X; one two-pass step of a 3 x 128^3
 // complex64 chain with 30 basis vectors): 4 entries and one basis vector per
-// sweep keep the streaming kernels small (54-60 VGPRs) and took 1.44 ms,
-// against 1.59 ms (2 vectors), 2.07 ms (4 vectors) and 3.31 ms (4 vectors of
-// 8 entries)
+// sweep keep the streaming kernels small and took 1.44 ms, against 1.59 ms
+// (2 vectors), 2.07 ms (4 vectors) and 3.31 ms (4 vectors of 8 entries).
+// Requesting the next vector's entries before the current one is reduced
+// (k_dots: 70 VGPRs) or applied (k_update: 54) took a 96^3 GMRES(40) solve
+// from 984 to 839 ms
 constexpr int kPer = 4;                 // entries per thread of a chunk
 constexpr int kChunk = kBlock * kPer;   // entries per partial-sum block
 constexpr int kGroup = 1;               // basis vectors per sweep over a chunk
@@ -116,14 +118,26 @@ __global__ void __launch_bounds__(kBlock) k_dots(JobTable t, int pass) {
     wv[s] = k < J.n ? w[k] : C{0, 0};
   }
   const int wave = threadIdx.x >> 6;
+  // the next sweep's basis entries are requested before this sweep's
+  // reduction and barriers, so they arrive meanwhile
+  C nx[kGroup][kPer];
+#pragma unroll
+  for (int g = 0; g < kGroup; ++g)
+#pragma unroll
+    for (int s = 0; s < kPer; ++s) {
+      const int64_t k = kb + (int64_t)s * kBlock;
+      nx[g][s] = (g < J.m && k < J.n) ? V[(int64_t)g * J.ldv + k] : C{0, 0};
+    }
   for (int64_t i0 = 0; i0 < J.m; i0 += kGroup) {
     C a[kGroup][kPer];
 #pragma unroll
     for (int g = 0; g < kGroup; ++g)
 #pragma unroll
       for (int s = 0; s < kPer; ++s) {
+        a[g][s] = nx[g][s];
         const int64_t k = kb + (int64_t)s * kBlock;
-        a[g][s] = (i0 + g < J.m && k < J.n) ? V[(i0 + g) * J.ldv + k] : C{0, 0};
+        const int64_t i1 = i0 + kGroup + g;
+        nx[g][s] = (i1 < J.m && k < J.n) ? V[i1 * J.ldv + k] : C{0, 0};
       }
 #pragma unroll
     for (int g = 0; g < kGroup; ++g) {
@@ -214,14 +228,25 @@ __global__ void __launch_bounds__(kBlock) k_update(JobTable t, int pass) {
     const int64_t k = kb + (int64_t)s * kBlock;
     acc[s] = k < J.n ? to_d(w[k]) : make_double2(0.0, 0.0);
   }
+  // the next sweep's basis entries are requested before this sweep's updates
+  C nx[kGroup][kPer];
+#pragma unroll
+  for (int g = 0; g < kGroup; ++g)
+#pragma unroll
+    for (int s = 0; s < kPer; ++s) {
+      const int64_t k = kb + (int64_t)s * kBlock;
+      nx[g][s] = (g < J.m && k < J.n) ? V[(int64_t)g * J.ldv + k] : C{0, 0};
+    }
   for (int64_t i0 = 0; i0 < J.m; i0 += kGroup) {
     C a[kGroup][kPer];
 #pragma unroll
     for (int g = 0; g < kGroup; ++g)
 #pragma unroll
       for (int s = 0; s < kPer; ++s) {
+        a[g][s] = nx[g][s];
         const int64_t k = kb + (int64_t)s * kBlock;
-        a[g][s] = (i0 + g < J.m && k < J.n) ? V[(i0 + g) * J.ldv + k] : C{0, 0};
+        const int64_t i1 = i0 + kGroup + g;
+        nx[g][s] = (i1 < J.m && k < J.n) ? V[i1 * J.ldv + k] : C{0, 0};
       }
 #pragma unroll
     for (int g = 0; g < kGroup; ++g) {
