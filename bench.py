@@ -624,7 +624,7 @@ def bench_gmres(args):
     """Krylov solve: (I - diag(chi) T) x = b by restarted GMRES(40) to a
     relative residual of 1e-8, on a 96^3 grid with 3x3 Green blocks (k = 0.7),
     chi = 0.05 (1 + 0.5i) on a ball of radius 12 cells (about 7,200 points);
-    Krylov steps with complex64 products (mirrored symbols), true residuals and
+    Krylov steps with complex64 products (mirrored symbols, autotuned schedule), true residuals and
     the refinement in FP64 with a complex128 plan. Time to solution (plans
     built beforehand), products per second, and the FP64 oracle's residual of
     the returned x on the host."""
@@ -645,7 +645,8 @@ def bench_gmres(args):
     rhs = wl.vectors(506, n, b, 1)[0]
     cd = torch.from_numpy(coeffs).cuda()
     hi = sf.Plan(n, b, cd, dtype="c128", schedule="depth")
-    lo = sf.Plan(n, b, cd, dtype="c64", parity=wl.green_parity(3), schedule="depth")
+    lo = sf.Plan(n, b, cd, dtype="c64", parity=wl.green_parity(3))
+    lo.autotune(nrhs=1, use_cache=False)  # schedule and pass widths of the Krylov product, by timing
     chi_d, rhs_d = torch.from_numpy(chi).cuda(), torch.from_numpy(rhs).cuda()
     ws = torch.empty(sf.gmres_workspace_size(lo, hi, m), dtype=torch.uint8, device="cuda")
     sf.gmres_solve(lo, hi, chi_d, rhs_d, m=m, max_cycles=1, tol=1e-1, workspace=ws)  # warm-up
@@ -669,7 +670,8 @@ def bench_gmres(args):
             "cycles": info["cycles"], "c64_matvecs": info["matvecs"], "fp64_matvecs": info["fp64_matvecs"],
             "matvecs_per_s": round(prods / wall, 1), "converged": info["converged"],
             "rel_residual": info["rel_residual"], "oracle_rel_residual": float(f"{res:.3e}"),
-            "chi_points": int((chi[0] != 0).sum())}
+            "chi_points": int((chi[0] != 0).sum()),
+            "c64_schedule": ["auto", "breadth", "depth", "slab"][lo.info()["schedule"]]}
     lo.close()
     hi.close()
     print(json.dumps(line), flush=True)
