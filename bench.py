@@ -694,7 +694,9 @@ def bench_serve(args):
     torch.cuda.synchronize()
     out = {}
     for name, mk, max_active, nreq in (
-            ("batched_c64", lambda: serve.GpuExecutor(coeff_fn, wl.green_parity, dtype="c64", mirrored=True), 256,
+            ("batched_c64", lambda: serve.GpuExecutor(coeff_fn, wl.green_parity, dtype="c64", mirrored=True,
+                                                       **({} if args.schedule == "auto" else
+                                                          {"schedule": args.schedule})), 256,
              len(reqs)),
             ("single_fp64", lambda: serve.SingleRequestExecutor(coeff_fn, None, dtype="c128", mirrored=False), 1,
              len(reqs) if args.single_requests is None else min(len(reqs), args.single_requests))):
